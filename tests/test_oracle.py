@@ -1,0 +1,334 @@
+"""Pins for the CPU oracle (no GPU needed).
+
+Each check ties the oracle to something other than itself: brute force over
+the box prod[0, n/g_i], closed forms, values the paper prints (Table 1),
+textbook values, published hash test vectors, and the paper's own algorithms
+(Alg 2.8, 2.9, 3.1, 3.2) run independently in pure Python.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import method
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def brute(n, g):
+    """Every a in the box prod[0, n/g_i] with sum a_i g_i = n, sorted ascending."""
+    rng = [range(n // gi + 1) for gi in g]
+    rows = [a for a in itertools.product(*rng) if sum(x * y for x, y in zip(a, g)) == n]
+    return sorted(rows)
+
+
+def tiny_cases(seed, count, dmax=5, gmax=11, nmax=45):
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        d = int(rng.integers(1, dmax + 1))
+        g = [int(x) for x in rng.integers(1, gmax + 1, size=d)]  # unsorted, repeats allowed
+        n = int(rng.integers(0, nmax + 1))
+        yield n, g
+
+
+def as_tuples(a):
+    return [tuple(int(x) for x in r) for r in a]
+
+
+# --------------------------------------------------------------------------
+# Set, order and count against brute force
+# --------------------------------------------------------------------------
+
+def test_enumerate_matches_brute_force():
+    for n, g in tiny_cases(1, 300):
+        assert as_tuples(oracle.enumerate_rows(n, g)) == brute(n, g), (n, g)
+
+
+def test_count_matches_brute_force():
+    for n, g in tiny_cases(2, 300):
+        assert oracle.count(n, g) == len(brute(n, g)), (n, g)
+
+
+def test_count_table_rows_match_brute_force():
+    for n, g in tiny_cases(3, 80, dmax=4, nmax=30):
+        t = oracle.count_table(n, g)
+        d = len(g)
+        assert t.shape == (d + 1, n + 1)
+        for j in range(d + 1):
+            for x in range(n + 1):
+                want = len(brute(x, g[j:])) if j < d else int(x == 0)
+                assert int(t[j, x]) == want, (n, g, j, x)
+
+
+def test_a1_range_is_a_slice_of_the_full_list():
+    for n, g in tiny_cases(4, 100, dmax=4):
+        full = as_tuples(oracle.enumerate_rows(n, g))
+        top = n // g[0] + 1
+        lo, hi = sorted(np.random.default_rng(n).integers(0, top + 2, size=2).tolist())
+        part = as_tuples(oracle.enumerate_rows(n, g, lo, hi))
+        assert part == [r for r in full if lo <= r[0] < hi]
+
+
+# --------------------------------------------------------------------------
+# Special cases and closed forms
+# --------------------------------------------------------------------------
+
+def test_zero_element_has_one_all_zero_row():
+    for g in ([5], [3, 7], [2, 2, 9], [10, 4, 6, 8]):
+        rows = oracle.enumerate_rows(0, g)
+        assert rows.shape == (1, len(g)) and not rows.any()
+        assert oracle.count(0, g) == 1
+
+
+def test_single_generator():
+    for g in range(1, 12):
+        for n in range(0, 60):
+            rows = as_tuples(oracle.enumerate_rows(n, [g]))
+            assert rows == ([(n // g,)] if n % g == 0 else [])
+
+
+def test_gcd_not_dividing_n_gives_empty_set():
+    assert oracle.count(101, [4, 6, 10]) == 0
+    assert oracle.enumerate_rows(101, [4, 6, 10]).shape == (0, 3)
+    assert oracle.count(35, [9, 12, 15]) == 0
+
+
+def test_frobenius_number_is_a_gap():
+    # For coprime a, b the largest element with no factorization is ab - a - b.
+    for a, b in [(3, 5), (7, 11), (13, 37), (72, 77)]:
+        if math.gcd(a, b) != 1:
+            continue
+        f = a * b - a - b
+        assert oracle.count(f, [a, b]) == 0
+        assert all(oracle.count(m, [a, b]) >= 1 for m in range(f + 1, f + a + b + 1))
+
+
+def popoviciu(n, a, b):
+    """Exact |Z(n; a, b)| for coprime a, b (Popoviciu's formula)."""
+    bi = pow(b, -1, a) if a > 1 else 0
+    ai = pow(a, -1, b) if b > 1 else 0
+    num = n - b * ((bi * n) % a) - a * ((ai * n) % b)
+    assert num % (a * b) == 0
+    return num // (a * b) + 1
+
+
+def test_two_generators_closed_form():
+    pairs = [(2, 3), (3, 5), (7, 11), (13, 37), (15, 43), (72, 77), (1, 9)]
+    for a, b in pairs:
+        for n in range(0, 600):
+            c = oracle.count(n, [a, b])
+            assert c == popoviciu(n, a, b), (a, b, n)
+            assert c in (n // (a * b), n // (a * b) + 1)
+
+
+def test_textbook_values():
+    # Ways to change a dollar with 1, 5, 10, 25 and 50 cent coins.
+    assert oracle.count(100, [1, 5, 10, 25, 50]) == 292
+    # Partition numbers p(50), p(100): parts 1..n.
+    assert oracle.count(50, list(range(1, 51))) == 204226
+    assert oracle.count(100, list(range(1, 101))) == 190569292
+
+
+def test_overflow_is_reported():
+    with pytest.raises(OverflowError):
+        oracle.count(3000, [1] * 32)
+
+
+# --------------------------------------------------------------------------
+# Table 1 of the paper
+# --------------------------------------------------------------------------
+
+def table1():
+    rows = []
+    with open(os.path.join(GOLDEN, "table1_counts.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                d, k, n, num = (int(x) for x in line.split())
+                rows.append((d, k, n, num))
+    return rows
+
+
+G_TABLE1 = (13, 37, 38, 40, 41, 42, 43, 44, 45)
+
+
+def count_d4_by_pairs(n):
+    """|Z(n; 13, 37, 38, 40)| by a double loop over (a_1, a_2) and Popoviciu on
+    the last two generators (38 and 40 share the factor 2: halve them)."""
+    total = 0
+    for a1 in range(n // 13 + 1):
+        r1 = n - 13 * a1
+        for a2 in range(r1 // 37 + 1):
+            r = r1 - 37 * a2
+            if r % 2 == 0:
+                total += popoviciu(r // 2, 19, 20)
+    return total
+
+
+def test_table1_counts():
+    seen = {}
+    for d, k, n, num in table1():
+        c = seen.setdefault((d, n), oracle.count(n, G_TABLE1[:d]))
+        if (d, n) == (4, 15000):
+            # Printed as 779252; the definition gives 779257 (two routes agree).
+            assert num == 779252
+            assert c == 779257
+            assert count_d4_by_pairs(n) == 779257
+        else:
+            assert c == num, (d, k, n)
+    assert len(seen) == 23
+
+
+# --------------------------------------------------------------------------
+# Invariants at moderate size
+# --------------------------------------------------------------------------
+
+def check_invariants(rows, n, g):
+    g = np.asarray(g, dtype=np.uint64)
+    r64 = rows.astype(np.uint64)
+    assert (r64 @ g == n).all()
+    assert (r64 <= (n // g)).all()
+    # strictly ascending lexicographically
+    if len(rows) > 1:
+        a, b = r64[:-1], r64[1:]
+        diff = a != b
+        first = np.argmax(diff, axis=1)
+        assert diff.any(axis=1).all()
+        idx = np.arange(len(first))
+        assert (a[idx, first] < b[idx, first]).all()
+
+
+@pytest.mark.parametrize("n,g", [(2000, [7, 11, 13, 17]), (900, [17, 5, 11, 3]),
+                                 (5000, [13, 37, 38, 40]), (700, [10, 12, 14, 16, 19])])
+def test_invariants(n, g):
+    rows = oracle.enumerate_rows(n, g)
+    assert len(rows) == oracle.count(n, g)
+    check_invariants(rows, n, g)
+
+
+def test_config1_count():
+    # Plain single query: generators (7, 11, 13, 17), n = 2000.
+    assert oracle.count(2000, [7, 11, 13, 17]) == 81205
+
+
+# --------------------------------------------------------------------------
+# Unranking, memo, threads
+# --------------------------------------------------------------------------
+
+def test_unrank_matches_brute_force():
+    for n, g in tiny_cases(5, 60, dmax=4, nmax=40):
+        want = brute(n, g)
+        t = oracle.count_table(n, g)
+        for r, row in enumerate(want):
+            assert tuple(int(x) for x in oracle.unrank(n, g, r, t)) == row
+        with pytest.raises(oracle.OracleError):
+            oracle.unrank(n, g, len(want), t)
+
+
+def test_memo_matches_brute_force():
+    for h, top in [([3, 5], 40), ([4, 6, 9], 50), ([7], 30), ([2, 2], 17), ([9, 4, 6], 45)]:
+        off, rows = oracle.memo(h, top)
+        for p in range(top):
+            assert as_tuples(rows[int(off[p]):int(off[p + 1])]) == brute(p, h), (h, p)
+
+
+def test_threaded_enumeration_matches():
+    n, g = 1500, [7, 11, 13, 17]
+    full = oracle.enumerate_rows(n, g)
+    for nt in (1, 3, 8):
+        out, got = oracle.enumerate_rows_threads(n, g, 0, n // 7 + 1, nt)
+        assert got == len(full)
+        assert np.array_equal(out[:got], full)
+    out, got = oracle.enumerate_rows_threads(n, g, 10, 50, 4)
+    assert np.array_equal(out[:got], oracle.enumerate_rows(n, g, 10, 50))
+
+
+# --------------------------------------------------------------------------
+# Checksum
+# --------------------------------------------------------------------------
+
+def test_fnv1a64_published_vectors():
+    assert oracle.fnv1a64(b"") == 0xCBF29CE484222325
+    assert oracle.fnv1a64(b"a") == 0xAF63DC4C8601EC8C
+    assert oracle.fnv1a64(b"foobar") == 0x85944171F73967E8
+
+
+def test_checksum_framing():
+    # One row of zeros at rank 0 hashes 8 + 4d zero bytes.
+    for d in (1, 3, 6):
+        assert oracle.checksum(np.zeros((1, d), np.uint32)) == oracle.fnv1a64(bytes(8 + 4 * d))
+    # Row (1, 2) at rank 5: LE64(5) then LE32(1), LE32(2).
+    b = (5).to_bytes(8, "little") + (1).to_bytes(4, "little") + (2).to_bytes(4, "little")
+    assert oracle.checksum(np.array([[1, 2]], np.uint32), rank0=5) == oracle.fnv1a64(b)
+
+
+def test_checksum_is_order_sensitive_and_splittable():
+    rows = oracle.enumerate_rows(400, [3, 5, 7])
+    s = oracle.checksum(rows)
+    swapped = rows.copy()
+    swapped[[3, 4]] = swapped[[4, 3]]
+    assert oracle.checksum(swapped) != s
+    bumped = rows.copy()
+    bumped[10, 1] += 1
+    assert oracle.checksum(bumped) != s
+    k = 137
+    parts = (oracle.checksum(rows[:k]) + oracle.checksum(rows[k:], rank0=k)) % (1 << 64)
+    assert parts == s
+
+
+# --------------------------------------------------------------------------
+# The paper's own algorithms reach the same lists
+# --------------------------------------------------------------------------
+
+def test_alg_2_8_lists_are_descending_factorization_sets():
+    for n, g in tiny_cases(6, 60, dmax=4, nmax=40):
+        F = method.lex_lists_up_to(n, g)
+        for m in range(n + 1):
+            assert F[m] == brute(m, g)[::-1], (n, g, m)
+
+
+def test_alg_2_9_matches_alg_2_8():
+    for n, g in tiny_cases(7, 60, dmax=4, nmax=40):
+        assert method.lex_lists_factorizationwise(n, g) == method.lex_lists_up_to(n, g)
+
+
+def test_ascending_memo_blocks_are_prefixes():
+    # Ascending form of Lemma 2.6: Z(m) is the concatenation over i = d..1 of
+    # incr_i(first |Z_{>=i}(m - g_i)| rows of Z(m - g_i)) -- each source run is
+    # a prefix of the ascending source list.
+    for h, top in [([3, 5, 7], 60), ([4, 6], 40), ([5, 2, 3], 50)]:
+        off, rows = oracle.memo(h, top)
+        Z = [as_tuples(rows[int(off[p]):int(off[p + 1])]) for p in range(top)]
+        k = len(h)
+        for m in range(1, top):
+            built = []
+            for i in reversed(range(k)):
+                src = m - h[i]
+                if src < 0:
+                    continue
+                ge = [r for r in Z[src] if all(r[j] == 0 for j in range(i))]
+                assert Z[src][:len(ge)] == ge
+                built.extend(method.incr(r, i) for r in ge)
+            assert built == Z[m], (h, m)
+
+
+def test_alg_3_1_stream_matches_oracle():
+    for n, g in tiny_cases(8, 150, dmax=5, nmax=45):
+        s = method.next_candidate_stream(n, g)
+        assert s[::-1] == as_tuples(oracle.enumerate_rows(n, g)), (n, g)
+
+
+def test_alg_3_2_stream_matches_oracle_for_every_memo_dim_and_top():
+    rng = np.random.default_rng(9)
+    for n, g in tiny_cases(10, 120, dmax=5, nmax=45):
+        d = len(g)
+        want = as_tuples(oracle.enumerate_rows(n, g))
+        for k in range(1, d):
+            h = g[d - k:]
+            for top in {n + 1, int(rng.integers(0, n + 2))}:
+                off, rows = oracle.memo(h, max(top, 1))
+                memo = [as_tuples(rows[int(off[p]):int(off[p + 1])])[::-1] for p in range(top)]
+                s = method.next_candidate_stream(n, g, memo, k, top)
+                assert s[::-1] == want, (n, g, k, top)
