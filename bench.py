@@ -1,0 +1,161 @@
+"""Benchmark: factorizations/s of one large enumeration of Z(n; g) on one GPU.
+
+A step is one pass of the whole path over the workload with the output
+buffer already resident in HBM: count table, memo build (k = 2, the dynamic
+recurrence), slice plan, and the write pass that stores every uint32 row.
+Prints one JSON line (the driver's contract).
+
+The default workload is the large single enumeration: d = 6 generators drawn
+distinct in [10, 100] with gcd 1 (seed 0), n the smallest element with
+|Z(n)| >= 2e8, memo dimension k = 2.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E peak, GB/s
+ALU_PEAK_OPS = 256 * 64 * 2.4e9   # 32-bit integer lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=["large", "plain"])
+    ap.add_argument("--seed", type=int, default=0, help="large workload seed (0, 1 or 2)")
+    ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--rows-per-tile", type=int, default=0)
+    ap.add_argument("--count-only", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=float, default=5e7)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, g, sample_rows):
+    """The CPU oracle (threaded over a_1) on the rows with a_1 < A, the smallest
+    prefix of a_1 values holding >= sample_rows rows."""
+    import numpy as np
+
+    import oracle
+    table = oracle.count_table(n, g)
+    row1 = table[1]
+    acc, a1 = 0, 0
+    while a1 * g[0] <= n and acc < sample_rows:
+        acc += int(row1[n - a1 * g[0]])
+        a1 += 1
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(int(threads), 64))
+    out = np.empty((acc, len(g)), dtype=np.uint32)
+    out[::max(1, acc // 1024)] = 0   # touch pages before timing
+    out.fill(0)
+    t = time.perf_counter()
+    _, rows = oracle.enumerate_rows_threads(n, g, 0, a1, threads, table=table, out=out)
+    dt = time.perf_counter() - t
+    return {"value": rows / dt, "unit": "factorizations/s", "cores": threads, "kind": "oracle",
+            "sample": f"rows with a_1 < {a1} ({rows} of the workload's rows), "
+                      f"threaded C oracle, {dt:.2f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the enumeration shards by rank ranges with no "
+              "communication, and this build runs on a single MI355X (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2407_20474_amd import inputs, zset
+
+    w = inputs.load_workloads()
+    if args.workload == "large":
+        item = w["large"][args.seed]
+        n, g, k = item["n"], item["gens"], item["k"]
+    else:
+        item = w["plain"]
+        n, g, k = item["n"], item["gens"], item["k"]
+    if args.k is not None:
+        k = args.k
+    d = len(g)
+    rows = zset.count(n, g)
+    assert rows == item["rows"], "count disagrees with the stored workload"
+    out = None
+    if not args.count_only:
+        out = torch.empty((rows, d), dtype=torch.int32, device="cuda")
+
+    def step():
+        return zset.enumerate_ex(n, g, out=out, k=k, rows_per_tile=args.rows_per_tile,
+                                 count_only=args.count_only)
+
+    for i in range(args.warmup):
+        step()
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step().stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = rows / (dt / args.steps)
+
+    def avg(key):
+        return sum(s[key] for s in stats) / len(stats)
+
+    write_us = avg("write_us")
+    bytes_written = rows * d * 4
+    if args.count_only:
+        # Count-only is integer-ALU bound: FNV-1a over 8 + 4d bytes per row,
+        # ~7 lane-ops per byte (xor, 64-bit multiply by 2^40 + 0x1b3).
+        ops = rows * (8 + 4 * d) * 7
+        roof = {"bound": "alu", "achieved": ops / (write_us * 1e-6) / 1e12,
+                "peak": ALU_PEAK_OPS / 1e12, "unit": "Tops/s",
+                "frac": (ops / (write_us * 1e-6)) / ALU_PEAK_OPS, "traffic": None}
+    else:
+        achieved = bytes_written / (write_us * 1e-6) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "kernel": "k_write<1,false,true> (write pass)",
+                "algorithmic_bytes_per_launch": bytes_written}
+    line = {
+        "metric": "Z(n) factorizations/s emitted (bit-exact)",
+        "value": value,
+        "unit": "factorizations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"{args.workload}: Z(n={n}; g={tuple(g)}), d={d}, k={k}, "
+                         f"|Z|={rows} rows of {d} uint32 ({bytes_written / 1e9:.2f} GB)"
+                         + (", count-only" if args.count_only else "")),
+            "rows": rows, "n": n, "gens": g, "k": k,
+            "rows_per_tile": stats[-1]["rows_per_tile"], "tiles": stats[-1]["tiles"],
+        },
+        "stages_us": {key: round(avg(key), 2) for key in
+                      ("count_us", "memo_us", "plan_us", "write_us", "total_us")},
+        "step_hbm_write_frac": round(bytes_written / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, g, args.cpu_sample_rows)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * zset.h -- C ABI of the MI355X factorization-set library (libzset.so).
+ *
+ * The library enumerates the factorization set
+ *
+ *     Z(n; g_1..g_d) = { a in N^d : sum_i a_i g_i = n }        (paper, Section 1)
+ *
+ * on one gfx950 GPU, writing every element as a row of d uint32 coordinates,
+ * row-major, in strictly ascending lexicographic order (a_1 most significant).
+ * It follows the paper's parallel bounded lexicographic enumeration with
+ * low-dimension tabulation (Section 3, Alg 3.2): workers own bounded slices of
+ * the output, step over the leading coordinates, and copy whole blocks of the
+ * trailing k coordinates from a memo built on the GPU by the dynamic recurrence
+ * of Lemma 2.3 run in elementwise batches (Section 2.2, Alg 2.9).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers documented as "host" are read before the call returns and are
+ *     owned by the caller.  Pointers documented as "device" must be device
+ *     memory of the current HIP device (hipMalloc or a torch CUDA tensor).
+ *   - Generators are taken in the caller's order; they are never sorted.
+ *     Repeated generators and gcd > 1 are allowed (Z stays finite and exact).
+ *   - Limits: 1 <= d <= ZSET_MAX_D, every g_i >= 1, n <= 2^32 - 1.
+ *   - Status codes are returned, never thrown; zset_strerror gives the text.
+ *     On any error returned before the first kernel launch, `out` is untouched.
+ *   - Every call that launches work synchronises its stream before returning.
+ *   - The library keeps per-device scratch memory (count table, tile table,
+ *     memo staging) that it grows on demand and reuses; calls are serialised
+ *     by an internal lock.
+ */
+#ifndef ZSET_H
+#define ZSET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZSET_MAX_D 32
+
+typedef enum {
+    ZSET_OK = 0,
+    ZSET_EINVAL = -1,     /* invalid argument (see each entry point)            */
+    ZSET_EOVERFLOW = -2,  /* |Z(n)| >= 2^64 - 1, or rows * d exceeds 2^64       */
+    ZSET_ENOMEM = -3,     /* device or pinned host allocation failed            */
+    ZSET_ECAPACITY = -4,  /* the output buffer holds fewer rows than |Z(n)|     */
+    ZSET_EDEVICE = -5     /* a HIP call failed, or a kernel's own check failed  */
+} zset_status;
+
+/* Opaque, immutable, device-resident memo of Z(p; h_1..h_k) for p < top. */
+typedef struct zset_memo_s *zset_memo;
+
+typedef struct {
+    int k;                   /* memo dimension (trailing coordinates copied from
+                                the memo); -1 = automatic.  k = 0 solves the last
+                                coordinate by division (Alg 3.1); k >= 1 uses the
+                                memo (Alg 3.2).  Must lie in [0, d-1].          */
+    int order;               /* 0 = ascending lex (default); 1 = descending, the
+                                order the paper's streams produce.              */
+    uint64_t rows_per_tile;  /* rows per worker slice; 0 = automatic.  Must be a
+                                multiple of 128 when set.                       */
+    int count_only;          /* 1 = no rows are written: only |Z(n)| and the
+                                checksum are produced (`out` may be NULL).      */
+    void *stream;            /* hipStream_t to run on; NULL = the null stream.  */
+} zset_opts;
+
+/* Per-call timings (device time between HIP events on the call's stream) and
+ * sizes.  Filled by zset_enumerate_ex when `stats` is non-NULL. */
+typedef struct {
+    double count_us;         /* count-table kernel                              */
+    double memo_us;          /* memo build (0 when a memo handle is passed)     */
+    double plan_us;          /* slice table (unranking of each slice start)     */
+    double write_us;         /* write (or count-only) pass                      */
+    double total_us;         /* first to last event                             */
+    uint64_t rows;           /* |Z(n)|                                          */
+    uint64_t memo_rows;      /* rows of the memo used                           */
+    uint64_t memo_bytes;     /* device bytes of the memo used                   */
+    uint64_t tiles;          /* worker slices launched                          */
+    uint64_t rows_per_tile;
+    int k;                   /* memo dimension used                             */
+} zset_stats;
+
+/* Fill *opts with the defaults: k = -1, ascending, automatic slices, rows
+ * written, null stream. */
+void zset_default_opts(zset_opts *opts);
+
+/*
+ * zset_count -- |Z(n; g)| (Section 1), computed on the GPU from the count
+ * table C_j[x] = |Z(x; g_j..g_d)| (C_j[x] = C_{j+1}[x] + C_j[x - g_j]).
+ *   n      element, <= 2^32 - 1
+ *   gens   host, d uint32 generators, each >= 1
+ *   count  host, receives |Z(n)|
+ * Errors: EINVAL (bad d, gens, n or NULL pointer), EOVERFLOW (|Z| >= 2^64-1),
+ *         ENOMEM, EDEVICE.
+ */
+zset_status zset_count(uint64_t n, const uint32_t *gens, int d, uint64_t *count);
+
+/*
+ * zset_count_table -- the whole count table, for inspection and tests:
+ *   table[j * (n+1) + x] = |Z(x; g_{j+1}..g_d)|  for j = 0..d, x = 0..n
+ * (row d is 1 at x = 0 and 0 elsewhere).  Entries saturate at 2^64 - 1.
+ *   table  device, (d+1)*(n+1) uint64, written
+ *   stream hipStream_t or NULL
+ * Errors: EINVAL, EDEVICE.
+ */
+zset_status zset_count_table(uint64_t n, const uint32_t *gens, int d,
+                             uint64_t *table, void *stream);
+
+/*
+ * zset_memo_build -- memo of the trailing generators h (Section 3.1): the
+ * lists Z(p; h_1..h_k) for every p in [0, top), each in ascending lex order,
+ * built on the GPU by the disjoint recurrence of Lemma 2.3 read in ascending
+ * order -- Z(p) is the concatenation over i = k..1 of incr_i applied to the
+ * first |Z_{>=i}(p - h_i)| rows of Z(p - h_i) -- run elementwise in batches of
+ * min(h) consecutive elements (Section 2.2) with one worker per copied row
+ * (Alg 2.9, Section 2.3).
+ *   gens_trailing host, k uint32 generators h_1..h_k, each >= 1
+ *   k             1 <= k <= ZSET_MAX_D - 1
+ *   top           number of elements tabulated, >= 1, <= 2^32
+ *   stream        hipStream_t or NULL
+ *   memo          host, receives the handle (free with zset_memo_free)
+ * Errors: EINVAL, EOVERFLOW (memo rows >= 2^32), ENOMEM, EDEVICE.
+ */
+zset_status zset_memo_build(const uint32_t *gens_trailing, int k, uint64_t top,
+                            void *stream, zset_memo *memo);
+
+/* Release a memo handle (NULL is ignored). */
+void zset_memo_free(zset_memo memo);
+
+/*
+ * zset_memo_read -- copy a memo to host memory.
+ *   off   host, top+1 uint64: rows of Z(p; h) are rows[off[p] .. off[p+1])
+ *   rows  host, off[top]*k uint32, or NULL to get the sizes only
+ *   top_out, k_out, rows_out: host, optional (NULL to skip)
+ * Errors: EINVAL, EDEVICE.
+ */
+zset_status zset_memo_read(zset_memo memo, uint64_t *off, uint32_t *rows,
+                           uint64_t *top_out, int *k_out, uint64_t *rows_out);
+
+/*
+ * zset_enumerate -- all of Z(n; g) into `out` (the spec form): default
+ * options, null stream, synchronous.
+ *   out  device, at least |Z(n)| * d uint32 (size it with zset_count)
+ * Errors: as zset_enumerate_ex.
+ */
+zset_status zset_enumerate(uint64_t n, const uint32_t *gens, int d, uint32_t *out);
+
+/*
+ * zset_enumerate_ex -- Z(n; g) with options.
+ *   out           device, out_rows_cap * d uint32; ignored when count_only
+ *   out_rows_cap  rows `out` holds; ECAPACITY before any launch if < |Z(n)|
+ *   opts          host, or NULL for the defaults
+ *   memo          optional memo handle whose generators equal g_{d-k+1..d}
+ *                 (then k = the memo's k) and whose top exceeds n; NULL = the
+ *                 call builds its own memo
+ *   rows_written  host, optional: |Z(n)|
+ *   checksum      host, optional: sum over rows r (ascending rank r) of
+ *                 FNV-1a-64(LE64(r) || LE32(a_1) .. LE32(a_d)) mod 2^64,
+ *                 computed on the GPU only when count_only is set (else 0)
+ *   stats         host, optional: timings and sizes
+ * Errors: EINVAL (bad d/gens/n/k/order/rows_per_tile, `out` not device
+ *         memory, memo mismatch or memo top <= n), EOVERFLOW, ECAPACITY,
+ *         ENOMEM, EDEVICE.
+ */
+zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t *out,
+                              uint64_t out_rows_cap, const zset_opts *opts,
+                              zset_memo memo, uint64_t *rows_written,
+                              uint64_t *checksum, zset_stats *stats);
+
+/* Static text for a status code. */
+const char *zset_strerror(zset_status status);
+
+/*
+ * zset_selftest_host -- checks of host-side helpers that need no GPU (the
+ * magic-number division used by the kernels, argument validation).  Returns
+ * ZSET_OK or ZSET_EDEVICE with a message in zset_last_error().
+ */
+zset_status zset_selftest_host(void);
+
+/* Text of the last error detected by the library on this thread ("" if none). */
+const char *zset_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZSET_H */

@@ -1,0 +1,587 @@
+// api.hip -- the C ABI of libzset.so (include/zset.h): argument checks,
+// per-device scratch memory, the order of launches, status codes and timings.
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "zset.h"
+#include "zset_internal.h"
+
+namespace zset {
+namespace {
+
+// Count-table rows have n + 1 entries indexed in 32 bits on the device.
+constexpr uint64_t kMaxN = (uint64_t(1) << 31) - 2;
+// LDS a single workgroup may use for the memo chain.
+constexpr size_t kChainLdsBudget = 152 * 1024;
+
+thread_local std::string g_last_error;
+
+zset_status fail(zset_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+zset_status hip_fail(hipError_t e, const char* what) {
+  (void)hipGetLastError();
+  return fail(ZSET_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define ZSET_HIP(call)                          \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+bool fault_injected(const char* what) {
+  const char* f = std::getenv("ZSET_FAULT");
+  return f && std::strcmp(f, what) == 0;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+zset_status ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return ZSET_OK;
+  if (fault_injected("alloc")) return fail(ZSET_ENOMEM, "allocation refused (ZSET_FAULT=alloc)");
+  if (b.p) {
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    if (hipMalloc(&b.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return fail(ZSET_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    want = bytes;
+  }
+  b.bytes = want;
+  return ZSET_OK;
+}
+
+// Per-device scratch, reused across calls.
+struct Ctx {
+  int device = -1;
+  DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount;
+  uint64_t* pinned = nullptr;  // host readback area
+  hipEvent_t ev[6] = {};
+};
+
+std::mutex g_mu;
+std::map<int, Ctx*> g_ctx;
+
+// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..] row sums
+constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2;
+constexpr size_t kMiscWords = 2 + kMaxD + 2;
+constexpr size_t kPinnedWords = 64;
+
+zset_status get_ctx(Ctx** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  auto it = g_ctx.find(dev);
+  if (it != g_ctx.end()) {
+    *out = it->second;
+    return ZSET_OK;
+  }
+  Ctx* c = new Ctx();
+  c->device = dev;
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->pinned), kPinnedWords * sizeof(uint64_t),
+                    hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    (void)hipGetLastError();
+    return fail(ZSET_ENOMEM, "hipHostMalloc of the readback area failed");
+  }
+  for (auto& ev : c->ev) {
+    if (hipEventCreate(&ev) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ZSET_EDEVICE, "hipEventCreate failed");
+    }
+  }
+  zset_status st = ensure(c->misc, kMiscWords * sizeof(uint64_t));
+  if (st != ZSET_OK) return st;
+  g_ctx[dev] = c;
+  *out = c;
+  return ZSET_OK;
+}
+
+zset_status check_gens(const uint32_t* gens, int d, const char* what) {
+  if (!gens) return fail(ZSET_EINVAL, std::string(what) + " is NULL");
+  if (d < 1 || d > kMaxD) return fail(ZSET_EINVAL, "d must lie in [1, 32]");
+  for (int i = 0; i < d; ++i)
+    if (gens[i] == 0) return fail(ZSET_EINVAL, "every generator must be >= 1");
+  return ZSET_OK;
+}
+
+zset_status check_query(uint64_t n, const uint32_t* gens, int d) {
+  zset_status st = check_gens(gens, d, "gens");
+  if (st != ZSET_OK) return st;
+  if (n > kMaxN) return fail(ZSET_EINVAL, "n exceeds 2^31 - 2");
+  return ZSET_OK;
+}
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
+const char* device_error_text(int code) {
+  switch (code) {
+    case kErrOdometer: return "a slice ran out of prefixes before its rows were written";
+    case kErrTileRows: return "a slice wrote a different number of rows than planned";
+    case kErrMemoTotal: return "the memo build produced a different row total than counted";
+    case kErrUnrank: return "a slice start could not be unranked";
+    default: return "unknown kernel check";
+  }
+}
+
+float elapsed_us(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms * 1000.f;
+}
+
+uint32_t next_pow2(uint32_t v) {
+  uint32_t p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+// Builds Memo[p] = Z(p; h) for p < top into nat (natural order).  `ge` holds
+// |Z(m; h_i..h_k)| for i = 0..k-1 (row stride ge_stride), `off` the natural
+// offsets (top + 1 entries), R = off[top].
+zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, const uint64_t* off,
+                            const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint32_t* nat,
+                            hipStream_t s) {
+  uint32_t b = h[0], hmax = h[0];
+  for (int i = 1; i < k; ++i) {
+    b = std::min(b, h[i]);
+    hmax = std::max(hmax, h[i]);
+  }
+  const char* path = std::getenv("ZSET_MEMO_PATH");
+  const bool force_global = path && std::strcmp(path, "global") == 0;
+  const uint64_t Wl = uint64_t(hmax) + b;
+  const uint32_t W = Wl < (uint64_t(1) << 30) ? next_pow2(uint32_t(Wl)) : 0;
+  int* err = reinterpret_cast<int*>(c->misc.p) + 0;
+  if (!force_global && W != 0 && b <= 1024 && R < (uint64_t(1) << 30) &&
+      memo_chain_lds_bytes(k, R, W, b) <= kChainLdsBudget) {
+    ZSET_HIP(launch_memo_chain_lds(h, k, top, b, W, R, nat, err, s));
+    return ZSET_OK;
+  }
+  zset_status st = ensure(c->srcw, size_t(R) * sizeof(uint64_t));
+  if (st != ZSET_OK) return st;
+  ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride,
+                              reinterpret_cast<uint64_t*>(c->srcw.p), nat, err, s));
+  return ZSET_OK;
+}
+
+}  // namespace
+}  // namespace zset
+
+struct zset_memo_s {
+  int device;
+  int k;
+  uint64_t top;
+  uint64_t rows;
+  uint32_t h[zset::kMaxD];
+  uint64_t* off;  // device, top + 1
+  uint32_t* nat;  // device, rows * k
+};
+
+using namespace zset;
+
+extern "C" {
+
+void zset_default_opts(zset_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->k = -1;
+}
+
+const char* zset_strerror(zset_status s) {
+  switch (s) {
+    case ZSET_OK: return "success";
+    case ZSET_EINVAL: return "invalid argument";
+    case ZSET_EOVERFLOW: return "count overflows 64 bits";
+    case ZSET_ENOMEM: return "out of memory";
+    case ZSET_ECAPACITY: return "output buffer too small";
+    case ZSET_EDEVICE: return "device error";
+  }
+  return "unknown status";
+}
+
+const char* zset_last_error(void) { return g_last_error.c_str(); }
+
+zset_status zset_count(uint64_t n, const uint32_t* gens, int d, uint64_t* count) {
+  g_last_error.clear();
+  zset_status st = check_query(n, gens, d);
+  if (st != ZSET_OK) return st;
+  if (!count) return fail(ZSET_EINVAL, "count is NULL");
+  std::lock_guard<std::mutex> lock(g_mu);
+  Ctx* c = nullptr;
+  if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  const uint64_t N = n + 1;
+  if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
+  uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
+  ZSET_HIP(launch_count_table(T, n, gens, d, nullptr));
+  ZSET_HIP(hipMemcpyAsync(c->pinned, T + n, sizeof(uint64_t), hipMemcpyDeviceToHost, nullptr));
+  ZSET_HIP(hipStreamSynchronize(nullptr));
+  *count = c->pinned[0];
+  if (*count == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
+  return ZSET_OK;
+}
+
+zset_status zset_count_table(uint64_t n, const uint32_t* gens, int d, uint64_t* table,
+                             void* stream) {
+  g_last_error.clear();
+  zset_status st = check_query(n, gens, d);
+  if (st != ZSET_OK) return st;
+  if (!table) return fail(ZSET_EINVAL, "table is NULL");
+  if (!is_device_pointer(table)) return fail(ZSET_EINVAL, "table is not device memory");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  ZSET_HIP(launch_count_table(table, n, gens, d, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  return ZSET_OK;
+}
+
+zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, void* stream,
+                            zset_memo* memo) {
+  g_last_error.clear();
+  if (!memo) return fail(ZSET_EINVAL, "memo is NULL");
+  *memo = nullptr;
+  if (k < 1 || k > kMaxD - 1) return fail(ZSET_EINVAL, "k must lie in [1, 31]");
+  zset_status st = check_gens(gens_trailing, k, "gens_trailing");
+  if (st != ZSET_OK) return st;
+  if (top < 1 || top - 1 > kMaxN) return fail(ZSET_EINVAL, "top must lie in [1, 2^31 - 1]");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  Ctx* c = nullptr;
+  if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  // Count table of the memo's own generators up to top - 1: row i holds
+  // |Z(m; h_i..h_k)| = |Z_{>=i}(m; h)|, and row 0 gives the list sizes.
+  const uint64_t nm = top - 1;
+  if ((st = ensure(c->hcount, size_t(k + 1) * top * sizeof(uint64_t))) != ZSET_OK) return st;
+  uint64_t* CT = reinterpret_cast<uint64_t*>(c->hcount.p);
+  ZSET_HIP(launch_count_table(CT, nm, gens_trailing, k, s));
+  zset_memo m = new zset_memo_s();
+  std::memset(m, 0, sizeof *m);
+  m->k = k;
+  m->top = top;
+  m->device = c->device;
+  for (int i = 0; i < k; ++i) m->h[i] = gens_trailing[i];
+  auto cleanup = [&](zset_status r) {
+    if (m->off) (void)hipFree(m->off);
+    if (m->nat) (void)hipFree(m->nat);
+    delete m;
+    return r;
+  };
+  if (fault_injected("alloc")) return cleanup(fail(ZSET_ENOMEM, "allocation refused (ZSET_FAULT=alloc)"));
+  if (hipMalloc(&m->off, (top + 1) * sizeof(uint64_t)) != hipSuccess) {
+    (void)hipGetLastError();
+    m->off = nullptr;
+    return cleanup(fail(ZSET_ENOMEM, "hipMalloc of memo offsets failed"));
+  }
+  hipError_t e = launch_exclusive_scan(CT, top, m->off, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->pinned, m->off + top, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "memo offsets"));
+  const uint64_t R = c->pinned[0];
+  if (R == ~uint64_t(0)) return cleanup(fail(ZSET_EOVERFLOW, "memo rows overflow 64 bits"));
+  m->rows = R;
+  if (hipMalloc(&m->nat, std::max<size_t>(16, size_t(R) * k * sizeof(uint32_t))) != hipSuccess) {
+    (void)hipGetLastError();
+    m->nat = nullptr;
+    return cleanup(fail(ZSET_ENOMEM, "hipMalloc of memo rows failed"));
+  }
+  int* err = reinterpret_cast<int*>(c->misc.p);
+  e = hipMemsetAsync(err, 0, sizeof(int), s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync"));
+  st = build_memo_rows(c, m->h, k, top, m->off, CT, top, R, m->nat, s);
+  if (st != ZSET_OK) return cleanup(st);
+  e = hipMemcpyAsync(c->pinned, err, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "memo build"));
+  const int code = *reinterpret_cast<int*>(c->pinned);
+  if (code != 0) return cleanup(fail(ZSET_EDEVICE, device_error_text(code)));
+  *memo = m;
+  return ZSET_OK;
+}
+
+void zset_memo_free(zset_memo memo) {
+  if (!memo) return;
+  if (memo->off) (void)hipFree(memo->off);
+  if (memo->nat) (void)hipFree(memo->nat);
+  delete memo;
+}
+
+zset_status zset_memo_read(zset_memo memo, uint64_t* off, uint32_t* rows, uint64_t* top_out,
+                           int* k_out, uint64_t* rows_out) {
+  g_last_error.clear();
+  if (!memo) return fail(ZSET_EINVAL, "memo is NULL");
+  if (top_out) *top_out = memo->top;
+  if (k_out) *k_out = memo->k;
+  if (rows_out) *rows_out = memo->rows;
+  if (off) ZSET_HIP(hipMemcpy(off, memo->off, (memo->top + 1) * sizeof(uint64_t),
+                              hipMemcpyDeviceToHost));
+  if (rows && memo->rows)
+    ZSET_HIP(hipMemcpy(rows, memo->nat, memo->rows * memo->k * sizeof(uint32_t),
+                       hipMemcpyDeviceToHost));
+  return ZSET_OK;
+}
+
+zset_status zset_enumerate(uint64_t n, const uint32_t* gens, int d, uint32_t* out) {
+  return zset_enumerate_ex(n, gens, d, out, ~uint64_t(0), nullptr, nullptr, nullptr, nullptr,
+                           nullptr);
+}
+
+zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
+                              uint64_t out_rows_cap, const zset_opts* opts_in, zset_memo memo,
+                              uint64_t* rows_written, uint64_t* checksum, zset_stats* stats) {
+  g_last_error.clear();
+  zset_status st = check_query(n, gens, d);
+  if (st != ZSET_OK) return st;
+  zset_opts opts;
+  if (opts_in) opts = *opts_in; else zset_default_opts(&opts);
+  if (opts.k < -1 || opts.k > d - 1) return fail(ZSET_EINVAL, "k must be -1 or lie in [0, d-1]");
+  if (opts.order != 0 && opts.order != 1) return fail(ZSET_EINVAL, "order must be 0 or 1");
+  if (opts.rows_per_tile % 128 != 0 || opts.rows_per_tile > (uint64_t(1) << 30))
+    return fail(ZSET_EINVAL, "rows_per_tile must be a multiple of 128 and at most 2^30");
+  const bool count_only = opts.count_only != 0;
+  if (!count_only && !out) return fail(ZSET_EINVAL, "out is NULL");
+  if (memo) {
+    if (opts.k != -1 && opts.k != memo->k)
+      return fail(ZSET_EINVAL, "opts.k differs from the memo's k");
+    if (memo->k > d - 1) return fail(ZSET_EINVAL, "memo has more coordinates than d - 1");
+    for (int i = 0; i < memo->k; ++i)
+      if (memo->h[i] != gens[d - memo->k + i])
+        return fail(ZSET_EINVAL, "memo generators differ from the trailing generators");
+    if (memo->top < n + 1) return fail(ZSET_EINVAL, "memo top must exceed n");
+  }
+  if (!count_only && !is_device_pointer(out)) return fail(ZSET_EINVAL, "out is not device memory");
+
+  hipStream_t s = reinterpret_cast<hipStream_t>(opts.stream);
+  std::lock_guard<std::mutex> lock(g_mu);
+  Ctx* c = nullptr;
+  if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  if (memo && memo->device != c->device)
+    return fail(ZSET_EINVAL, "memo lives on another device");
+
+  const uint64_t N = n + 1;
+  uint64_t* misc = reinterpret_cast<uint64_t*>(c->misc.p);
+  int* err = reinterpret_cast<int*>(misc + kMiscErr);
+  if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
+  uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
+
+  // 1. Count table, row sums (memo sizes), total.
+  ZSET_HIP(hipEventRecord(c->ev[0], s));
+  ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
+  ZSET_HIP(launch_count_table(T, n, gens, d, s));
+  ZSET_HIP(launch_row_sums(T, n, d + 1, misc + kMiscRowSums, s));
+  ZSET_HIP(hipEventRecord(c->ev[1], s));
+  ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 1) * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipMemcpyAsync(c->pinned + (d + 1), T + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  uint64_t sums[kMaxD + 1];
+  for (int j = 0; j <= d; ++j) sums[j] = c->pinned[j];
+  const uint64_t total = c->pinned[d + 1];
+  if (total == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
+  if (total > (~uint64_t(0)) / (4 * uint64_t(d)))
+    return fail(ZSET_EOVERFLOW, "|Z(n)| * d * 4 bytes overflows 64 bits");
+  if (!count_only && total > out_rows_cap)
+    return fail(ZSET_ECAPACITY, "out holds " + std::to_string(out_rows_cap) + " rows, |Z(n)| = " +
+                                    std::to_string(total));
+
+  // 2. Memo dimension.
+  int k = memo ? memo->k : opts.k;
+  if (d == 1) {
+    k = 0;
+  } else if (k < 0) {
+    // Largest k whose memo stays small beside the output (at most 1/16 of
+    // the rows and 512 MiB); k = 1 always qualifies in practice.
+    k = 1;
+    for (int kk = d - 1; kk >= 1; --kk) {
+      const uint64_t R = sums[d - kk];
+      if (R != ~uint64_t(0) && R <= std::max<uint64_t>(uint64_t(1) << 16, total / 16) &&
+          R * (kk + 1) * 4 <= (uint64_t(512) << 20)) {
+        k = kk;
+        break;
+      }
+    }
+  }
+
+  double memo_us = 0, plan_us = 0, write_us = 0;
+  uint64_t memo_rows = 0, memo_bytes = 0, ntiles = 0, T_rows = 0;
+
+  if (total > 0 && d == 1) {
+    ZSET_HIP(hipEventRecord(c->ev[2], s));
+    ZSET_HIP(hipEventRecord(c->ev[3], s));
+    ZSET_HIP(launch_single(n, gens[0], out, count_only, misc + kMiscSum, s));
+    ZSET_HIP(hipEventRecord(c->ev[4], s));
+  } else if (total > 0) {
+    const int L = d - std::max(k, 1);
+    const int U = (k == 0) ? d - 1 : L - 1;
+    const uint32_t G = gens[U];
+    EnumParams P;
+    std::memset(&P, 0, sizeof P);
+    for (int i = 0; i < d; ++i) P.g.g[i] = gens[i];
+    P.n = uint32_t(n);
+    P.d = d;
+    P.U = U;
+    P.k = k;
+    P.total = total;
+    P.table = T;
+    P.err = err;
+    P.checksum = misc + kMiscSum;
+    P.out = out;
+    P.dG = DivMod32::make(G);
+
+    // 3. Memo (k >= 1): natural-order rows, then the leaf-order layout.
+    ZSET_HIP(hipEventRecord(c->ev[2], s));
+    if (k >= 1) {
+      const uint64_t Rn = sums[L];  // rows of Memo[p] over p <= n
+      memo_rows = Rn;
+      const uint64_t* off = nullptr;
+      const uint32_t* nat = nullptr;
+      if (memo) {
+        off = memo->off;
+        nat = memo->nat;
+      } else {
+        if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+        if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
+        uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
+        ZSET_HIP(launch_exclusive_scan(T + uint64_t(L) * N, N, o, s));
+        st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn,
+                             reinterpret_cast<uint32_t*>(c->nat.p), s);
+        if (st != ZSET_OK) return st;
+        off = o;
+        nat = reinterpret_cast<const uint32_t*>(c->nat.p);
+      }
+      const uint64_t nclass_max = std::min<uint64_t>(G, N);
+      if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
+      if ((st = ensure(c->leaf, size_t(Rn) * (k + 1) * sizeof(uint32_t))) != ZSET_OK) return st;
+      uint32_t nclass = 0;
+      uint64_t* endc = reinterpret_cast<uint64_t*>(c->endc.p);
+      ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, endc, &nclass, s));
+      uint32_t* leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
+      ZSET_HIP(launch_memo_leaf(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, err, s));
+      P.endc = endc;
+      P.leaf = leaf;
+      P.leaf_rows = Rn;
+      memo_bytes = Rn * (k + 1) * 4;
+    }
+    ZSET_HIP(hipEventRecord(c->ev[3], s));
+
+    // 4. Slices: exact rank ranges, starts unranked on the device.
+    T_rows = opts.rows_per_tile;
+    if (T_rows == 0) {
+      const uint64_t want_tiles = 16384;
+      T_rows = (total + want_tiles - 1) / want_tiles;
+      T_rows = (T_rows + 127) / 128 * 128;
+      T_rows = std::max<uint64_t>(T_rows, 128);
+      T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 20);
+    }
+    ntiles = (total + T_rows - 1) / T_rows;
+    P.rows_per_tile = T_rows;
+    P.ntiles = ntiles;
+    if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
+    P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
+    ZSET_HIP(launch_plan(P, s));
+    ZSET_HIP(hipEventRecord(c->ev[4], s));
+
+    // 5. Write (or count-only) pass.
+    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    ZSET_HIP(launch_write(P, count_only, align16, s));
+  } else {
+    ZSET_HIP(hipEventRecord(c->ev[2], s));
+    ZSET_HIP(hipEventRecord(c->ev[3], s));
+    ZSET_HIP(hipEventRecord(c->ev[4], s));
+  }
+  ZSET_HIP(hipEventRecord(c->ev[5], s));
+  if (!count_only && opts.order == 1 && total > 1) ZSET_HIP(launch_reverse(out, total, d, s));
+  ZSET_HIP(hipMemcpyAsync(c->pinned, misc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  const int code = *reinterpret_cast<int*>(c->pinned);
+  if (code != 0) return fail(ZSET_EDEVICE, device_error_text(code));
+  if (rows_written) *rows_written = total;
+  if (checksum) *checksum = count_only ? c->pinned[1] : 0;
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
+    memo_us = elapsed_us(c->ev[2], c->ev[3]);
+    plan_us = elapsed_us(c->ev[3], c->ev[4]);
+    write_us = elapsed_us(c->ev[4], c->ev[5]);
+    stats->memo_us = memo ? 0.0 : memo_us;
+    stats->plan_us = plan_us;
+    stats->write_us = write_us;
+    stats->total_us = elapsed_us(c->ev[0], c->ev[5]);
+    stats->rows = total;
+    stats->memo_rows = memo_rows;
+    stats->memo_bytes = memo_bytes;
+    stats->tiles = ntiles;
+    stats->rows_per_tile = T_rows;
+    stats->k = k;
+  }
+  return ZSET_OK;
+}
+
+zset_status zset_selftest_host(void) {
+  g_last_error.clear();
+  // Division by invariant divisors: spot values around powers of two and
+  // a deterministic pseudo-random sweep.
+  uint64_t state = 0x9e3779b97f4a7c15ull;
+  auto next = [&]() {
+    state ^= state << 13;
+    state ^= state >> 7;
+    state ^= state << 17;
+    return state;
+  };
+  uint32_t divisors[64];
+  int nd = 0;
+  for (uint32_t v : {1u, 2u, 3u, 5u, 7u, 10u, 13u, 37u, 64u, 100u, 641u, 65535u, 65536u,
+                     65537u, 2147483647u, 2147483648u, 4294967295u})
+    divisors[nd++] = v;
+  while (nd < 64) divisors[nd++] = uint32_t(next() >> (next() % 32)) | 1u;
+  for (int i = 0; i < nd; ++i) {
+    const DivMod32 dm = DivMod32::make(divisors[i]);
+    for (int t = 0; t < 20000; ++t) {
+      uint32_t x;
+      switch (t % 4) {
+        case 0: x = uint32_t(next()); break;
+        case 1: x = uint32_t(next() % 100000); break;
+        case 2: x = 4294967295u - uint32_t(next() % 1000); break;
+        default: x = divisors[i] * uint32_t(next() % 1000) + uint32_t(t % 3); break;
+      }
+      const uint32_t q = dm.div(x);
+      if (q != x / divisors[i] || dm.mod(x, q) != x % divisors[i]) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "DivMod32 wrong for %u / %u: got %u", x, divisors[i], q);
+        return fail(ZSET_EDEVICE, buf);
+      }
+    }
+  }
+  return ZSET_OK;
+}
+
+}  // extern "C"

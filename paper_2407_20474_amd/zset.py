@@ -1,0 +1,241 @@
+"""Python binding of libzset.so (include/zset.h): argument marshalling only.
+
+Every step of the enumeration runs in the HIP library; torch supplies device
+memory (the output tensor) and streams.  Importing works without a GPU; the
+calls that launch work need one.  If the library has not been built this
+module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libzset.so")
+
+OK, EINVAL, EOVERFLOW, ENOMEM, ECAPACITY, EDEVICE = 0, -1, -2, -3, -4, -5
+MAX_D = 32
+
+# Exported symbols, in the order include/zset.h declares them.
+SYMBOLS = (
+    "zset_default_opts", "zset_count", "zset_count_table", "zset_memo_build",
+    "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
+    "zset_strerror", "zset_selftest_host", "zset_last_error",
+)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("order", ctypes.c_int),
+                ("rows_per_tile", ctypes.c_uint64), ("count_only", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("count_us", ctypes.c_double), ("memo_us", ctypes.c_double),
+                ("plan_us", ctypes.c_double), ("write_us", ctypes.c_double),
+                ("total_us", ctypes.c_double), ("rows", ctypes.c_uint64),
+                ("memo_rows", ctypes.c_uint64), ("memo_bytes", ctypes.c_uint64),
+                ("tiles", ctypes.c_uint64), ("rows_per_tile", ctypes.c_uint64),
+                ("k", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class ZsetError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        msg = f"{where}: {strerror(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+        self.status = status
+
+
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_lib = None
+
+
+def load():
+    """Load libzset.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2407_20474_amd.build` (no fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.zset_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    lib.zset_default_opts.restype = None
+    lib.zset_count.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, _u64p]
+    lib.zset_count_table.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]
+    lib.zset_memo_build.argtypes = [_u32p, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]
+    lib.zset_memo_free.argtypes = [ctypes.c_void_p]
+    lib.zset_memo_free.restype = None
+    lib.zset_memo_read.argtypes = [ctypes.c_void_p, _u64p, _u32p, _u64p,
+                                   ctypes.POINTER(ctypes.c_int), _u64p]
+    lib.zset_enumerate.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p]
+    lib.zset_enumerate_ex.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
+                                      _u64p, _u64p, ctypes.POINTER(Stats)]
+    lib.zset_strerror.argtypes = [ctypes.c_int]
+    lib.zset_strerror.restype = ctypes.c_char_p
+    lib.zset_selftest_host.argtypes = []
+    lib.zset_last_error.argtypes = []
+    lib.zset_last_error.restype = ctypes.c_char_p
+    for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
+                 "zset_enumerate", "zset_enumerate_ex", "zset_selftest_host"):
+        getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    return load().zset_strerror(status).decode()
+
+
+def last_error() -> str:
+    return load().zset_last_error().decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != OK:
+        raise ZsetError(status, where, last_error())
+
+
+def _gens(gens) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(gens, dtype=np.uint32).reshape(-1))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def selftest_host() -> None:
+    _check(load().zset_selftest_host(), "zset_selftest_host")
+
+
+def count(n: int, gens) -> int:
+    """|Z(n; g)|, computed on the GPU."""
+    g = _gens(gens)
+    out = ctypes.c_uint64(0)
+    _check(load().zset_count(n, g.ctypes.data_as(_u32p), len(g), ctypes.byref(out)),
+           "zset_count")
+    return int(out.value)
+
+
+def count_table(n: int, gens, stream=None):
+    """(d+1, n+1) int64 CUDA tensor holding the uint64 count table bit patterns."""
+    import torch
+    g = _gens(gens)
+    t = torch.empty((len(g) + 1, n + 1), dtype=torch.int64, device="cuda")
+    _check(load().zset_count_table(n, g.ctypes.data_as(_u32p), len(g), t.data_ptr(),
+                                   _stream_handle(stream)), "zset_count_table")
+    return t
+
+
+class Memo:
+    """Device-resident memo of Z(p; h) for p < top (zset_memo_build)."""
+
+    def __init__(self, h, top: int, stream=None):
+        self.h = [int(x) for x in _gens(h)]
+        self.k = len(self.h)
+        self.top = int(top)
+        g = _gens(h)
+        handle = ctypes.c_void_p(None)
+        _check(load().zset_memo_build(g.ctypes.data_as(_u32p), self.k, self.top,
+                                      _stream_handle(stream), ctypes.byref(handle)),
+               "zset_memo_build")
+        self._handle = handle
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def sizes(self):
+        top, k, rows = ctypes.c_uint64(), ctypes.c_int(), ctypes.c_uint64()
+        _check(load().zset_memo_read(self._handle, None, None, ctypes.byref(top),
+                                     ctypes.byref(k), ctypes.byref(rows)), "zset_memo_read")
+        return int(top.value), int(k.value), int(rows.value)
+
+    def read(self):
+        """(off[top+1] uint64, rows[R, k] uint32) copied to the host."""
+        top, k, rows = self.sizes()
+        off = np.empty(top + 1, dtype=np.uint64)
+        data = np.empty((max(rows, 1), k), dtype=np.uint32)
+        _check(load().zset_memo_read(self._handle, off.ctypes.data_as(_u64p),
+                                     data.ctypes.data_as(_u32p), None, None, None),
+               "zset_memo_read")
+        return off, data[:rows]
+
+    def free(self):
+        if self._handle is not None and self._handle.value:
+            load().zset_memo_free(self._handle)
+        self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+@dataclass
+class Result:
+    rows: int
+    checksum: int
+    stats: dict
+    out: object = None   # torch.int32 CUDA tensor (rows, d): the uint32 rows
+
+
+def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
+                 rows_per_tile: int = 0, count_only: bool = False, memo: Memo | None = None,
+                 stream=None, out_rows_cap: int | None = None) -> Result:
+    """Z(n; g) through zset_enumerate_ex.  `out` is an int32 CUDA tensor with at least
+    |Z(n)| * d elements (allocated here when None and count_only is False)."""
+    import torch
+    g = _gens(gens)
+    d = len(g)
+    if out is None and not count_only:
+        rows = count(n, g)
+        out = torch.empty((max(rows, 1), d), dtype=torch.int32, device="cuda")
+    if out is not None:
+        cap = out.numel() // max(d, 1) if out_rows_cap is None else out_rows_cap
+        ptr = out.data_ptr()
+    else:
+        cap, ptr = 0, None
+    opts = Opts()
+    load().zset_default_opts(ctypes.byref(opts))
+    opts.k, opts.order, opts.rows_per_tile = k, order, rows_per_tile
+    opts.count_only = 1 if count_only else 0
+    opts.stream = _stream_handle(stream)
+    rows_written, csum, stats = ctypes.c_uint64(), ctypes.c_uint64(), Stats()
+    _check(load().zset_enumerate_ex(n, g.ctypes.data_as(_u32p), d, ptr, cap, ctypes.byref(opts),
+                                    memo.handle if memo is not None else None,
+                                    ctypes.byref(rows_written), ctypes.byref(csum),
+                                    ctypes.byref(stats)), "zset_enumerate_ex")
+    r = int(rows_written.value)
+    view = out[:r] if (out is not None and out.dim() == 2) else out
+    return Result(rows=r, checksum=int(csum.value), stats=stats.as_dict(), out=view)
+
+
+def enumerate(n: int, gens, out=None):
+    """Z(n; g) through the plain zset_enumerate (default options, null stream)."""
+    import torch
+    g = _gens(gens)
+    d = len(g)
+    rows = count(n, g)
+    if out is None:
+        out = torch.empty((max(rows, 1), d), dtype=torch.int32, device="cuda")
+    _check(load().zset_enumerate(n, g.ctypes.data_as(_u32p), d, out.data_ptr()),
+           "zset_enumerate")
+    return out[:rows]

@@ -1,0 +1,256 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Integer work: every comparison is bit-exact.  Small cases span several slices
+and a ragged last slice (rows_per_tile = 128); the full-size case is the
+large single enumeration in the launch configuration the benchmark times.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_20474_amd import inputs
+from paper_2407_20474_amd import zset
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_rows(n, g, **kw):
+    say(f"  enumerate_ex n={n} g={list(g)} {kw}")
+    r = zset.enumerate_ex(n, g, **kw)
+    if r.rows == 0:
+        return np.zeros((0, len(g)), np.uint32), r
+    host = r.out[: r.rows].cpu().numpy().view(np.uint32).reshape(r.rows, len(g))
+    return host, r
+
+
+def assert_same(got, want, what):
+    assert got.shape == want.shape, (what, got.shape, want.shape)
+    if not np.array_equal(got, want):
+        bad = np.nonzero((got != want).any(axis=1))[0]
+        i = int(bad[0])
+        raise AssertionError(f"{what}: {len(bad)} rows differ, first at {i}: "
+                             f"got {got[i].tolist()} want {want[i].tolist()}")
+
+
+# --------------------------------------------------------------------------
+# Counting pass
+# --------------------------------------------------------------------------
+
+def test_count_table_matches_oracle():
+    rng = np.random.default_rng(11)
+    cases = [(2000, [7, 11, 13, 17]), (10130, [13, 34, 37, 54, 65, 83]), (0, [5]),
+             (3000, [1, 1, 2]), (500, [600, 7, 3])]
+    for _ in range(20):
+        cases.append(inputs.random_small_query(rng, nmax=3000))
+    for n, g in cases:
+        say(f"count_table n={n} g={g}")
+        t = zset.count_table(n, g).cpu().numpy().view(np.uint64)
+        want = oracle.count_table(n, g)
+        assert np.array_equal(t, want), (n, g)
+        assert zset.count(n, g) == int(want[0, n])
+
+
+def test_count_overflow_is_reported():
+    say("count overflow: 32 generators equal to 1, n = 100000")
+    with pytest.raises(zset.ZsetError) as e:
+        zset.count(100000, [1] * 32)
+    assert e.value.status == zset.EOVERFLOW
+
+
+# --------------------------------------------------------------------------
+# Enumeration: small and medium cases, every memo dimension
+# --------------------------------------------------------------------------
+
+def test_plain_config_every_k_and_slice_size():
+    w = inputs.load_workloads()["plain"]
+    n, g = w["n"], w["gens"]
+    want = oracle.enumerate_rows(n, g)
+    assert len(want) == 81205
+    for k in range(len(g)):
+        for rpt in (128, 256, 1280, 0):
+            got, r = gpu_rows(n, g, k=k, rows_per_tile=rpt)
+            assert r.stats["k"] == k
+            assert_same(got, want, f"plain k={k} rows_per_tile={rpt}")
+
+
+def test_plain_entry_point():
+    say("zset_enumerate (plain entry point) on (7, 11, 13, 17), n = 2000")
+    out = zset.enumerate(2000, [7, 11, 13, 17])
+    got = out.cpu().numpy().view(np.uint32)
+    assert_same(got, oracle.enumerate_rows(2000, [7, 11, 13, 17]), "zset_enumerate")
+
+
+def test_random_small_queries_every_k():
+    rng = np.random.default_rng(12)
+    for _ in range(60):
+        n, g = inputs.random_small_query(rng, dmax=6, gmax=30, nmax=300)
+        want = oracle.enumerate_rows(n, g)
+        for k in range(len(g)):
+            got, _ = gpu_rows(n, g, k=k, rows_per_tile=128)
+            assert_same(got, want, f"n={n} g={g} k={k}")
+
+
+@pytest.mark.parametrize("n,g", [
+    (0, [5]), (0, [3, 7, 9]), (35, [5]), (36, [5]),        # n = 0 and d = 1
+    (101, [4, 6, 10]),                                       # gcd does not divide n: empty
+    (7 * 11 - 7 - 11, [7, 11]),                              # Frobenius number: empty
+    (5000, [7, 11]), (40, [50, 60, 3]),                      # d = 2; generators above n
+    (60, [1, 1, 1, 1]), (200, [2, 2, 3, 3, 5]),             # repeated generators
+    (1000, [17, 5, 11, 3]),                                  # unsorted
+    (3000, [3, 5, 7, 11, 13, 17]),                           # k = d - 1: one segment
+])
+def test_edge_cases(n, g):
+    want = oracle.enumerate_rows(n, g)
+    for k in range(len(g)):
+        got, r = gpu_rows(n, g, k=k, rows_per_tile=128)
+        assert r.rows == len(want)
+        assert_same(got, want, f"edge n={n} g={g} k={k}")
+
+
+def test_medium_cases_default_slices():
+    for n, g in [(5000, [13, 37, 38, 40]), (1000, [13, 37, 38, 40, 41, 42, 43]),
+                 (700, [10, 12, 14, 16, 19]), (20000, [3, 5, 7])]:
+        want = oracle.enumerate_rows(n, g)
+        for k in range(len(g)):
+            got, _ = gpu_rows(n, g, k=k)
+            assert_same(got, want, f"medium n={n} g={g} k={k}")
+
+
+def test_descending_order_is_the_reversal():
+    n, g = 2000, [7, 11, 13, 17]
+    want = oracle.enumerate_rows(n, g)[::-1]
+    for k in (0, 2):
+        got, _ = gpu_rows(n, g, k=k, order=1, rows_per_tile=256)
+        assert_same(got, np.ascontiguousarray(want), f"descending k={k}")
+
+
+def test_count_only_checksum():
+    rng = np.random.default_rng(13)
+    cases = [(2000, [7, 11, 13, 17]), (5000, [13, 37, 38, 40]), (0, [4, 6]), (35, [5])]
+    for _ in range(10):
+        cases.append(inputs.random_small_query(rng, dmax=5, gmax=20, nmax=200))
+    for n, g in cases:
+        rows = oracle.enumerate_rows(n, g)
+        want = oracle.checksum(rows)
+        for k in range(len(g)):
+            for rpt in (128, 0):
+                say(f"count_only n={n} g={g} k={k} rows_per_tile={rpt}")
+                r = zset.enumerate_ex(n, g, k=k, rows_per_tile=rpt, count_only=True)
+                assert r.rows == len(rows)
+                assert r.checksum == want, (n, g, k, rpt)
+
+
+# --------------------------------------------------------------------------
+# Memo build (the dynamic recurrence) and memo handles
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("path", ["lds", "global"])
+def test_memo_build_matches_oracle(path, monkeypatch):
+    monkeypatch.setenv("ZSET_MEMO_PATH", path)
+    for h, top in [([3, 5], 200), ([72, 75], 3000), ([4, 6, 9], 300), ([7], 100),
+                   ([2, 2], 50), ([9, 4, 6], 400), ([13, 37, 38], 2000), ([1], 10),
+                   ([5, 3, 2, 7], 150)]:
+        say(f"memo_build h={h} top={top} path={path}")
+        m = zset.Memo(h, top)
+        off, rows = m.read()
+        want_off, want_rows = oracle.memo(h, top)
+        assert np.array_equal(off, want_off), (h, top)
+        assert np.array_equal(rows, want_rows), (h, top)
+        m.free()
+
+
+def test_memo_handle_gives_the_same_rows():
+    n, g = 2000, [7, 11, 13, 17]
+    want = oracle.enumerate_rows(n, g)
+    for k in (1, 2, 3):
+        for top in (n + 1, n + 500):
+            say(f"memo handle k={k} top={top}")
+            m = zset.Memo(g[len(g) - k:], top)
+            got, r = gpu_rows(n, g, memo=m, rows_per_tile=256)
+            assert r.stats["k"] == k and r.stats["memo_us"] == 0
+            assert_same(got, want, f"memo handle k={k} top={top}")
+            m.free()
+
+
+# --------------------------------------------------------------------------
+# Errors reported on the GPU side
+# --------------------------------------------------------------------------
+
+def test_errors():
+    g = [7, 11, 13, 17]
+    say("ECAPACITY: out holds one row too few")
+    out = torch.empty((81204, 4), dtype=torch.int32, device="cuda")
+    with pytest.raises(zset.ZsetError) as e:
+        zset.enumerate_ex(2000, g, out=out)
+    assert e.value.status == zset.ECAPACITY
+    say("EINVAL: memo generators differ from the trailing generators")
+    m = zset.Memo([13, 16], 3000)
+    with pytest.raises(zset.ZsetError) as e:
+        zset.enumerate_ex(2000, g, memo=m)
+    assert e.value.status == zset.EINVAL
+    m.free()
+    say("EINVAL: memo top does not exceed n")
+    m = zset.Memo([13, 17], 2000)
+    with pytest.raises(zset.ZsetError) as e:
+        zset.enumerate_ex(2000, g, memo=m)
+    assert e.value.status == zset.EINVAL
+    m.free()
+    say("EINVAL: out is host memory")
+    host = np.zeros(81205 * 4, dtype=np.int32)
+    import ctypes
+    lib = zset.load()
+    gg = np.asarray(g, dtype=np.uint32)
+    st = lib.zset_enumerate(2000, gg.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 4,
+                            host.ctypes.data)
+    assert st == zset.EINVAL
+    assert not host.any()
+
+
+def test_alloc_fault_is_reported(monkeypatch):
+    say("ENOMEM: ZSET_FAULT=alloc on a memo build")
+    monkeypatch.setenv("ZSET_FAULT", "alloc")
+    with pytest.raises(zset.ZsetError) as e:
+        zset.Memo([7, 9], 500)
+    assert e.value.status == zset.ENOMEM
+
+
+# --------------------------------------------------------------------------
+# Full size: the large single enumeration, as the benchmark runs it
+# --------------------------------------------------------------------------
+
+def test_large_config_full_size_bit_exact():
+    w = inputs.load_workloads()["large"][0]
+    n, g, k = w["n"], w["gens"], w["k"]
+    rows = w["rows"]
+    say(f"large: n={n} g={g} k={k} rows={rows}: oracle (threads)")
+    table = oracle.count_table(n, g)
+    want = np.empty((rows, len(g)), dtype=np.uint32)
+    nthreads = min(16, os.cpu_count() or 1)
+    _, got_rows = oracle.enumerate_rows_threads(n, g, 0, n // g[0] + 1, nthreads,
+                                                table=table, out=want)
+    assert got_rows == rows
+    say("large: GPU enumerate (default slices, k=2)")
+    out = torch.empty((rows, len(g)), dtype=torch.int32, device="cuda")
+    r = zset.enumerate_ex(n, g, out=out, k=k)
+    assert r.rows == rows
+    chunk = 20_000_000
+    for s in range(0, rows, chunk):
+        e = min(rows, s + chunk)
+        got = out[s:e].cpu().numpy().view(np.uint32)
+        assert_same(got, want[s:e], f"large rows [{s}, {e})")
+    say("large: count-only checksum")
+    c = zset.enumerate_ex(n, g, k=k, count_only=True)
+    assert c.rows == rows
+    assert c.checksum == oracle.checksum(want)
+    del out
+    torch.cuda.empty_cache()
