@@ -81,9 +81,9 @@ struct Ctx {
 std::mutex g_mu;
 std::map<int, Ctx*> g_ctx;
 
-// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..] row sums
+// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..34] row sums
 constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2;
-constexpr size_t kMiscWords = 2 + kMaxD + 2;
+constexpr size_t kMiscWords = kMiscRowSums + kMaxD + 1;
 constexpr size_t kPinnedWords = 64;
 
 zset_status get_ctx(Ctx** out) {
@@ -159,6 +159,16 @@ float elapsed_us(hipEvent_t a, hipEvent_t b) {
     return 0.f;
   }
   return ms * 1000.f;
+}
+
+int max_lds_bytes(Ctx* c) {
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return v;
 }
 
 uint32_t next_pow2(uint32_t v) {
@@ -456,6 +466,9 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     P.checksum = misc + kMiscSum;
     P.out = out;
     P.dG = DivMod32::make(G);
+    P.ring = d <= 16 ? 128 : 64;
+    P.flush = P.ring / 2;
+    P.max_tiles = uint32_t(std::min(512, std::max(16, 4096 / (U + 2))));
 
     // 3. Memo (k >= 1): natural-order rows, then the leaf-order layout.
     ZSET_HIP(hipEventRecord(c->ev[2], s));
@@ -478,31 +491,81 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         off = o;
         nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       }
+      // Leaf-order row format: fields floor(p / G) <= n / G and m_c <= n / h_c,
+      // packed into one 32- or 64-bit word when they fit, and then copied to
+      // LDS by the write pass when that fits too.
+      uint32_t shift = 0;
+      for (int c2 = 0; c2 <= k; ++c2) {
+        const uint32_t vmax = uint32_t(n / gens[U + c2]);
+        uint32_t bits = 0;
+        while (bits < 32 && (uint64_t(vmax) >> bits) != 0) ++bits;
+        P.fshift[c2] = shift;
+        P.fmask[c2] = bits >= 32 ? ~0u : ((1u << bits) - 1u);
+        shift += bits;
+      }
+      P.pack = shift <= 32 ? 1 : (shift <= 64 ? 2 : 0);
+      P.nclass = uint32_t(std::min<uint64_t>(G, N));
+      const char* lds_env = std::getenv("ZSET_MEMO_LDS");
+      const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
+      const size_t lds_max = size_t(max_lds_bytes(c));
+      if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
+      if (P.pack != 0) {
+        P.memo_words = Rn * uint64_t(P.pack);
+        if (write_lds_bytes(P) > lds_max) P.pack = 0;
+      }
+      if (P.pack == 0) P.memo_words = 0;
+      // Segment counts and class ends in LDS too when every value fits 32 bits
+      // (their sum over x <= n bounds each) and the space is there.
+      if (!lds_off && sums[U] < (uint64_t(1) << 32) && Rn < (uint64_t(1) << 32)) {
+        P.lds_cnt = 1;
+        if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
+      }
+      const uint64_t leaf_words = P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
       const uint64_t nclass_max = std::min<uint64_t>(G, N);
       if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
-      if ((st = ensure(c->leaf, size_t(Rn) * (k + 1) * sizeof(uint32_t))) != ZSET_OK) return st;
+      if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
       uint32_t nclass = 0;
       uint64_t* endc = reinterpret_cast<uint64_t*>(c->endc.p);
       ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, endc, &nclass, s));
       uint32_t* leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
-      ZSET_HIP(launch_memo_leaf(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, err, s));
+      ZSET_HIP(launch_memo_leaf(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, P, err, s));
       P.endc = endc;
       P.leaf = leaf;
       P.leaf_rows = Rn;
-      memo_bytes = Rn * (k + 1) * 4;
+      memo_bytes = leaf_words * 4;
     }
     ZSET_HIP(hipEventRecord(c->ev[3], s));
 
-    // 4. Slices: exact rank ranges, starts unranked on the device.
+    // 4. Slices: exact rank ranges, starts unranked on the device.  Slice t
+    // goes to workgroup t mod NB of a grid sized to what stays resident; about
+    // 24 slices per wavefront by default, handed out dynamically inside each
+    // workgroup.
+    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    int cus = 0, per_cu = 0;
+    ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    ZSET_HIP(write_occupancy(P, count_only, align16, &per_cu));
+    if (per_cu < 1) return fail(ZSET_EDEVICE, "the write pass does not fit on a compute unit");
+    const uint64_t wpb = uint64_t(write_waves_per_block());
+    const uint64_t resident_waves = uint64_t(cus) * per_cu * wpb;
     T_rows = opts.rows_per_tile;
     if (T_rows == 0) {
-      const uint64_t want_tiles = 16384;
+      const uint64_t want_tiles = resident_waves * 24;
       T_rows = (total + want_tiles - 1) / want_tiles;
       T_rows = (T_rows + 127) / 128 * 128;
       T_rows = std::max<uint64_t>(T_rows, 128);
-      T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 20);
+      T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 30);
     }
     ntiles = (total + T_rows - 1) / T_rows;
+    if (ntiles > 0xffffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+    {
+      uint64_t blocks = uint64_t(cus) * per_cu;
+      const uint64_t min_blocks = (ntiles + P.max_tiles - 1) / P.max_tiles;
+      const uint64_t max_blocks = (ntiles + wpb - 1) / wpb;
+      blocks = std::max(blocks, min_blocks);
+      blocks = std::min(blocks, max_blocks);
+      if (blocks > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+      P.write_blocks = uint32_t(std::max<uint64_t>(blocks, 1));
+    }
     P.rows_per_tile = T_rows;
     P.ntiles = ntiles;
     if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
@@ -511,7 +574,6 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     ZSET_HIP(hipEventRecord(c->ev[4], s));
 
     // 5. Write (or count-only) pass.
-    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     ZSET_HIP(launch_write(P, count_only, align16, s));
   } else {
     ZSET_HIP(hipEventRecord(c->ev[2], s));

@@ -12,20 +12,30 @@
 // number C[j][x] - C[j][x - A g_j], a nondecreasing function of A that is
 // bisected.
 //
-// k_write: one wavefront per slice.  The first U-1 coordinates are the outer
-// prefix, kept lane-distributed (lane j holds a_j) and advanced by an odometer
-// in ascending lex order (Alg 3.1's successor, mirrored).  Coordinate U-1 is
-// spread across the 64 lanes.  Then:
+// k_write runs a persistent grid: slice t belongs to workgroup t mod NB.  In a
+// prologue each workgroup copies the packed leaf-order memo (memo.hip), the
+// segment counts and class ends (when they fit) and the start states of its
+// slices into LDS; its wavefronts then take the slices one at a time from an
+// LDS counter, so the load balances within the workgroup while no global load
+// is issued after the prologue -- only LDS traffic and the coalesced stores
+// of the output.  Within a slice the first U-1
+// coordinates are the outer prefix, kept lane-distributed (lane j holds a_j)
+// and advanced by an odometer in ascending lex order (Alg 3.1's successor,
+// mirrored).  Coordinate U-1 is spread across the 64 lanes.  Then:
 //  * k = 0 (MODE 0, Alg 3.1): the last coordinate is solved by division; each
 //    lane is a candidate giving 0 or 1 row; a ballot plus mbcnt gives each
 //    valid lane its output row.
 //  * k >= 1 (MODE 1, Alg 3.2): each lane owns the segment of rows sharing its
-//    prefix, which is one contiguous run of the leaf-order memo (memo.hip) of
-//    length C[U][x].  A wave prefix sum of the segment lengths gives row
-//    offsets; rows are then produced 64 at a time, each lane finding its
-//    segment by bisection over the prefix sums and copying one memo row.
-// Rows are staged in a per-wave LDS ring and written to HBM 128 rows at a time
-// with 16-byte stores, so the global stores are fully coalesced for any d.
+//    prefix, one contiguous run of the leaf-order memo of length C[U][x].  A
+//    wave prefix sum of the segment lengths gives row offsets; rows are then
+//    produced 64 at a time: segment starts are marked in LDS and a wave
+//    prefix-max gives every row lane its segment, and each lane copies one
+//    memo row.
+// Rows are staged in a per-wave LDS ring and written to HBM `flush` rows at a
+// time with 16-byte stores, so the global stores are fully coalesced for any
+// d.  Loads and stores share one wait counter on this GPU, so a global load
+// issued after stores waits for all of them to reach memory; keeping every
+// load in the prologue is what lets the stores stream.
 // In count-only mode no row is stored: each row's FNV-1a-64 (rank, row) hash is
 // summed instead.
 #include "zset_internal.h"
@@ -34,8 +44,7 @@ namespace zset {
 
 namespace {
 
-constexpr uint32_t kRingRows = 256;   // rows per wave in the LDS ring
-constexpr uint32_t kFlushRows = 128;  // rows per coalesced flush
+constexpr int kWriteWaves = 16;  // wavefronts per workgroup of the write pass
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -54,6 +63,35 @@ __device__ inline uint32_t mbcnt64(uint64_t mask) {
 
 __device__ inline uint32_t readlane_u32(uint32_t v, int l) {
   return __builtin_amdgcn_readlane(v, l);
+}
+
+// DPP move with lanes outside the pattern reading `identity`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline uint32_t dpp_u32(uint32_t v, uint32_t identity) {
+  return uint32_t(__builtin_amdgcn_update_dpp(int(identity), int(v), CTRL, ROW_MASK, 0xf, false));
+}
+
+// Inclusive prefix max over the wave: row_shr 1/2/4/8 inside each 16-lane
+// row, then row_bcast 15 and 31 across rows.
+__device__ inline uint32_t wave_incl_max(uint32_t v) {
+  v = max(v, dpp_u32<0x111>(v, 0u));
+  v = max(v, dpp_u32<0x112>(v, 0u));
+  v = max(v, dpp_u32<0x114>(v, 0u));
+  v = max(v, dpp_u32<0x118>(v, 0u));
+  v = max(v, dpp_u32<0x142, 0xa>(v, 0u));
+  v = max(v, dpp_u32<0x143, 0xc>(v, 0u));
+  return v;
+}
+
+// Inclusive prefix sum over the wave, saturated at cap (cap < 2^31).
+__device__ inline uint32_t wave_incl_sum_sat(uint32_t v, uint32_t cap) {
+  v = min(v + dpp_u32<0x111>(v, 0u), cap);
+  v = min(v + dpp_u32<0x112>(v, 0u), cap);
+  v = min(v + dpp_u32<0x114>(v, 0u), cap);
+  v = min(v + dpp_u32<0x118>(v, 0u), cap);
+  v = min(v + dpp_u32<0x142, 0xa>(v, 0u), cap);
+  v = min(v + dpp_u32<0x143, 0xc>(v, 0u), cap);
+  return v;
 }
 
 // Slice start: first U coordinates and the offset t0 inside their block.
@@ -84,10 +122,10 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
 }
 
 template <bool ALIGN16>
-__device__ inline void flush_rows(const uint32_t* stage, uint32_t slot0, uint32_t rows, int d,
+__device__ inline void flush_rows(const uint32_t* ring, uint32_t slot0, uint32_t rows, int d,
                                   uint32_t* out_rows) {
   const uint32_t nd = rows * uint32_t(d);
-  const uint32_t* src = stage + slot0 * uint32_t(d);
+  const uint32_t* src = ring + slot0 * uint32_t(d);
   const int lane = lane_id();
   if (ALIGN16) {
     const uint32_t nd4 = nd & ~3u;
@@ -101,219 +139,324 @@ __device__ inline void flush_rows(const uint32_t* stage, uint32_t slot0, uint32_
   }
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16>
-__global__ __launch_bounds__(256) void k_write(EnumParams P) {
-  extern __shared__ uint32_t stage_all[];
+// Memo row access: PACK 1 = one packed 32-bit word in LDS, PACK 2 = one packed
+// 64-bit word in LDS, PACK 0 = k+1 plain words in global memory.  Field c is
+// (word >> shift_c) & mask_c; shifts and masks live in lanes 0..k of fsh/fmk.
+template <int PACK>
+struct MemoRow {
+  uint64_t w;
+  const uint32_t* g;
+  __device__ inline void load(const uint32_t* lds_memo, const uint32_t* leaf, uint64_t row,
+                              int k) {
+    if (PACK == 1) {
+      w = lds_memo[row];
+    } else if (PACK == 2) {
+      w = reinterpret_cast<const uint64_t*>(lds_memo)[row];
+    } else {
+      g = leaf + row * uint64_t(k + 1);
+    }
+  }
+  __device__ inline uint32_t field(uint32_t fsh, uint32_t fmk, int c) const {
+    if (PACK == 0) return g[c];
+    return uint32_t(w >> readlane_u32(fsh, c)) & readlane_u32(fmk, c);
+  }
+};
+
+__host__ __device__ inline uint64_t align4(uint64_t words) { return (words + 3) & ~uint64_t(3); }
+
+// LDS words of one workgroup of the write pass: packed memo, segment counts and
+// class ends (LDSCNT), the start states of the workgroup's slices, then per
+// wavefront its staging ring and 64 marks.
+__host__ __device__ inline uint64_t write_wave_words(const EnumParams& P) {
+  return uint64_t(P.ring) * P.d + kWave;
+}
+__host__ __device__ inline uint64_t write_shared_words(const EnumParams& P) {
+  uint64_t w = align4(P.memo_words);
+  if (P.lds_cnt) w += align4(uint64_t(P.n) + 1) + align4(P.nclass);
+  w += align4(uint64_t(P.max_tiles) * (P.U + 2));
+  return w;
+}
+
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+__global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
+  extern __shared__ uint32_t lds[];
   const int lane = lane_id();
   const int wave = int(threadIdx.x / kWave);
-  const int waves = int(blockDim.x / kWave);
-  const uint64_t tile = uint64_t(blockIdx.x) * waves + wave;
-  if (tile >= P.ntiles) return;
-
   const int d = P.d, U = P.U, k = P.k;
   const uint64_t N = uint64_t(P.n) + 1;
-  uint32_t* stage = stage_all + size_t(wave) * kRingRows * d;
-  const uint64_t r0 = tile * P.rows_per_tile;
-  const uint64_t left = P.total - r0;
-  const uint32_t target = uint32_t(left < P.rows_per_tile ? left : P.rows_per_tile);
+  const uint32_t ring_rows = P.ring;
+  const uint32_t ring_mask = ring_rows - 1;
+  const uint32_t flush_rows_n = P.flush;
+  const uint32_t S = uint32_t(U + 2);  // words of one slice start
 
-  // Slice start, lane-distributed: lane j < U holds a_j and the remainder
-  // after coordinate j.
-  const uint32_t* st = P.tiles + tile * uint64_t(U + 2);
-  uint32_t aj = lane < U ? st[lane] : 0;
-  const uint32_t gj = lane < d ? P.g.g[lane] : 0;
-  const uint64_t t0 = uint64_t(st[U]) | (uint64_t(st[U + 1]) << 32);
-  uint32_t remj;
-  {
-    uint32_t ps = lane < U ? aj * gj : 0;  // every partial sum is <= n
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_up(ps, off, kWave);
-      if (lane >= off) ps += y;
+  // ---- Prologue: every global load of the kernel happens here, before the
+  // first store (a load issued after stores would wait for all of them).
+  const uint32_t* lds_memo = lds;
+  uint32_t* lds_cnt = lds + align4(P.memo_words);
+  uint32_t* lds_endc = lds_cnt + align4(N);
+  if (MODE == 1 && PACK > 0) {
+    const uint64_t nvec = P.memo_words / 4;
+    const uint4* src = reinterpret_cast<const uint4*>(P.leaf);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    const uint64_t stride = blockDim.x;
+    uint64_t i = threadIdx.x;
+    for (; i + 3 * stride < nvec; i += 4 * stride) {
+      const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], e = src[i + 3 * stride];
+      dst[i] = a;
+      dst[i + stride] = b;
+      dst[i + 2 * stride] = c;
+      dst[i + 3 * stride] = e;
     }
-    remj = P.n - ps;
+    for (; i < nvec; i += stride) dst[i] = src[i];
+    for (uint64_t w = nvec * 4 + threadIdx.x; w < P.memo_words; w += stride) lds[w] = P.leaf[w];
   }
+  if (MODE == 1 && LDSCNT) {
+    // Values fit 32 bits (checked by the host).
+    const uint64_t* cu = P.table + uint64_t(U) * N;
+    for (uint64_t x = threadIdx.x; x < N; x += blockDim.x) lds_cnt[x] = uint32_t(cu[x]);
+    for (uint32_t r = threadIdx.x; r < P.nclass; r += blockDim.x) lds_endc[r] = uint32_t(P.endc[r]);
+  }
+  // Slices of this workgroup: blockIdx.x, + gridDim.x, + 2 gridDim.x, ...  Their
+  // start states go to LDS; the wavefronts take them in turn from an LDS counter.
+  uint32_t* tstates =
+      lds + align4(P.memo_words) + (P.lds_cnt ? align4(N) + align4(P.nclass) : 0);
+  uint32_t* wbase = lds + write_shared_words(P) + size_t(wave) * write_wave_words(P);
+  uint32_t* ring = wbase;  // 16-byte aligned: every region above is a multiple of 4 words
+  uint32_t* marks = ring + ring_rows * d;
+  __shared__ uint32_t next_slot;
+  const uint64_t B = blockIdx.x, NB = gridDim.x;
+  uint32_t my_tiles = B < P.ntiles ? uint32_t((P.ntiles - B + NB - 1) / NB) : 0;
+  if (my_tiles > P.max_tiles) {  // the host sizes the grid so that this cannot happen
+    if (threadIdx.x == 0) set_error(P.err, kErrTileRows);
+    my_tiles = 0;
+  }
+  for (uint32_t i = threadIdx.x; i < my_tiles * S; i += blockDim.x) {
+    const uint32_t t = i / S, w = i - t * S;
+    tstates[i] = P.tiles[(B + uint64_t(t) * NB) * S + w];
+  }
+  if (threadIdx.x == 0) next_slot = 0;
+  const uint32_t gj = lane < d ? P.g.g[lane] : 0;
+  const uint32_t fsh = lane <= k ? P.fshift[lane] : 0;
+  const uint32_t fmk = lane <= k ? P.fmask[lane] : 0;
+  __syncthreads();
+
   const int nouter = U >= 1 ? U - 1 : 0;  // coordinates 0..U-2 form the outer prefix
-  uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
-  uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
   const uint32_t gseg = (U >= 1) ? P.g.g[U - 1] : 0;
   const uint64_t* cnt_row = P.table + uint64_t(U) * N;
-
-  uint32_t produced = 0, flushed = 0;
   uint64_t csum = 0;
-  bool first = true;
-  bool single_done = false;
-  uint32_t* out_tile = P.out + r0 * uint64_t(d);
 
-  while (produced < target) {
-    const uint32_t remaining = target - produced;
-    const uint32_t A = aseg + uint32_t(lane);
-    bool ok;
-    uint32_t xs;
-    if (U >= 1) {
-      const uint64_t ag = uint64_t(A) * gseg;
-      ok = ag <= xouter;
-      xs = ok ? xouter - uint32_t(ag) : 0;
-    } else {
-      ok = (lane == 0) && !single_done;
-      xs = P.n;
-    }
-    const uint32_t qx = P.dG.div(xs);
-    uint32_t tot;
+  for (;;) {
+    uint32_t slot_l = 0;
+    if (lane == 0) slot_l = atomicAdd(&next_slot, 1u);
+    const uint32_t ti = __builtin_amdgcn_readfirstlane(slot_l);
+    if (ti >= my_tiles) break;
+    const uint64_t tile = B + uint64_t(ti) * NB;
+    const uint64_t r0 = tile * P.rows_per_tile;
+    const uint64_t left = P.total - r0;
+    const uint32_t target = uint32_t(left < P.rows_per_tile ? left : P.rows_per_tile);
 
-    if (MODE == 0) {
-      const bool valid = ok && (P.dG.mod(xs, qx) == 0);
-      const uint64_t mask = ballot64(valid);
-      const uint32_t pos = mbcnt64(mask);
-      const uint32_t cnt = uint32_t(__popcll((unsigned long long)mask));
-      tot = cnt < remaining ? cnt : remaining;
-      if (valid && pos < tot) {
-        if (COUNT_ONLY) {
-          uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + pos);
-          for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
-          h = fnv1a_u32(h, A);
-          h = fnv1a_u32(h, qx);
-          csum += h;
-        } else {
-          uint32_t* row = stage + ((produced + pos) & (kRingRows - 1)) * uint32_t(d);
-          for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-          row[U - 1] = A;
-          row[U] = qx;
-        }
-      }
-      if (!COUNT_ONLY) {
-        wave_sync();
-        uint32_t written = produced + tot;
-        while (written - flushed >= kFlushRows) {
-          flush_rows<ALIGN16>(stage, flushed & (kRingRows - 1), kFlushRows, d,
-                              out_tile + uint64_t(flushed) * d);
-          flushed += kFlushRows;
-        }
-        wave_sync();
-      }
-    } else {
-      uint64_t c = ok ? cnt_row[xs] : 0;
-      const uint32_t rx = P.dG.mod(xs, qx);
-      uint64_t start = ok ? P.endc[rx] - c : 0;
-      if (first && lane == 0) {
-        if (t0 >= c) {  // the plan guarantees t0 < c; refuse to read past the segment
-          set_error(P.err, kErrUnrank);
-          c = 0;
-        } else {
-          start += t0;
-          c -= t0;
-        }
-      }
-      const uint32_t c32 = uint32_t(c < remaining ? c : remaining);
-      // Inclusive prefix sum saturated at `remaining`.
-      uint32_t incl = c32;
+    // Slice start, lane-distributed: lane j < U holds a_j and the remainder
+    // after coordinate j.
+    const uint32_t* st = tstates + ti * S;
+    uint32_t aj = lane < U ? st[lane] : 0;
+    const uint64_t t0 = uint64_t(st[U]) | (uint64_t(st[U + 1]) << 32);
+    uint32_t remj;
+    {
+      uint32_t ps = lane < U ? aj * gj : 0;  // every partial sum is <= n
 #pragma unroll
       for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off, kWave);
-        if (lane >= off) {
-          const uint32_t s = incl + y;
-          incl = s < remaining ? s : remaining;
-        }
+        const uint32_t y = __shfl_up(ps, off, kWave);
+        if (lane >= off) ps += y;
       }
-      const uint32_t up = __shfl_up(incl, 1, kWave);
-      const uint32_t excl = lane ? up : 0;
-      tot = readlane_u32(incl, kWave - 1);
-      const int ms = k + 1;
-      for (uint32_t beta = 0; beta < tot; beta += kWave) {
-        const uint32_t rho = beta + uint32_t(lane);
-        const bool act = rho < tot;
-        // Segment of this row: the number of lanes whose inclusive sum is <= rho.
-        int owner = 0;
-#pragma unroll
-        for (int step = 32; step >= 1; step >>= 1) {
-          const uint32_t v = __shfl(incl, owner + step - 1, kWave);
-          if (v <= rho) owner += step;
-        }
-        owner = owner < kWave ? owner : kWave - 1;
-        const uint32_t o_excl = __shfl(excl, owner, kWave);
-        const uint64_t o_start = __shfl(start, owner, kWave);
-        const uint32_t o_qx = __shfl(qx, owner, kWave);
-        const uint32_t o_A = aseg + uint32_t(owner);
-        const uint64_t mrow = o_start + (rho - o_excl);
-        if (act && mrow >= P.leaf_rows) {
-          set_error(P.err, kErrTileRows);
-        } else if (act) {
-          const uint32_t* mr = P.leaf + mrow * ms;
-          const uint32_t aU = o_qx - mr[0];
+      remj = P.n - ps;
+    }
+    uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
+    uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
+
+    uint32_t produced = 0, flushed = 0;
+    bool first = true;
+    bool single_done = false;
+    uint32_t* out_tile = P.out + r0 * uint64_t(d);
+
+    while (produced < target) {
+      const uint32_t remaining = target - produced;
+      const uint32_t A = aseg + uint32_t(lane);
+      bool ok;
+      uint32_t xs;
+      if (U >= 1) {
+        const uint64_t ag = uint64_t(A) * gseg;
+        ok = ag <= xouter;
+        xs = ok ? xouter - uint32_t(ag) : 0;
+      } else {
+        ok = (lane == 0) && !single_done;
+        xs = P.n;
+      }
+      const uint32_t qx = P.dG.div(xs);
+      uint32_t tot;
+
+      if (MODE == 0) {
+        const bool valid = ok && (P.dG.mod(xs, qx) == 0);
+        const uint64_t mask = ballot64(valid);
+        const uint32_t pos = mbcnt64(mask);
+        const uint32_t cnt = uint32_t(__popcll((unsigned long long)mask));
+        tot = cnt < remaining ? cnt : remaining;
+        if (valid && pos < tot) {
           if (COUNT_ONLY) {
-            uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
+            uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + pos);
             for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
-            if (U >= 1) h = fnv1a_u32(h, o_A);
-            h = fnv1a_u32(h, aU);
-            for (int c2 = 0; c2 < k; ++c2) h = fnv1a_u32(h, mr[1 + c2]);
+            h = fnv1a_u32(h, A);
+            h = fnv1a_u32(h, qx);
             csum += h;
           } else {
-            uint32_t* row = stage + ((produced + rho) & (kRingRows - 1)) * uint32_t(d);
+            uint32_t* row = ring + ((produced + pos) & ring_mask) * uint32_t(d);
             for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-            if (U >= 1) row[U - 1] = o_A;
-            row[U] = aU;
-            for (int c2 = 0; c2 < k; ++c2) row[U + 1 + c2] = mr[1 + c2];
+            row[U - 1] = A;
+            row[U] = qx;
           }
         }
         if (!COUNT_ONLY) {
           wave_sync();
-          const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
-          const uint32_t written = produced + beta + nrows;
-          while (written - flushed >= kFlushRows) {
-            flush_rows<ALIGN16>(stage, flushed & (kRingRows - 1), kFlushRows, d,
+          const uint32_t written = produced + tot;
+          while (written - flushed >= flush_rows_n) {
+            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
                                 out_tile + uint64_t(flushed) * d);
-            flushed += kFlushRows;
+            flushed += flush_rows_n;
           }
           wave_sync();
         }
+      } else {
+        const uint32_t rx = P.dG.mod(xs, qx);
+        uint64_t c, start;
+        if (LDSCNT) {
+          const uint32_t c32v = ok ? lds_cnt[xs] : 0;
+          c = c32v;
+          start = ok ? uint64_t(lds_endc[rx] - c32v) : 0;
+        } else {
+          c = ok ? cnt_row[xs] : 0;
+          start = ok ? P.endc[rx] - c : 0;
+        }
+        if (first && lane == 0) {
+          if (t0 >= c) {  // the plan guarantees t0 < c; refuse to read past the segment
+            set_error(P.err, kErrUnrank);
+            c = 0;
+          } else {
+            start += t0;
+            c -= t0;
+          }
+        }
+        const uint32_t c32 = uint32_t(c < remaining ? c : remaining);
+        const uint32_t incl = wave_incl_sum_sat(c32, remaining);
+        const uint32_t up = __shfl_up(incl, 1, kWave);
+        const uint32_t excl = lane ? up : 0;
+        tot = readlane_u32(incl, kWave - 1);
+        // Memo row of batch row rho is segbase[owner] + rho (wrapping arithmetic).
+        const uint64_t segbase = start - excl;
+        const uint32_t seg_lo = uint32_t(segbase), seg_hi = uint32_t(segbase >> 32);
+        uint32_t carry = 0;  // 1 + segment lane of the row just before this chunk
+        for (uint32_t beta = 0; beta < tot; beta += kWave) {
+          const uint32_t rho = beta + uint32_t(lane);
+          const bool act = rho < tot;
+          marks[lane] = 0;
+          wave_sync();
+          if (c32 != 0 && excl >= beta && excl - beta < uint32_t(kWave)) marks[excl - beta] = lane + 1;
+          wave_sync();
+          uint32_t m = wave_incl_max(marks[lane]);
+          m = max(m, carry);
+          carry = readlane_u32(m, kWave - 1);
+          const int owner = int(m) - 1;  // >= 0: row 0 of a batch always starts a segment
+          const uint32_t o_lo = __shfl(seg_lo, owner, kWave);
+          const uint32_t o_qx = __shfl(qx, owner, kWave);
+          uint64_t mrow;
+          if (PACK == 0) {
+            const uint32_t o_hi = __shfl(seg_hi, owner, kWave);
+            mrow = ((uint64_t(o_hi) << 32) | o_lo) + rho;
+          } else {
+            mrow = uint32_t(o_lo + rho);
+          }
+          const uint32_t o_A = aseg + uint32_t(owner);
+          if (act && mrow >= P.leaf_rows) {
+            set_error(P.err, kErrTileRows);
+          } else if (act) {
+            MemoRow<PACK> mr;
+            mr.load(lds_memo, P.leaf, mrow, k);
+            const uint32_t aU = o_qx - mr.field(fsh, fmk, 0);
+            if (COUNT_ONLY) {
+              uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
+              for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
+              if (U >= 1) h = fnv1a_u32(h, o_A);
+              h = fnv1a_u32(h, aU);
+              for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
+              csum += h;
+            } else {
+              uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
+              for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+              if (U >= 1) row[U - 1] = o_A;
+              row[U] = aU;
+              for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
+            }
+          }
+          wave_sync();
+          if (!COUNT_ONLY) {
+            const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
+            const uint32_t written = produced + beta + nrows;
+            while (written - flushed >= flush_rows_n) {
+              flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
+                                  out_tile + uint64_t(flushed) * d);
+              flushed += flush_rows_n;
+            }
+            wave_sync();
+          }
+        }
       }
+
+      produced += tot;
+      if (produced >= target) break;
+      first = false;
+      if (U == 0) {
+        if (single_done) break;
+        single_done = true;
+        continue;
+      }
+      if (uint64_t(aseg + kWave) * gseg <= xouter) {
+        aseg += kWave;
+        continue;
+      }
+      // Odometer: the rightmost outer coordinate that can still grow.
+      const bool can = lane < nouter && remj >= gj;
+      const uint64_t mask = ballot64(can);
+      if (mask == 0) {
+        if (lane == 0) set_error(P.err, kErrOdometer);
+        break;
+      }
+      const int js = 63 - __clzll((unsigned long long)mask);
+      if (lane == js) {
+        aj += 1;
+        remj -= gj;
+      }
+      const uint32_t nrem = readlane_u32(remj, js);
+      if (lane > js && lane < nouter) {
+        aj = 0;
+        remj = nrem;
+      }
+      xouter = nrem;
+      aseg = 0;
     }
 
-    produced += tot;
-    if (produced >= target) break;
-    first = false;
-    if (U == 0) {
-      if (single_done) break;
-      single_done = true;
-      continue;
-    }
-    if (uint64_t(aseg + kWave) * gseg <= xouter) {
-      aseg += kWave;
-      continue;
-    }
-    // Odometer: the rightmost outer coordinate that can still grow.
-    const bool can = lane < nouter && remj >= gj;
-    const uint64_t mask = ballot64(can);
-    if (mask == 0) {
-      if (lane == 0) set_error(P.err, kErrOdometer);
-      break;
-    }
-    const int js = 63 - __clzll((unsigned long long)mask);
-    if (lane == js) {
-      aj += 1;
-      remj -= gj;
-    }
-    const uint32_t nrem = readlane_u32(remj, js);
-    if (lane > js && lane < nouter) {
-      aj = 0;
-      remj = nrem;
-    }
-    xouter = nrem;
-    aseg = 0;
-  }
-
-  if (!COUNT_ONLY) {
-    if (produced > flushed) {
-      flush_rows<ALIGN16>(stage, flushed & (kRingRows - 1), produced - flushed, d,
+    if (!COUNT_ONLY && produced > flushed) {
+      flush_rows<ALIGN16>(ring, flushed & ring_mask, produced - flushed, d,
                           out_tile + uint64_t(flushed) * d);
     }
-  } else {
+    wave_sync();
+    if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
+  }
+
+  if (COUNT_ONLY) {
 #pragma unroll
     for (int off = kWave / 2; off >= 1; off >>= 1) csum += __shfl_xor(csum, off, kWave);
-    if (lane == 0) atomicAdd(reinterpret_cast<unsigned long long*>(P.checksum),
-                             static_cast<unsigned long long>(csum));
+    if (lane == 0 && csum != 0)
+      atomicAdd(reinterpret_cast<unsigned long long*>(P.checksum),
+                static_cast<unsigned long long>(csum));
   }
-  if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
 }
 
 // d = 1: Z(n; g_1) is {n / g_1} when g_1 divides n.
@@ -344,19 +487,76 @@ __global__ __launch_bounds__(256) void k_reverse_rows(uint32_t* out, uint64_t ro
   }
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16>
-hipError_t launch_write_t(const EnumParams& P, int waves, hipStream_t s) {
-  const uint64_t blocks = (P.ntiles + waves - 1) / waves;
-  const size_t lds = COUNT_ONLY ? 0 : size_t(waves) * kRingRows * P.d * sizeof(uint32_t);
-  hipLaunchKernelGGL((k_write<MODE, COUNT_ONLY, ALIGN16>), dim3(uint32_t(blocks)),
-                     dim3(waves * kWave), lds, s, P);
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+hipError_t launch_write_t(const EnumParams& P, hipStream_t s) {
+  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>;
+  const size_t lds = write_lds_bytes(P);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3(P.write_blocks), dim3(kWriteWaves * kWave), lds, s, P);
   return hipGetLastError();
 }
 
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+hipError_t occupancy_t(const EnumParams& P, int* per_cu) {
+  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>;
+  const size_t lds = write_lds_bytes(P);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, kWriteWaves * kWave, lds);
+}
+
+// Dispatch on the run-time choices to the matching instantiation.
+template <template <int, bool, bool, int, bool> class F, class... A>
+hipError_t dispatch(const EnumParams& P, bool count_only, bool align16, A... args) {
+  if (P.k == 0) {
+    if (count_only) return F<0, true, false, 0, false>::run(P, args...);
+    return align16 ? F<0, false, true, 0, false>::run(P, args...)
+                   : F<0, false, false, 0, false>::run(P, args...);
+  }
+#define ZSET_PACK_CASES(PK)                                                          \
+  if (P.lds_cnt) {                                                                   \
+    if (count_only) return F<1, true, false, PK, true>::run(P, args...);             \
+    return align16 ? F<1, false, true, PK, true>::run(P, args...)                    \
+                   : F<1, false, false, PK, true>::run(P, args...);                  \
+  }                                                                                  \
+  if (count_only) return F<1, true, false, PK, false>::run(P, args...);              \
+  return align16 ? F<1, false, true, PK, false>::run(P, args...)                     \
+                 : F<1, false, false, PK, false>::run(P, args...);
+  switch (P.pack) {
+    case 1: { ZSET_PACK_CASES(1) }
+    case 2: { ZSET_PACK_CASES(2) }
+    default: { ZSET_PACK_CASES(0) }
+  }
+#undef ZSET_PACK_CASES
+}
+
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+struct LaunchF {
+  static hipError_t run(const EnumParams& P, hipStream_t s) {
+    return launch_write_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(P, s);
+  }
+};
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+struct OccF {
+  static hipError_t run(const EnumParams& P, int* per_cu) {
+    return occupancy_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(P, per_cu);
+  }
+};
+
 }  // namespace
 
-uint32_t write_ring_rows() { return kRingRows; }
-uint32_t write_flush_rows() { return kFlushRows; }
+size_t write_lds_bytes(const EnumParams& P) {
+  return size_t(write_shared_words(P) + kWriteWaves * write_wave_words(P)) * sizeof(uint32_t);
+}
+
+int write_waves_per_block() { return kWriteWaves; }
+
+hipError_t write_occupancy(const EnumParams& P, bool count_only, bool align16, int* per_cu) {
+  return dispatch<OccF>(P, count_only, align16, per_cu);
+}
 
 hipError_t launch_plan(const EnumParams& P, hipStream_t s) {
   const uint64_t blocks = (P.ntiles + 255) / 256;
@@ -364,18 +564,8 @@ hipError_t launch_plan(const EnumParams& P, hipStream_t s) {
   return hipGetLastError();
 }
 
-int write_waves_per_block(int d) { return d <= 12 ? 4 : 2; }
-
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s) {
-  const int waves = write_waves_per_block(P.d);
-  if (P.k == 0) {
-    if (count_only) return launch_write_t<0, true, false>(P, waves, s);
-    return align16 ? launch_write_t<0, false, true>(P, waves, s)
-                   : launch_write_t<0, false, false>(P, waves, s);
-  }
-  if (count_only) return launch_write_t<1, true, false>(P, waves, s);
-  return align16 ? launch_write_t<1, false, true>(P, waves, s)
-                 : launch_write_t<1, false, false>(P, waves, s);
+  return dispatch<LaunchF>(P, count_only, align16, s);
 }
 
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,

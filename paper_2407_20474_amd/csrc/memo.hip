@@ -184,15 +184,16 @@ __global__ __launch_bounds__(256) void k_memo_batch(int k, const uint64_t* __res
 }
 
 // Natural order -> leaf order for p in [0, n]: row t of Memo[p] goes to
-// pos(p) + t with pos(p) = end[p mod G] - cu[p]; it is stored as
-// (floor(p / G), m_1..m_k).
+// pos(p) + t with pos(p) = end[p mod G] - cu[p]; it is stored as the fields
+// (floor(p / G), m_1..m_k): k+1 plain words (pack 0), or packed into one 32-
+// or 64-bit word at the bit offsets of the write pass (pack 1, 2).
 __global__ __launch_bounds__(256) void k_memo_leaf(int k, uint32_t n, DivMod32 dG,
                                                    const uint64_t* __restrict__ off,
                                                    const uint32_t* __restrict__ nat,
                                                    const uint64_t* __restrict__ cu,
                                                    const uint64_t* __restrict__ endc,
                                                    uint32_t* __restrict__ leaf,
-                                                   uint64_t leaf_rows,
+                                                   uint64_t leaf_rows, EnumParams P,
                                                    int* __restrict__ err) {
   const uint64_t p64 = uint64_t(blockIdx.x) * 256 + threadIdx.x;
   if (p64 > n) return;
@@ -206,11 +207,18 @@ __global__ __launch_bounds__(256) void k_memo_leaf(int k, uint32_t n, DivMod32 d
     set_error(err, kErrMemoTotal);
     return;
   }
-  const int ms = k + 1;
   for (uint64_t t = 0; t < cnt; ++t) {
-    uint32_t* dst = leaf + (pos + t) * ms;
-    dst[0] = q;
-    for (int c = 0; c < k; ++c) dst[1 + c] = nat[(o + t) * k + c];
+    const uint32_t* src = nat + (o + t) * k;
+    if (P.pack == 0) {
+      uint32_t* dst = leaf + (pos + t) * (k + 1);
+      dst[0] = q;
+      for (int c = 0; c < k; ++c) dst[1 + c] = src[c];
+    } else {
+      uint64_t w = uint64_t(q) << P.fshift[0];
+      for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << P.fshift[1 + c];
+      if (P.pack == 1) leaf[pos + t] = uint32_t(w);
+      else reinterpret_cast<uint64_t*>(leaf)[pos + t] = w;
+    }
   }
 }
 
@@ -255,10 +263,11 @@ hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b
 
 hipError_t launch_memo_leaf(int k, uint64_t n, uint32_t G, const uint64_t* off,
                             const uint32_t* nat, const uint64_t* cu, const uint64_t* endc,
-                            uint32_t* leaf, uint64_t leaf_rows, int* err, hipStream_t s) {
+                            uint32_t* leaf, uint64_t leaf_rows, const EnumParams& P, int* err,
+                            hipStream_t s) {
   const uint32_t blocks = uint32_t((n + 1 + 255) / 256);
   hipLaunchKernelGGL(k_memo_leaf, dim3(blocks), dim3(256), 0, s, k, uint32_t(n),
-                     DivMod32::make(G), off, nat, cu, endc, leaf, leaf_rows, err);
+                     DivMod32::make(G), off, nat, cu, endc, leaf, leaf_rows, P, err);
   return hipGetLastError();
 }
 

@@ -29,6 +29,17 @@ struct EnumParams {
   uint64_t* checksum;       // count-only: wrapping sum of row hashes
   int* err;                 // device status word
   DivMod32 dG;              // division by g_U
+  uint32_t ring;            // rows in each wavefront's LDS staging ring (power of two)
+  uint32_t flush;           // rows per coalesced flush (ring / 2)
+  int pack;                 // memo row format: 0 plain words in global, 1 / 2 packed
+                            // 32- / 64-bit words copied into LDS
+  uint64_t memo_words;      // uint32 words of packed memo copied into LDS (0 if pack == 0)
+  uint32_t fshift[kMaxD + 1];  // packed field c (0 = floor(p / G), c >= 1 = m_c): bit offset
+  uint32_t fmask[kMaxD + 1];   // and mask
+  int lds_cnt;              // 1: segment counts C[U][x] and class ends copied to LDS as uint32
+  uint32_t nclass;          // residue classes of the leaf layout: min(G, n + 1)
+  uint32_t max_tiles;       // slices one workgroup may own (their starts are held in LDS)
+  uint32_t write_blocks;    // workgroups of the write pass; slice t goes to workgroup t mod NB
 };
 
 // count_table.hip
@@ -52,12 +63,13 @@ hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);
 hipError_t launch_memo_leaf(int k, uint64_t n, uint32_t G, const uint64_t* off,
                             const uint32_t* nat, const uint64_t* cu, const uint64_t* endc,
-                            uint32_t* leaf, uint64_t leaf_rows, int* err, hipStream_t s);
+                            uint32_t* leaf, uint64_t leaf_rows, const EnumParams& P, int* err,
+                            hipStream_t s);
 
 // enumerate.hip
-uint32_t write_ring_rows();
-uint32_t write_flush_rows();
-int write_waves_per_block(int d);
+size_t write_lds_bytes(const EnumParams& P);
+int write_waves_per_block();
+hipError_t write_occupancy(const EnumParams& P, bool count_only, bool align16, int* per_cu);
 hipError_t launch_plan(const EnumParams& P, hipStream_t s);
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s);
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,
