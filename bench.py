@@ -36,6 +36,8 @@ def parse():
     ap.add_argument("--count-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=float, default=5e7)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -165,6 +167,15 @@ def main():
         "store_ceiling_gbs": ceiling,
         "roofline": roof,
     }
+    if args.calibrate:
+        # A plain copy kernel of known size: 1 GiB read + 1 GiB written (an
+        # elementwise kernel, so that it shows in the kernel counters).
+        src = torch.empty(1 << 28, dtype=torch.int32, device="cuda").fill_(7)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1, out=dst)
+        torch.cuda.synchronize()
+        line["calibration_copy_bytes"] = src.numel() * 4
+        del src, dst
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, g, args.cpu_sample_rows)
     print(json.dumps(line), flush=True)

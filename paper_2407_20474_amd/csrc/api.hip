@@ -16,8 +16,6 @@ namespace {
 
 // Count-table rows have n + 1 entries indexed in 32 bits on the device.
 constexpr uint64_t kMaxN = (uint64_t(1) << 31) - 2;
-// LDS a single workgroup may use for the memo chain.
-constexpr size_t kChainLdsBudget = 152 * 1024;
 
 thread_local std::string g_last_error;
 
@@ -177,10 +175,12 @@ uint32_t next_pow2(uint32_t v) {
   return p;
 }
 
-// Builds Memo[p] = Z(p; h) for p < top into nat (natural order).  `ge` holds
-// |Z(m; h_i..h_k)| for i = 0..k-1 (row stride ge_stride), `off` the natural
-// offsets (top + 1 entries), R = off[top].
-zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, const uint64_t* off,
+// Builds Memo[p] = Z(p; h) for p < top into nat (natural order) and the
+// natural offsets off[0..top].  `ge` holds |Z(m; h_i..h_k)| for i = 0..k-1
+// (row stride ge_stride) and `sizes` = ge row 0; R = the total row count.
+// Memos that fit in LDS are built by one wavefront (k_memo_chain_wave), which
+// also writes the offsets; larger ones by the global schedule after a scan.
+zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint32_t* nat,
                             hipStream_t s) {
   uint32_t b = h[0], hmax = h[0];
@@ -190,14 +190,16 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, cons
   }
   const char* path = std::getenv("ZSET_MEMO_PATH");
   const bool force_global = path && std::strcmp(path, "global") == 0;
-  const uint64_t Wl = uint64_t(hmax) + b;
+  const uint32_t step = std::min<uint32_t>(b, kWave);
+  const uint64_t Wl = uint64_t(hmax) + step;
   const uint32_t W = Wl < (uint64_t(1) << 30) ? next_pow2(uint32_t(Wl)) : 0;
-  int* err = reinterpret_cast<int*>(c->misc.p) + 0;
-  if (!force_global && W != 0 && b <= 1024 && R < (uint64_t(1) << 30) &&
-      memo_chain_lds_bytes(k, R, W, b) <= kChainLdsBudget) {
-    ZSET_HIP(launch_memo_chain_lds(h, k, top, b, W, R, nat, err, s));
+  int* err = reinterpret_cast<int*>(c->misc.p);
+  if (!force_global && W != 0 && R < (uint64_t(1) << 30) &&
+      memo_wave_lds_bytes(k, R, W) <= size_t(max_lds_bytes(c))) {
+    ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, nat, off, err, s));
     return ZSET_OK;
   }
+  ZSET_HIP(launch_exclusive_scan(ge, top, off, s));
   zset_status st = ensure(c->srcw, size_t(R) * sizeof(uint64_t));
   if (st != ZSET_OK) return st;
   ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride,
@@ -253,7 +255,7 @@ zset_status zset_count(uint64_t n, const uint32_t* gens, int d, uint64_t* count)
   const uint64_t N = n + 1;
   if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
-  ZSET_HIP(launch_count_table(T, n, gens, d, nullptr));
+  ZSET_HIP(launch_count_table(T, n, gens, d, nullptr, nullptr));
   ZSET_HIP(hipMemcpyAsync(c->pinned, T + n, sizeof(uint64_t), hipMemcpyDeviceToHost, nullptr));
   ZSET_HIP(hipStreamSynchronize(nullptr));
   *count = c->pinned[0];
@@ -269,7 +271,7 @@ zset_status zset_count_table(uint64_t n, const uint32_t* gens, int d, uint64_t* 
   if (!table) return fail(ZSET_EINVAL, "table is NULL");
   if (!is_device_pointer(table)) return fail(ZSET_EINVAL, "table is not device memory");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  ZSET_HIP(launch_count_table(table, n, gens, d, s));
+  ZSET_HIP(launch_count_table(table, n, gens, d, nullptr, s));
   ZSET_HIP(hipStreamSynchronize(s));
   return ZSET_OK;
 }
@@ -292,7 +294,7 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   const uint64_t nm = top - 1;
   if ((st = ensure(c->hcount, size_t(k + 1) * top * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* CT = reinterpret_cast<uint64_t*>(c->hcount.p);
-  ZSET_HIP(launch_count_table(CT, nm, gens_trailing, k, s));
+  ZSET_HIP(launch_count_table(CT, nm, gens_trailing, k, nullptr, s));
   zset_memo m = new zset_memo_s();
   std::memset(m, 0, sizeof *m);
   m->k = k;
@@ -406,8 +408,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   // 1. Count table, row sums (memo sizes), total.
   ZSET_HIP(hipEventRecord(c->ev[0], s));
   ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
-  ZSET_HIP(launch_count_table(T, n, gens, d, s));
-  ZSET_HIP(launch_row_sums(T, n, d + 1, misc + kMiscRowSums, s));
+  ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
   ZSET_HIP(hipEventRecord(c->ev[1], s));
   ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 1) * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
@@ -484,7 +485,6 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
         if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
         uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
-        ZSET_HIP(launch_exclusive_scan(T + uint64_t(L) * N, N, o, s));
         st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn,
                              reinterpret_cast<uint32_t*>(c->nat.p), s);
         if (st != ZSET_OK) return st;

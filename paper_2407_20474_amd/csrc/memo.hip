@@ -16,9 +16,9 @@
 // work item (factorizationwise parallelism, Alg 2.9).
 //
 // Two schedules compute the same natural-order memo:
-//  * k_memo_chain_lds: one workgroup keeps the whole memo in LDS and saves the
-//    cardinalities |Z_{>=i}(p)| as it goes (Section 2.3), in a ring of the
-//    last W elements, so a batch costs a few LDS round trips.
+//  * k_memo_chain_wave: one wavefront keeps the whole memo in LDS and saves
+//    the cardinalities |Z_{>=i}(p)| as it goes (Section 2.3), in a ring of the
+//    last W elements, so a batch costs a few LDS round trips and no barrier.
 //  * k_memo_src + k_memo_batch: for memos larger than LDS, every destination
 //    row's source is precomputed in parallel from the count table, then one
 //    multi-workgroup launch per batch copies rows in global memory.
@@ -36,101 +36,121 @@ namespace zset {
 
 namespace {
 
-constexpr int kChainThreads = 1024;
-
-__device__ inline uint32_t block_exclusive_scan_u32(uint32_t v, uint32_t* wsum, uint32_t* total) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wave = threadIdx.x / kWave;
-  uint32_t incl = v;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const uint32_t y = __shfl_up(incl, off, kWave);
-    if (lane >= off) incl += y;
-  }
-  if (lane == kWave - 1) wsum[wave] = incl;
-  __syncthreads();
-  if (wave == 0) {
-    const int nw = kChainThreads / kWave;
-    uint32_t w = lane < nw ? wsum[lane] : 0;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_up(w, off, kWave);
-      if (lane >= off) w += y;
-    }
-    if (lane < nw) wsum[lane] = w;
-  }
-  __syncthreads();
-  const uint32_t before = wave ? wsum[wave - 1] : 0;
-  *total = wsum[kChainThreads / kWave - 1];
-  __syncthreads();
-  return before + incl - v;
+// Inclusive prefix sum over the 64 lanes with DPP (row_shr within 16-lane
+// rows, then row_bcast 15 / 31 across rows): no LDS round trip.
+__device__ inline uint32_t wave_incl_sum_u32(uint32_t v) {
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xf, 0xf, false));
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xf, 0xf, false));
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xf, 0xf, false));
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xf, 0xf, false));
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xa, 0xf, false));
+  v += uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xc, 0xf, false));
+  return v;
 }
 
-// Whole memo in LDS.  Dynamic LDS layout (uint32): M[R*k] | GE[W*k] | OFF[W] | S[b*k].
-// Requires b <= kChainThreads, W a power of two >= max(h) + b, and
-// R*k + W*(k+1) + b*k words of LDS.
-__global__ __launch_bounds__(kChainThreads) void k_memo_chain_lds(Gens h, int k, uint32_t top,
-                                                                  uint32_t b, uint32_t W,
-                                                                  uint32_t R,
-                                                                  uint32_t* __restrict__ nat,
-                                                                  int* __restrict__ err) {
+// One wavefront, no barriers: the schedule for memos that fit in LDS.  Steps
+// take `step` = min(64, min(h)) consecutive elements, one per lane; a step
+// never reads an element of its own (p - h_i < x0), so steps are the paper's
+// elementwise batches cut to the wave width.  The cardinalities
+// |Z_{>=i}(p)| are saved as they are computed (Section 2.3), in a ring GE of
+// the last W elements, with the start OFF of each list; a wave prefix sum of
+// the list sizes gives each element its output location, and each lane then
+// copies-and-increments its element's source blocks.  The natural offsets are
+// written to off_out as they are found.
+// Dynamic LDS layout (uint32): M[R*k] | GE[W*k] | OFF[W]; W a power of two
+// >= max(h) + step.
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32_t top,
+                                                            uint32_t step, uint32_t W,
+                                                            uint32_t R,
+                                                            uint32_t* __restrict__ nat,
+                                                            uint64_t* __restrict__ off_out,
+                                                            int* __restrict__ err) {
   extern __shared__ uint32_t lds[];
-  __shared__ uint32_t wsum[kChainThreads / kWave];
   uint32_t* M = lds;
   uint32_t* GE = M + size_t(R) * k;
   uint32_t* OFF = GE + size_t(W) * k;
-  uint32_t* S = OFF + W;
-  const int tid = threadIdx.x;
+  const uint32_t lane = threadIdx.x;
+  const uint32_t Wm = W - 1;
 
   // Z(0) = [0]: one all-zero row, and |Z_{>=i}(0)| = 1 for every i.
-  if (tid < k) {
-    M[tid] = 0;
-    GE[tid] = 1;
+  if (lane < uint32_t(k)) {
+    M[lane] = 0;
+    GE[lane] = 1;
   }
-  if (tid == 0) OFF[0] = 0;
+  if (lane == 0) {
+    OFF[0] = 0;
+    off_out[0] = 0;
+  }
   uint32_t running = 1;
-  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-  for (uint32_t x0 = 1; x0 < top; x0 += b) {
-    const uint32_t nb = (top - x0 < b) ? top - x0 : b;
-    // Phase A: block sizes |Z_{=i}(p)| = |Z_{>=i}(p - h_i)| and the saved
-    // cardinalities |Z_{>=i}(p)| (suffix sums over i).
-    uint32_t size = 0;
-    uint32_t p = x0 + tid;
-    if (uint32_t(tid) < nb) {
-      uint32_t acc = 0;
-      for (int i = k - 1; i >= 0; --i) {
-        const uint32_t s = (p >= h.g[i]) ? GE[((p - h.g[i]) & (W - 1)) * k + i] : 0;
-        S[tid * k + i] = s;
-        acc += s;
-        GE[(p & (W - 1)) * k + i] = acc;
-      }
-      size = acc;
-    }
-    uint32_t total = 0;
-    const uint32_t excl = block_exclusive_scan_u32(size, wsum, &total);
-    if (uint32_t(tid) < nb) OFF[p & (W - 1)] = running + excl;
-    __syncthreads();
-    // Phase B: one work item per (element, block); copy-and-increment.
-    for (uint32_t pair = tid; pair < nb * uint32_t(k); pair += kChainThreads) {
-      const uint32_t t = pair / k;
-      const int i = int(pair % k);
-      const uint32_t s = S[t * k + i];
-      if (s == 0) continue;
-      const uint32_t pp = x0 + t;
-      const uint32_t src = OFF[(pp - h.g[i]) & (W - 1)];
-      uint32_t dst = OFF[pp & (W - 1)];
-      for (int i2 = k - 1; i2 > i; --i2) dst += S[t * k + i2];
-      for (uint32_t r = 0; r < s; ++r) {
-        for (int c = 0; c < k; ++c)
-          M[(dst + r) * k + c] = M[(src + r) * k + c] + (c == i ? 1u : 0u);
+  for (uint32_t x0 = 1; x0 < top; x0 += step) {
+    const uint32_t p = x0 + lane;
+    const bool valid = lane < step && p < top;
+    // |Z_{=i}(p)| = |Z_{>=i}(p - h_i)| and where Z(p - h_i) starts.
+    uint32_t s[KMAX], so[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      s[i] = 0;
+      so[i] = 0;
+      if (i < k && valid && p >= h.g[i]) {
+        const uint32_t slot = (p - h.g[i]) & Wm;
+        s[i] = GE[slot * k + i];
+        so[i] = OFF[slot];
       }
     }
-    running += total;
-    __syncthreads();
+    // Saved cardinalities: |Z_{>=i}(p)| = sum over i' >= i of |Z_{=i'}(p)|.
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; --i) {
+      if (i < k) {
+        acc += s[i];
+        if (valid) GE[(p & Wm) * k + i] = acc;
+      }
+    }
+    const uint32_t size = valid ? acc : 0;
+    const uint32_t incl = wave_incl_sum_u32(size);
+    const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
+    const uint32_t off_p = running + incl - size;
+    if (valid) {
+      OFF[p & Wm] = off_p;
+      off_out[p] = off_p;
+    }
+    // Copy-and-increment, blocks in ascending order i = k..1.
+    uint32_t dst = off_p;
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; --i) {
+      if (i < k) {
+        for (uint32_t r = 0; r < s[i]; ++r) {
+          uint32_t v[KMAX];
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c)
+            if (c < k) v[c] = M[(so[i] + r) * k + c];
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c)
+            if (c < k) M[(dst + r) * k + c] = v[c] + (c == i ? 1u : 0u);
+        }
+        dst += s[i];
+      }
+    }
+    running += tot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  if (tid == 0 && running != R) set_error(err, kErrMemoTotal);
-  for (uint32_t w = tid; w < R * uint32_t(k); w += kChainThreads) nat[w] = M[w];
+  if (lane == 0) {
+    off_out[top] = running;
+    if (running != R) set_error(err, kErrMemoTotal);
+  }
+  const uint32_t words = R * uint32_t(k);
+  const uint32_t nvec = words / 4;
+  const uint4* src = reinterpret_cast<const uint4*>(M);
+  uint4* dstv = reinterpret_cast<uint4*>(nat);
+  for (uint32_t v = lane; v < nvec; v += kWave) dstv[v] = src[v];
+  for (uint32_t w = nvec * 4 + lane; w < words; w += kWave) nat[w] = M[w];
 }
 
 // Sources of every destination row, from the count table.  Row j of Memo[p]
@@ -224,21 +244,28 @@ __global__ __launch_bounds__(256) void k_memo_leaf(int k, uint32_t n, DivMod32 d
 
 }  // namespace
 
-size_t memo_chain_lds_bytes(int k, uint64_t R, uint32_t W, uint32_t b) {
-  return (size_t(R) * k + size_t(W) * (k + 1) + size_t(b) * k) * sizeof(uint32_t);
+size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W) {
+  return (size_t(R) * k + size_t(W) * (k + 1)) * sizeof(uint32_t);
 }
 
-hipError_t launch_memo_chain_lds(const uint32_t* h, int k, uint64_t top, uint32_t b, uint32_t W,
-                                 uint64_t R, uint32_t* nat, int* err, hipStream_t s) {
+hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32_t step,
+                                  uint32_t W, uint64_t R, uint32_t* nat, uint64_t* off_out,
+                                  int* err, hipStream_t s) {
   Gens hg{};
   for (int i = 0; i < k; ++i) hg.g[i] = h[i];
-  const size_t lds = memo_chain_lds_bytes(k, R, W, b);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_memo_chain_lds),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_memo_chain_lds, dim3(1), dim3(kChainThreads), lds, s, hg, k,
-                     uint32_t(top), b, W, uint32_t(R), nat, err);
-  return hipGetLastError();
+  const size_t lds = memo_wave_lds_bytes(k, R, W);
+  auto go = [&](auto kern) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kWave), lds, s, hg, k, uint32_t(top), step, W,
+                       uint32_t(R), nat, off_out, err);
+    return hipGetLastError();
+  };
+  if (k <= 2) return go(k_memo_chain_wave<2>);
+  if (k <= 4) return go(k_memo_chain_wave<4>);
+  if (k <= 8) return go(k_memo_chain_wave<8>);
+  return go(k_memo_chain_wave<kMaxD>);
 }
 
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,

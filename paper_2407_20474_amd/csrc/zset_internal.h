@@ -43,10 +43,9 @@ struct EnumParams {
 };
 
 // count_table.hip
+// Count table (d+1) x (n+1); when sums is non-NULL also sums[j] = sum_x C[j][x].
 hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens, int d,
-                              hipStream_t s);
-hipError_t launch_row_sums(const uint64_t* table, uint64_t n, int rows, uint64_t* sums,
-                           hipStream_t s);
+                              uint64_t* sums, hipStream_t s);
 
 // scan.hip
 hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t count, uint64_t* out,
@@ -55,9 +54,10 @@ hipError_t launch_class_ends(const uint64_t* count_row_u, uint64_t n, uint32_t G
                              uint64_t* endc, uint32_t* nclass_out, hipStream_t s);
 
 // memo.hip
-size_t memo_chain_lds_bytes(int k, uint64_t R, uint32_t W, uint32_t b);
-hipError_t launch_memo_chain_lds(const uint32_t* h, int k, uint64_t top, uint32_t b, uint32_t W,
-                                 uint64_t R, uint32_t* nat, int* err, hipStream_t s);
+size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W);
+hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32_t step,
+                                  uint32_t W, uint64_t R, uint32_t* nat, uint64_t* off_out,
+                                  int* err, hipStream_t s);
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);
