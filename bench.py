@@ -21,6 +21,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E peak, GB/s
+COUNTERS = os.path.join(ROOT, "profiles", "write_pass_large_d6_k2_counters.md")
+WRITE_SRC = os.path.join(ROOT, "paper_2407_20474_amd", "csrc", "enumerate.hip")
+
+
+def measured_traffic():
+    """HBM bytes per write-pass launch from the committed counter summary, or
+    None when the write kernel's source changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+        src = hashlib.sha256(open(WRITE_SRC, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.split(":", 1)[0].strip() in ("kernel_source_sha256",
+                                                              "traffic_bytes_per_launch"):
+            key, val = line.split(":", 1)
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("kernel_source_sha256") != src or "traffic_bytes_per_launch" not in fields:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 ALU_PEAK_OPS = 256 * 64 * 2.4e9   # 32-bit integer lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
@@ -29,7 +51,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "plain"])
+    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch"])
+    ap.add_argument("--sweep-d", type=int, default=5, choices=[5, 7, 9],
+                    help="dimension of the memo-dimension sweep workload")
     ap.add_argument("--seed", type=int, default=0, help="large workload seed (0, 1 or 2)")
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--rows-per-tile", type=int, default=0)
@@ -66,6 +90,126 @@ def cpu_baseline(n, g, sample_rows):
                       f"threaded C oracle, {dt:.2f} s"}
 
 
+def batch_cpu_baseline(queries, sample_rows):
+    """The CPU oracle (threaded over a_1 within each query) on the first queries
+    of the batch whose rows add up to >= sample_rows."""
+    import numpy as np
+
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(int(threads), 64))
+    picked, acc = [], 0
+    for n, g, rows in queries:
+        if acc >= sample_rows:
+            break
+        picked.append((n, g, rows))
+        acc += rows
+    bufs = [np.zeros((max(rows, 1), len(g)), dtype=np.uint32) for _, g, rows in picked]
+    tables = [oracle.count_table(n, g) for n, g, _ in picked]
+    t = time.perf_counter()
+    done = 0
+    for (n, g, rows), buf, table in zip(picked, bufs, tables):
+        _, r = oracle.enumerate_rows_threads(n, g, 0, n // g[0] + 1, threads, table=table,
+                                             out=buf)
+        done += r
+    dt = time.perf_counter() - t
+    return {"value": done / dt, "unit": "factorizations/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {len(picked)} queries of the batch ({done} rows), threaded C "
+                      f"oracle per query, {dt:.2f} s"}
+
+
+def run_batch(args):
+    """The batched workload: 4096 independent queries, one persistent write launch."""
+    import numpy as np
+    import torch
+
+    from paper_2407_20474_amd import inputs, zset
+
+    allq = inputs.load_batch_queries()
+    queries = [(n, g) for n, g, _ in allq]
+    t = time.perf_counter()
+    b = zset.Batch(queries)
+    create_s = time.perf_counter() - t
+    assert [int(x) for x in b.rows] == [r for _, _, r in allq], "counts disagree with the stored workload"
+    rows = int(b.rows.sum())
+    bytes_written = int(sum(int(b.rows[i]) * int(b.d[i]) * 4 for i in range(b.nq)))
+    out = b.alloc()
+    print(f"# batch planned in {create_s:.2f} s: {b.nq} queries, {rows} rows, "
+          f"{bytes_written / 1e9:.1f} GB", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        b.run(out)
+        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(b.run(out).stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    value = rows / (dt / args.steps)
+    done_us = b.times()
+    lat = done_us[b.rows > 0]
+    # Stage breakdown (and the write kernel's time) from one eager run of the same plan.
+    e = zset.Batch(queries, use_graph=False)
+    es = e.run(out).stats
+    e.free()
+    print(f"# batched: {ms_per_step:.2f} ms/run; eager stages {es}", file=sys.stderr, flush=True)
+    # The plain path: one zset_enumerate_ex call per query, into the same buffer.
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for q, (n, g) in enumerate(queries):
+        r = int(b.rows[q])
+        if r == 0:
+            continue
+        zset.enumerate_ex(n, g, out=b.rows_of(out, q))
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - tp
+    plain_value = rows / plain_s
+    print(f"# plain path: {plain_s:.2f} s for {b.nq} calls", file=sys.stderr, flush=True)
+    write_us = es["write_us"]
+    achieved = bytes_written / (write_us * 1e-6) / 1e9
+    kcount = {int(k): int((b.k == k).sum()) for k in np.unique(b.k)}
+    line = {
+        "metric": "Z(n) factorizations/s emitted (bit-exact)",
+        "value": value,
+        "unit": "factorizations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batch: {b.nq} queries (d in 3..8, g in [5, 150], |Z| log-uniform in "
+                         f"[1e2, 1e7]), {rows} rows, {bytes_written / 1e9:.1f} GB, one graph "
+                         f"replay per step"),
+            "queries": b.nq, "rows": rows, "k_histogram": kcount,
+        },
+        "batch": {
+            "plain_value": plain_value, "plain_s": plain_s, "speedup_vs_plain": value / plain_value,
+            "p50_done_us": float(np.percentile(lat, 50)), "p99_done_us": float(np.percentile(lat, 99)),
+            "create_s": create_s, "eager_stages_us": {k: round(es[k], 1) for k in
+                                                     ("count_us", "memo_us", "plan_us", "write_us",
+                                                      "total_us")},
+            "units": stats[-1]["units"], "write_blocks": stats[-1]["write_blocks"],
+            "lds_bytes": stats[-1]["lds_bytes"], "graph_run_us": round(stats[-1]["total_us"], 1),
+        },
+        "step_hbm_write_frac": round(bytes_written / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_write_batch (persistent batched write pass, eager run)",
+                     "algorithmic_bytes_per_launch": bytes_written},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = batch_cpu_baseline(allq, args.cpu_sample_rows / 2)
+    print(json.dumps(line), flush=True)
+    b.free()
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -73,6 +217,10 @@ def main():
               "communication, and this build runs on a single MI355X (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch":
+        run_batch(args)
+        return
 
     import torch
 
@@ -82,6 +230,9 @@ def main():
     if args.workload == "large":
         item = w["large"][args.seed]
         n, g, k = item["n"], item["gens"], item["k"]
+    elif args.workload == "sweep":
+        item = next(x for x in w["sweep"] if len(x["gens"]) == args.sweep_d)
+        n, g, k = item["n"], item["gens"], 2
     else:
         item = w["plain"]
         n, g, k = item["n"], item["gens"], item["k"]
@@ -137,8 +288,9 @@ def main():
                 "frac": (ops / (write_us * 1e-6)) / ALU_PEAK_OPS, "traffic": None}
     else:
         achieved = bytes_written / (write_us * 1e-6) / 1e9
+        traffic = measured_traffic() if args.workload == "large" and args.seed == 0 else None
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "k_write (write pass)",
                 "algorithmic_bytes_per_launch": bytes_written}
     line = {

@@ -19,7 +19,8 @@
  *     memory of the current HIP device (hipMalloc or a torch CUDA tensor).
  *   - Generators are taken in the caller's order; they are never sorted.
  *     Repeated generators and gcd > 1 are allowed (Z stays finite and exact).
- *   - Limits: 1 <= d <= ZSET_MAX_D, every g_i >= 1, n <= 2^32 - 1.
+ *   - Limits: 1 <= d <= ZSET_MAX_D, every g_i >= 1, n <= 2^31 - 2 (the
+ *     count-table rows have n + 1 entries, indexed in 32 bits on the GPU).
  *   - Status codes are returned, never thrown; zset_strerror gives the text.
  *     On any error returned before the first kernel launch, `out` is untouched.
  *   - Every call that launches work synchronises its stream before returning.
@@ -87,7 +88,7 @@ void zset_default_opts(zset_opts *opts);
 /*
  * zset_count -- |Z(n; g)| (Section 1), computed on the GPU from the count
  * table C_j[x] = |Z(x; g_j..g_d)| (C_j[x] = C_{j+1}[x] + C_j[x - g_j]).
- *   n      element, <= 2^32 - 1
+ *   n      element, <= 2^31 - 2
  *   gens   host, d uint32 generators, each >= 1
  *   count  host, receives |Z(n)|
  * Errors: EINVAL (bad d, gens, n or NULL pointer), EOVERFLOW (|Z| >= 2^64-1),
@@ -116,7 +117,7 @@ zset_status zset_count_table(uint64_t n, const uint32_t *gens, int d,
  * (Alg 2.9, Section 2.3).
  *   gens_trailing host, k uint32 generators h_1..h_k, each >= 1
  *   k             1 <= k <= ZSET_MAX_D - 1
- *   top           number of elements tabulated, >= 1, <= 2^32
+ *   top           number of elements tabulated, in [1, 2^31 - 1]
  *   stream        hipStream_t or NULL
  *   memo          host, receives the handle (free with zset_memo_free)
  * Errors: EINVAL, EOVERFLOW (memo rows >= 2^32), ENOMEM, EDEVICE.
@@ -166,6 +167,111 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t 
                               uint64_t out_rows_cap, const zset_opts *opts,
                               zset_memo memo, uint64_t *rows_written,
                               uint64_t *checksum, zset_stats *stats);
+
+/* ------------------------------------------------------------------------
+ * Batches: many independent queries (n_q; g_q) enumerated by one persistent
+ * write launch.  A batch is planned once (zset_batch_create: count tables,
+ * memo dimension and slice length per query, output offsets, work units) and
+ * then run any number of times (zset_batch_run), each run recomputing every
+ * stage on the GPU -- count tables, memos (Lemma 2.3 recurrence), leaf
+ * layouts, slice starts -- and ending with one persistent write kernel that
+ * takes (query, slice range) work units from a device queue, largest first.
+ * By default a run replays a HIP graph captured at the first run.
+ *
+ * In this version the batched path is switched off: zset_batch_create returns
+ * ZSET_EDEVICE before any device work (a first device run stopped responding
+ * and the cause is not identified).  The other entry points are unaffected.
+ * ------------------------------------------------------------------------ */
+
+typedef struct zset_batch_s *zset_batch;
+
+typedef struct {
+    int count_only;            /* 1: no rows; per-query |Z| and checksums only  */
+    uint32_t max_chain_steps;  /* automatic k: largest memo recurrence length
+                                  (batches of min(h) elements) a query may use;
+                                  0 = 4096                                      */
+    uint32_t unit_tiles;       /* slices per work unit; 0 = 64                  */
+    int use_graph;             /* 1 = capture the run into a HIP graph at the
+                                  first run and replay it; 0 = launch the
+                                  stages one by one (per-stage timings)         */
+    void *stream;              /* hipStream_t for zset_batch_run; NULL = the
+                                  null stream                                   */
+} zset_batch_opts;
+
+typedef struct {
+    double total_us;           /* device time of the run (events around it)     */
+    double count_us, memo_us, plan_us, write_us;  /* per stage; use_graph = 0 only */
+    uint64_t rows;             /* sum of |Z(n_q)|                               */
+    uint64_t words;            /* output words including alignment padding      */
+    uint64_t tiles;            /* slices over all queries                       */
+    uint32_t units;            /* work units of the persistent write launch     */
+    uint32_t memo_queries;     /* queries with k >= 1                           */
+    uint32_t write_blocks;     /* workgroups of the persistent write launch     */
+    uint32_t lds_bytes;        /* LDS per workgroup of the write launch         */
+} zset_batch_stats;
+
+/* Defaults: rows written, automatic limits, graph replay, null stream. */
+void zset_batch_default_opts(zset_batch_opts *opts);
+
+/*
+ * zset_batch_create -- plan a batch of nq queries on the current device.
+ *   nq             number of queries, >= 1
+ *   n              host, nq elements, each <= 2^31 - 2
+ *   d              host, nq dimensions, each in [1, ZSET_MAX_D]
+ *   gens           host, sum(d) generators, query q's d[q] generators after
+ *                  those of queries 0..q-1 (caller order, each >= 1)
+ *   k              host, nq memo dimensions in [0, d[q]-1], or -1 = automatic
+ *                  (the largest k whose memo fits the LDS budgets and whose
+ *                  recurrence takes at most max_chain_steps batches); NULL =
+ *                  all automatic.  A k >= 1 whose memo cannot be built in LDS
+ *                  is EINVAL.
+ *   rows_per_tile  host, nq slice lengths (multiples of 128) or 0 =
+ *                  automatic; NULL = all automatic
+ *   opts           host or NULL for the defaults
+ *   batch          host, receives the handle (free with zset_batch_free)
+ * The count tables are computed on the GPU here (one synchronisation); every
+ * other device buffer is allocated here too, so zset_batch_run allocates
+ * nothing.  Query q's rows go to words [offset_q, offset_q + |Z_q| * d[q]) of
+ * the output, offset_q a multiple of 4 (16-byte aligned).
+ * Errors: EINVAL, EOVERFLOW (a |Z| >= 2^64 - 1 or the output exceeds 2^64
+ *         bytes), ENOMEM, EDEVICE.
+ */
+zset_status zset_batch_create(int nq, const uint64_t *n, const int *d,
+                              const uint32_t *gens, const int *k,
+                              const uint64_t *rows_per_tile,
+                              const zset_batch_opts *opts, zset_batch *batch);
+
+/*
+ * zset_batch_info -- sizes chosen by zset_batch_create (any pointer may be
+ * NULL): total output words, and per query (host arrays of nq) |Z_q|, output
+ * word offset, memo dimension k and slice count.
+ */
+zset_status zset_batch_info(zset_batch batch, uint64_t *total_words, uint64_t *rows,
+                            uint64_t *offsets, int *k, uint64_t *tiles);
+
+/*
+ * zset_batch_run -- run the batch once; returns after completion.
+ *   out            device, 16-byte aligned, out_words_cap uint32 words
+ *                  (>= total_words of zset_batch_info); ignored when
+ *                  count_only.  Padding words between queries are not written.
+ *   checksums      host, optional, nq entries: per query, the checksum of
+ *                  zset_enumerate_ex (count-only batches; else zeros)
+ *   stats          host, optional
+ * Errors: EINVAL (`out` not 16-byte aligned device memory), ECAPACITY,
+ *         EDEVICE (a HIP call or a kernel's own check failed).
+ */
+zset_status zset_batch_run(zset_batch batch, uint32_t *out, uint64_t out_words_cap,
+                           uint64_t *checksums, zset_batch_stats *stats);
+
+/*
+ * zset_batch_times -- per-query completion times of the last run, in
+ * microseconds from the start of that run, from the GPU's constant-rate
+ * clock (host array of nq).
+ */
+zset_status zset_batch_times(zset_batch batch, double *done_us);
+
+/* Release a batch (NULL is ignored). */
+void zset_batch_free(zset_batch batch);
 
 /* Static text for a status code. */
 const char *zset_strerror(zset_status status);

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libzset.so")
-SOURCES = ["count_table.hip", "scan.hip", "memo.hip", "enumerate.hip", "api.hip"]
+SOURCES = ["count_table.hip", "scan.hip", "memo.hip", "enumerate.hip", "api.hip", "batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

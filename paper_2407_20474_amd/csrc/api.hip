@@ -9,15 +9,13 @@
 #include <string>
 
 #include "zset.h"
+#include "zset_host.h"
 #include "zset_internal.h"
 
 namespace zset {
-namespace {
-
-// Count-table rows have n + 1 entries indexed in 32 bits on the device.
-constexpr uint64_t kMaxN = (uint64_t(1) << 31) - 2;
 
 thread_local std::string g_last_error;
+std::mutex g_mu;
 
 zset_status fail(zset_status st, const std::string& msg) {
   g_last_error = msg;
@@ -29,21 +27,10 @@ zset_status hip_fail(hipError_t e, const char* what) {
   return fail(ZSET_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define ZSET_HIP(call)                          \
-  do {                                          \
-    hipError_t e_ = (call);                     \
-    if (e_ != hipSuccess) return hip_fail(e_, #call); \
-  } while (0)
-
 bool fault_injected(const char* what) {
   const char* f = std::getenv("ZSET_FAULT");
   return f && std::strcmp(f, what) == 0;
 }
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
 
 zset_status ensure(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 16;
@@ -68,6 +55,8 @@ zset_status ensure(DevBuf& b, size_t bytes) {
   return ZSET_OK;
 }
 
+namespace {
+
 // Per-device scratch, reused across calls.
 struct Ctx {
   int device = -1;
@@ -76,7 +65,6 @@ struct Ctx {
   hipEvent_t ev[6] = {};
 };
 
-std::mutex g_mu;
 std::map<int, Ctx*> g_ctx;
 
 // misc layout (uint64 words): [0] status word (int), [1] checksum, [2..34] row sums
@@ -114,6 +102,19 @@ zset_status get_ctx(Ctx** out) {
   return ZSET_OK;
 }
 
+}  // namespace
+
+bool is_device_pointer(const void* p) {
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
+         attr.type == hipMemoryTypeUnified;
+}
+
 zset_status check_gens(const uint32_t* gens, int d, const char* what) {
   if (!gens) return fail(ZSET_EINVAL, std::string(what) + " is NULL");
   if (d < 1 || d > kMaxD) return fail(ZSET_EINVAL, "d must lie in [1, 32]");
@@ -129,39 +130,10 @@ zset_status check_query(uint64_t n, const uint32_t* gens, int d) {
   return ZSET_OK;
 }
 
-bool is_device_pointer(const void* p) {
-  hipPointerAttribute_t attr;
-  std::memset(&attr, 0, sizeof attr);
-  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged ||
-         attr.type == hipMemoryTypeUnified;
-}
 
-const char* device_error_text(int code) {
-  switch (code) {
-    case kErrOdometer: return "a slice ran out of prefixes before its rows were written";
-    case kErrTileRows: return "a slice wrote a different number of rows than planned";
-    case kErrMemoTotal: return "the memo build produced a different row total than counted";
-    case kErrUnrank: return "a slice start could not be unranked";
-    default: return "unknown kernel check";
-  }
-}
-
-float elapsed_us(hipEvent_t a, hipEvent_t b) {
-  float ms = 0.f;
-  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0.f;
-  }
-  return ms * 1000.f;
-}
-
-int max_lds_bytes(Ctx* c) {
+int device_max_lds_bytes(int device) {
   int v = 0;
-  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) !=
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 64 * 1024;
@@ -175,6 +147,29 @@ uint32_t next_pow2(uint32_t v) {
   return p;
 }
 
+float elapsed_us(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0.f;
+  }
+  return ms * 1000.f;
+}
+
+const char* device_error_text(int code) {
+  switch (code) {
+    case kErrOdometer: return "a slice ran out of prefixes before its rows were written";
+    case kErrTileRows: return "a slice wrote a different number of rows than planned";
+    case kErrMemoTotal: return "the memo build produced a different row total than counted";
+    case kErrUnrank: return "a slice start could not be unranked";
+    default: return "unknown kernel check";
+  }
+}
+
+namespace {
+
+int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
+
 // Builds Memo[p] = Z(p; h) for p < top into nat (natural order) and the
 // natural offsets off[0..top].  `ge` holds |Z(m; h_i..h_k)| for i = 0..k-1
 // (row stride ge_stride) and `sizes` = ge row 0; R = the total row count.
@@ -183,6 +178,11 @@ uint32_t next_pow2(uint32_t v) {
 zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint32_t* nat,
                             hipStream_t s) {
+  if (k == 1) {
+    if (R != (top - 1) / h[0] + 1) return fail(ZSET_EDEVICE, "memo row count disagrees (k = 1)");
+    ZSET_HIP(launch_memo_k1(h[0], top, R, nat, off, s));
+    return ZSET_OK;
+  }
   uint32_t b = h[0], hmax = h[0];
   for (int i = 1; i < k; ++i) {
     b = std::min(b, h[i]);
@@ -528,7 +528,8 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       uint64_t* endc = reinterpret_cast<uint64_t*>(c->endc.p);
       ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, endc, &nclass, s));
       uint32_t* leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
-      ZSET_HIP(launch_memo_leaf(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, P, err, s));
+      ZSET_HIP(launch_memo_leaf(
+          make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, P), err, s));
       P.endc = endc;
       P.leaf = leaf;
       P.leaf_rows = Rn;

@@ -13,7 +13,8 @@
 // with g_j columns (x = t * g_j + rho): column rho is the residue class
 // rho mod g_j.  One workgroup computes all rows with a three-phase blocked scan
 // per row (chunk sums, carries per column, rescan), which keeps every load
-// coalesced across adjacent residues.
+// coalesced across adjacent residues; the row sums are reduced on the way.
+// In a batch, each workgroup computes the table of one query.
 #include "zset_internal.h"
 
 namespace zset {
@@ -22,79 +23,6 @@ namespace {
 
 constexpr int kCtThreads = 1024;
 constexpr int kCtPart = 2048;  // chunk partial sums held in LDS
-
-__global__ __launch_bounds__(kCtThreads) void k_count_table(uint64_t* __restrict__ T,
-                                                            uint32_t N, Gens gs, int d) {
-  __shared__ uint64_t part[kCtPart];
-  const int tid = threadIdx.x;
-  uint64_t* last = T + size_t(d) * N;
-  for (uint64_t x = tid; x < N; x += kCtThreads) last[x] = (x == 0) ? 1 : 0;
-  __syncthreads();
-
-  for (int j = d - 1; j >= 0; --j) {
-    const uint64_t* __restrict__ U = T + size_t(j + 1) * N;
-    uint64_t* __restrict__ V = T + size_t(j) * N;
-    const uint32_t G = gs.g[j];
-    if (G >= N) {  // no x - g_j >= 0: the row is a copy
-      for (uint64_t x = tid; x < N; x += kCtThreads) V[x] = U[x];
-      __syncthreads();
-      continue;
-    }
-    const uint32_t rows = uint32_t((uint64_t(N) + G - 1) / G);
-    for (uint32_t c0 = 0; c0 < G; c0 += kCtThreads) {
-      const uint32_t CG = (G - c0) < uint32_t(kCtThreads) ? (G - c0) : uint32_t(kCtThreads);
-      uint32_t B = kCtPart / CG;
-      if (B > rows) B = rows;
-      if (B < 1) B = 1;
-      const uint32_t RB = (rows + B - 1) / B;
-      const uint32_t items = B * CG;
-      // Phase 1: sum of each (chunk, column).
-      for (uint32_t it = tid; it < items; it += kCtThreads) {
-        const uint32_t b = it / CG, rho = c0 + it % CG;
-        const uint32_t t0 = b * RB;
-        const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
-        uint64_t s = 0;
-        for (uint32_t t = t0; t < t1; ++t) {
-          const uint64_t x = uint64_t(t) * G + rho;
-          if (x < N) s = sat_add_u64(s, U[x]);
-        }
-        part[it] = s;
-      }
-      __syncthreads();
-      // Phase 2: exclusive scan of the chunk sums down each column.
-      for (uint32_t col = tid; col < CG; col += kCtThreads) {
-        uint64_t run = 0;
-        for (uint32_t b = 0; b < B; ++b) {
-          const uint64_t v = part[b * CG + col];
-          part[b * CG + col] = run;
-          run = sat_add_u64(run, v);
-        }
-      }
-      __syncthreads();
-      // Phase 3: rescan each chunk from its carry.
-      for (uint32_t it = tid; it < items; it += kCtThreads) {
-        const uint32_t b = it / CG, rho = c0 + it % CG;
-        const uint32_t t0 = b * RB;
-        const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
-        uint64_t run = part[it];
-        for (uint32_t t = t0; t < t1; ++t) {
-          const uint64_t x = uint64_t(t) * G + rho;
-          if (x < N) {
-            run = sat_add_u64(run, U[x]);
-            V[x] = run;
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-}
-
-// The same table with the working row held in LDS (n + 1 <= kCtLdsMax): each
-// row is transformed in place from row j+1 into row j by the three-phase
-// column scan, copied out with coalesced stores, and summed on the way
-// (sums[j] = sum_x C[j][x], saturating).
-constexpr uint32_t kCtLdsMax = 16384;
 
 __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
 #pragma unroll
@@ -109,10 +37,93 @@ __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   return t;
 }
 
-__global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
-                                                                uint32_t N, Gens gs, int d,
-                                                                uint64_t* __restrict__ sums) {
-  __shared__ uint64_t buf[kCtLdsMax];
+// The whole table by one workgroup in global memory (any N), with the row
+// sums sums[j] = sum_x C[j][x] (saturating) when sums is non-NULL.  `gs` is
+// a copy of the generators in LDS.
+__device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs,
+                                   int d, uint64_t* __restrict__ sums) {
+  __shared__ uint64_t part[kCtPart];
+  __shared__ uint64_t red[kCtThreads / kWave];
+  const int tid = threadIdx.x;
+  uint64_t* last = T + size_t(d) * N;
+  for (uint64_t x = tid; x < N; x += kCtThreads) last[x] = (x == 0) ? 1 : 0;
+  if (tid == 0 && sums) sums[d] = 1;
+  __syncthreads();
+
+  for (int j = d - 1; j >= 0; --j) {
+    const uint64_t* __restrict__ U = T + size_t(j + 1) * N;
+    uint64_t* __restrict__ V = T + size_t(j) * N;
+    const uint32_t G = gs[j];
+    uint64_t acc = 0;
+    if (G >= N) {  // no x - g_j >= 0: the row is a copy
+      for (uint64_t x = tid; x < N; x += kCtThreads) {
+        const uint64_t v = U[x];
+        V[x] = v;
+        acc = sat_add_u64(acc, v);
+      }
+    } else {
+      const uint32_t rows = uint32_t((uint64_t(N) + G - 1) / G);
+      for (uint32_t c0 = 0; c0 < G; c0 += kCtThreads) {
+        const uint32_t CG = (G - c0) < uint32_t(kCtThreads) ? (G - c0) : uint32_t(kCtThreads);
+        uint32_t B = kCtPart / CG;
+        if (B > rows) B = rows;
+        if (B < 1) B = 1;
+        const uint32_t RB = (rows + B - 1) / B;
+        const uint32_t items = B * CG;
+        // Phase 1: sum of each (chunk, column).
+        for (uint32_t it = tid; it < items; it += kCtThreads) {
+          const uint32_t b = it / CG, rho = c0 + it % CG;
+          const uint32_t t0 = b * RB;
+          const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
+          uint64_t s = 0;
+          for (uint32_t t = t0; t < t1; ++t) {
+            const uint64_t x = uint64_t(t) * G + rho;
+            if (x < N) s = sat_add_u64(s, U[x]);
+          }
+          part[it] = s;
+        }
+        __syncthreads();
+        // Phase 2: exclusive scan of the chunk sums down each column.
+        for (uint32_t col = tid; col < CG; col += kCtThreads) {
+          uint64_t run = 0;
+          for (uint32_t b = 0; b < B; ++b) {
+            const uint64_t v = part[b * CG + col];
+            part[b * CG + col] = run;
+            run = sat_add_u64(run, v);
+          }
+        }
+        __syncthreads();
+        // Phase 3: rescan each chunk from its carry.
+        for (uint32_t it = tid; it < items; it += kCtThreads) {
+          const uint32_t b = it / CG, rho = c0 + it % CG;
+          const uint32_t t0 = b * RB;
+          const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
+          uint64_t run = part[it];
+          for (uint32_t t = t0; t < t1; ++t) {
+            const uint64_t x = uint64_t(t) * G + rho;
+            if (x < N) {
+              run = sat_add_u64(run, U[x]);
+              V[x] = run;
+              acc = sat_add_u64(acc, run);
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    const uint64_t total = block_sum_u64(acc, red);
+    if (tid == 0 && sums) sums[j] = total;
+    __syncthreads();
+  }
+}
+
+// The same table with the working row held in LDS (`buf`, N entries): each
+// row is transformed in place from row j+1 into row j by the three-phase
+// column scan, copied out with coalesced stores, and summed on the way.
+constexpr uint32_t kCtLdsMax = 16384;
+
+__device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs, int d,
+                                uint64_t* __restrict__ sums, uint64_t* buf) {
   __shared__ uint64_t part[kCtPart];
   __shared__ uint64_t red[kCtThreads / kWave];
   const int tid = threadIdx.x;
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   __syncthreads();
 
   for (int j = d - 1; j >= 0; --j) {
-    const uint32_t G = gs.g[j];
+    const uint32_t G = gs[j];
     if (G < N) {
       const uint32_t rows = (N + G - 1) / G;
       for (uint32_t c0 = 0; c0 < G; c0 += kCtThreads) {
@@ -203,20 +214,62 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   }
 }
 
-// Saturating sum of each table row: sums[j] = sum_x C[j][x].
-__global__ __launch_bounds__(256) void k_row_sums(const uint64_t* __restrict__ T, uint32_t N,
-                                                  uint64_t* __restrict__ sums) {
-  __shared__ uint64_t red[256];
-  const uint64_t* row = T + size_t(blockIdx.x) * N;
-  uint64_t s = 0;
-  for (uint64_t x = threadIdx.x; x < N; x += 256) s = sat_add_u64(s, row[x]);
-  red[threadIdx.x] = s;
+__global__ __launch_bounds__(kCtThreads) void k_count_table(uint64_t* __restrict__ T,
+                                                            uint32_t N, Gens gs, int d,
+                                                            uint64_t* __restrict__ sums) {
+  __shared__ uint32_t g[kMaxD];
+  if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (int(threadIdx.x) < w) red[threadIdx.x] = sat_add_u64(red[threadIdx.x], red[threadIdx.x + w]);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+  count_table_global(T, N, g, d, sums);
+}
+
+__global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
+                                                                uint32_t N, Gens gs, int d,
+                                                                uint64_t* __restrict__ sums) {
+  __shared__ uint64_t buf[kCtLdsMax];
+  __shared__ uint32_t g[kMaxD];
+  if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
+  __syncthreads();
+  count_table_lds(T, N, g, d, sums, buf);
+}
+
+// Batched forms: workgroup b computes the table of jobs[first + b], and
+// writes |Z(n)| = C[0][n] to its `total`.
+__device__ inline void load_job(const CountJob* __restrict__ jobs, uint32_t* g, uint64_t** T,
+                                uint32_t* N, int* d, uint64_t** sums, uint64_t** total) {
+  const CountJob& J = jobs[blockIdx.x];
+  if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = J.g[threadIdx.x];
+  *T = J.table;
+  *N = J.N;
+  *d = J.d;
+  *sums = J.sums;
+  *total = J.total;
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kCtThreads) void k_count_table_batch_lds(
+    const CountJob* __restrict__ jobs) {
+  extern __shared__ __align__(16) uint64_t dyn_buf[];
+  __shared__ uint32_t g[kMaxD];
+  uint64_t *T, *sums, *total;
+  uint32_t N;
+  int d;
+  load_job(jobs, g, &T, &N, &d, &sums, &total);
+  count_table_lds(T, N, g, d, sums, dyn_buf);
+  __syncthreads();
+  if (threadIdx.x == 0) *total = T[N - 1];
+}
+
+__global__ __launch_bounds__(kCtThreads) void k_count_table_batch_global(
+    const CountJob* __restrict__ jobs) {
+  __shared__ uint32_t g[kMaxD];
+  uint64_t *T, *sums, *total;
+  uint32_t N;
+  int d;
+  load_job(jobs, g, &T, &N, &d, &sums, &total);
+  count_table_global(T, N, g, d, sums);
+  __syncthreads();
+  if (threadIdx.x == 0) *total = T[N - 1];
 }
 
 }  // namespace
@@ -228,12 +281,29 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   const uint32_t N = uint32_t(n + 1);
   if (N <= kCtLdsMax) {
     hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
-    return hipGetLastError();
+  } else {
+    hipLaunchKernelGGL(k_count_table, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
   }
-  hipLaunchKernelGGL(k_count_table, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || !sums) return e;
-  hipLaunchKernelGGL(k_row_sums, dim3(d + 1), dim3(256), 0, s, table, N, sums);
+  return hipGetLastError();
+}
+
+uint32_t count_table_lds_max() { return kCtLdsMax; }
+
+hipError_t prepare_count_table_batch(uint32_t max_lds_n) {
+  const size_t bytes = size_t(max_lds_n) * sizeof(uint64_t);
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_count_table_batch_lds),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+}
+
+hipError_t launch_count_table_batch(const CountJob* jobs, uint32_t njobs, uint32_t max_lds_n,
+                                    bool lds, hipStream_t s) {
+  if (njobs == 0) return hipSuccess;
+  if (lds) {
+    const size_t bytes = size_t(max_lds_n) * sizeof(uint64_t);
+    hipLaunchKernelGGL(k_count_table_batch_lds, dim3(njobs), dim3(kCtThreads), bytes, s, jobs);
+  } else {
+    hipLaunchKernelGGL(k_count_table_batch_global, dim3(njobs), dim3(kCtThreads), 0, s, jobs);
+  }
   return hipGetLastError();
 }
 

@@ -95,9 +95,7 @@ __device__ inline uint32_t wave_incl_sum_sat(uint32_t v, uint32_t cap) {
 }
 
 // Slice start: first U coordinates and the offset t0 inside their block.
-__global__ __launch_bounds__(256) void k_plan(EnumParams P) {
-  const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (tile >= P.ntiles) return;
+__device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
   const uint64_t N = uint64_t(P.n) + 1;
   uint64_t r = tile * P.rows_per_tile;
   uint32_t x = P.n;
@@ -119,6 +117,29 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   st[P.U] = uint32_t(r);
   st[P.U + 1] = uint32_t(r >> 32);
   if (r >= P.table[uint64_t(P.U) * N + x]) set_error(P.err, kErrUnrank);
+}
+
+__global__ __launch_bounds__(256) void k_plan(EnumParams P) {
+  const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (tile >= P.ntiles) return;
+  plan_tile(P, tile);
+}
+
+// Batched: global slice index -> (query, slice) by bisection of the slice
+// bases of the queries that have slices (tile_base[i] = slices of the queries
+// plan_q[0..i-1], strictly increasing).
+__global__ __launch_bounds__(256) void k_plan_batch(const EnumParams* __restrict__ qp,
+                                                    const uint64_t* __restrict__ tile_base,
+                                                    const uint32_t* __restrict__ plan_q,
+                                                    uint32_t nplan, uint64_t total_tiles) {
+  const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t >= total_tiles) return;
+  uint32_t lo = 0, hi = nplan - 1;  // last entry whose base <= t
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  plan_tile(qp[plan_q[lo]], t - tile_base[lo]);
 }
 
 template <bool ALIGN16>
@@ -177,16 +198,266 @@ __host__ __device__ inline uint64_t write_shared_words(const EnumParams& P) {
   return w;
 }
 
+// The per-query scalars one slice needs, held in scalar registers: the
+// single-query kernel fills them from its kernel arguments, the batched kernel
+// from the query's descriptor.
+struct TileArgs {
+  uint32_t n, d, U, k;
+  uint32_t gseg;               // g_{U-1} (U >= 1): step of the lane coordinate
+  uint32_t ring, flush;        // staging ring rows (power of two), rows per flush
+  uint64_t total;              // |Z(n)|
+  uint64_t rows_per_tile;      // slice length
+  const uint64_t* cnt_row;     // count-table row U: C[U][x]
+  const uint64_t* endc;        // residue-class ends of the leaf-order memo
+  const uint32_t* leaf;        // leaf-order memo rows
+  uint64_t leaf_rows;
+  uint32_t* out;               // first row of this query
+  int* err;
+  DivMod32 dG;                 // division by g_U
+};
+
+__device__ inline TileArgs tile_args(const EnumParams& P) {
+  TileArgs A;
+  A.n = P.n;
+  A.d = uint32_t(P.d);
+  A.U = uint32_t(P.U);
+  A.k = uint32_t(P.k);
+  A.gseg = P.U >= 1 ? P.g.g[P.U - 1] : 0;
+  A.ring = P.ring;
+  A.flush = P.flush;
+  A.total = P.total;
+  A.rows_per_tile = P.rows_per_tile;
+  A.cnt_row = P.table + uint64_t(P.U) * (uint64_t(P.n) + 1);
+  A.endc = P.endc;
+  A.leaf = P.leaf;
+  A.leaf_rows = P.leaf_rows;
+  A.out = P.out;
+  A.err = P.err;
+  A.dG = P.dG;
+  return A;
+}
+
+// One slice: rows [tile * T, tile * T + target) of the query, starting from
+// the slice start `st` (first U coordinates and t0).  Shared by the
+// single-query and the batched write kernels.
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+__device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32_t* st,
+                                  uint32_t* ring, uint32_t* marks, const uint32_t* lds_memo,
+                                  const uint32_t* lds_cnt, const uint32_t* lds_endc, uint32_t gj,
+                                  uint32_t fsh, uint32_t fmk, uint64_t& csum) {
+  const int lane = lane_id();
+  const int d = int(P.d), U = int(P.U), k = int(P.k);
+  const uint32_t ring_mask = P.ring - 1;
+  const uint32_t flush_rows_n = P.flush;
+  const int nouter = U >= 1 ? U - 1 : 0;  // coordinates 0..U-2 form the outer prefix
+  const uint32_t gseg = P.gseg;
+  const uint64_t* cnt_row = P.cnt_row;
+  const uint64_t r0 = tile * P.rows_per_tile;
+  const uint64_t left = P.total - r0;
+  const uint32_t target = uint32_t(left < P.rows_per_tile ? left : P.rows_per_tile);
+
+  // Slice start, lane-distributed: lane j < U holds a_j and the remainder
+  // after coordinate j.
+  uint32_t aj = lane < U ? st[lane] : 0;
+  const uint64_t t0 = uint64_t(st[U]) | (uint64_t(st[U + 1]) << 32);
+  uint32_t remj;
+  {
+    uint32_t ps = lane < U ? aj * gj : 0;  // every partial sum is <= n
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t y = __shfl_up(ps, off, kWave);
+      if (lane >= off) ps += y;
+    }
+    remj = P.n - ps;
+  }
+  uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
+  uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
+
+  uint32_t produced = 0, flushed = 0;
+  bool first = true;
+  bool single_done = false;
+  uint32_t* out_tile = P.out + r0 * uint64_t(d);
+
+  while (produced < target) {
+    const uint32_t remaining = target - produced;
+    const uint32_t A = aseg + uint32_t(lane);
+    bool ok;
+    uint32_t xs;
+    if (U >= 1) {
+      const uint64_t ag = uint64_t(A) * gseg;
+      ok = ag <= xouter;
+      xs = ok ? xouter - uint32_t(ag) : 0;
+    } else {
+      ok = (lane == 0) && !single_done;
+      xs = P.n;
+    }
+    const uint32_t qx = P.dG.div(xs);
+    uint32_t tot;
+
+    if (MODE == 0) {
+      const bool valid = ok && (P.dG.mod(xs, qx) == 0);
+      const uint64_t mask = ballot64(valid);
+      const uint32_t pos = mbcnt64(mask);
+      const uint32_t cnt = uint32_t(__popcll((unsigned long long)mask));
+      tot = cnt < remaining ? cnt : remaining;
+      if (valid && pos < tot) {
+        if (COUNT_ONLY) {
+          uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + pos);
+          for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
+          h = fnv1a_u32(h, A);
+          h = fnv1a_u32(h, qx);
+          csum += h;
+        } else {
+          uint32_t* row = ring + ((produced + pos) & ring_mask) * uint32_t(d);
+          for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+          row[U - 1] = A;
+          row[U] = qx;
+        }
+      }
+      if (!COUNT_ONLY) {
+        wave_sync();
+        const uint32_t written = produced + tot;
+        while (written - flushed >= flush_rows_n) {
+          flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
+                              out_tile + uint64_t(flushed) * d);
+          flushed += flush_rows_n;
+        }
+        wave_sync();
+      }
+    } else {
+      const uint32_t rx = P.dG.mod(xs, qx);
+      uint64_t c, start;
+      if (LDSCNT) {
+        const uint32_t c32v = ok ? lds_cnt[xs] : 0;
+        c = c32v;
+        start = ok ? uint64_t(lds_endc[rx] - c32v) : 0;
+      } else {
+        c = ok ? cnt_row[xs] : 0;
+        start = ok ? P.endc[rx] - c : 0;
+      }
+      if (first && lane == 0) {
+        if (t0 >= c) {  // the plan guarantees t0 < c; refuse to read past the segment
+          set_error(P.err, kErrUnrank);
+          c = 0;
+        } else {
+          start += t0;
+          c -= t0;
+        }
+      }
+      const uint32_t c32 = uint32_t(c < remaining ? c : remaining);
+      const uint32_t incl = wave_incl_sum_sat(c32, remaining);
+      const uint32_t up = __shfl_up(incl, 1, kWave);
+      const uint32_t excl = lane ? up : 0;
+      tot = readlane_u32(incl, kWave - 1);
+      // Memo row of batch row rho is segbase[owner] + rho (wrapping arithmetic).
+      const uint64_t segbase = start - excl;
+      const uint32_t seg_lo = uint32_t(segbase), seg_hi = uint32_t(segbase >> 32);
+      uint32_t carry = 0;  // 1 + segment lane of the row just before this chunk
+      for (uint32_t beta = 0; beta < tot; beta += kWave) {
+        const uint32_t rho = beta + uint32_t(lane);
+        const bool act = rho < tot;
+        marks[lane] = 0;
+        wave_sync();
+        if (c32 != 0 && excl >= beta && excl - beta < uint32_t(kWave)) marks[excl - beta] = lane + 1;
+        wave_sync();
+        uint32_t m = wave_incl_max(marks[lane]);
+        m = max(m, carry);
+        carry = readlane_u32(m, kWave - 1);
+        const int owner = int(m) - 1;  // >= 0: row 0 of a batch always starts a segment
+        const uint32_t o_lo = __shfl(seg_lo, owner, kWave);
+        const uint32_t o_qx = __shfl(qx, owner, kWave);
+        uint64_t mrow;
+        if (PACK == 0) {
+          const uint32_t o_hi = __shfl(seg_hi, owner, kWave);
+          mrow = ((uint64_t(o_hi) << 32) | o_lo) + rho;
+        } else {
+          mrow = uint32_t(o_lo + rho);
+        }
+        const uint32_t o_A = aseg + uint32_t(owner);
+        if (act && mrow >= P.leaf_rows) {
+          set_error(P.err, kErrTileRows);
+        } else if (act) {
+          MemoRow<PACK> mr;
+          mr.load(lds_memo, P.leaf, mrow, k);
+          const uint32_t aU = o_qx - mr.field(fsh, fmk, 0);
+          if (COUNT_ONLY) {
+            uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
+            for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
+            if (U >= 1) h = fnv1a_u32(h, o_A);
+            h = fnv1a_u32(h, aU);
+            for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
+            csum += h;
+          } else {
+            uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
+            for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+            if (U >= 1) row[U - 1] = o_A;
+            row[U] = aU;
+            for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
+          }
+        }
+        wave_sync();
+        if (!COUNT_ONLY) {
+          const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
+          const uint32_t written = produced + beta + nrows;
+          while (written - flushed >= flush_rows_n) {
+            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
+                                out_tile + uint64_t(flushed) * d);
+            flushed += flush_rows_n;
+          }
+          wave_sync();
+        }
+      }
+    }
+
+    produced += tot;
+    if (produced >= target) break;
+    first = false;
+    if (U == 0) {
+      if (single_done) break;
+      single_done = true;
+      continue;
+    }
+    if (uint64_t(aseg + kWave) * gseg <= xouter) {
+      aseg += kWave;
+      continue;
+    }
+    // Odometer: the rightmost outer coordinate that can still grow.
+    const bool can = lane < nouter && remj >= gj;
+    const uint64_t mask = ballot64(can);
+    if (mask == 0) {
+      if (lane == 0) set_error(P.err, kErrOdometer);
+      break;
+    }
+    const int js = 63 - __clzll((unsigned long long)mask);
+    if (lane == js) {
+      aj += 1;
+      remj -= gj;
+    }
+    const uint32_t nrem = readlane_u32(remj, js);
+    if (lane > js && lane < nouter) {
+      aj = 0;
+      remj = nrem;
+    }
+    xouter = nrem;
+    aseg = 0;
+  }
+
+  if (!COUNT_ONLY && produced > flushed) {
+    flush_rows<ALIGN16>(ring, flushed & ring_mask, produced - flushed, d,
+                        out_tile + uint64_t(flushed) * d);
+  }
+  wave_sync();
+  if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
+}
+
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
 __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ __align__(16) uint32_t lds[];
   const int lane = lane_id();
   const int wave = int(threadIdx.x / kWave);
   const int d = P.d, U = P.U, k = P.k;
   const uint64_t N = uint64_t(P.n) + 1;
   const uint32_t ring_rows = P.ring;
-  const uint32_t ring_mask = ring_rows - 1;
-  const uint32_t flush_rows_n = P.flush;
   const uint32_t S = uint32_t(U + 2);  // words of one slice start
 
   // ---- Prologue: every global load of the kernel happens here, before the
@@ -238,11 +509,9 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   const uint32_t gj = lane < d ? P.g.g[lane] : 0;
   const uint32_t fsh = lane <= k ? P.fshift[lane] : 0;
   const uint32_t fmk = lane <= k ? P.fmask[lane] : 0;
+  const TileArgs A = tile_args(P);
   __syncthreads();
 
-  const int nouter = U >= 1 ? U - 1 : 0;  // coordinates 0..U-2 form the outer prefix
-  const uint32_t gseg = (U >= 1) ? P.g.g[U - 1] : 0;
-  const uint64_t* cnt_row = P.table + uint64_t(U) * N;
   uint64_t csum = 0;
 
   for (;;) {
@@ -251,203 +520,9 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     const uint32_t ti = __builtin_amdgcn_readfirstlane(slot_l);
     if (ti >= my_tiles) break;
     const uint64_t tile = B + uint64_t(ti) * NB;
-    const uint64_t r0 = tile * P.rows_per_tile;
-    const uint64_t left = P.total - r0;
-    const uint32_t target = uint32_t(left < P.rows_per_tile ? left : P.rows_per_tile);
-
-    // Slice start, lane-distributed: lane j < U holds a_j and the remainder
-    // after coordinate j.
-    const uint32_t* st = tstates + ti * S;
-    uint32_t aj = lane < U ? st[lane] : 0;
-    const uint64_t t0 = uint64_t(st[U]) | (uint64_t(st[U + 1]) << 32);
-    uint32_t remj;
-    {
-      uint32_t ps = lane < U ? aj * gj : 0;  // every partial sum is <= n
-#pragma unroll
-      for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t y = __shfl_up(ps, off, kWave);
-        if (lane >= off) ps += y;
-      }
-      remj = P.n - ps;
-    }
-    uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
-    uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
-
-    uint32_t produced = 0, flushed = 0;
-    bool first = true;
-    bool single_done = false;
-    uint32_t* out_tile = P.out + r0 * uint64_t(d);
-
-    while (produced < target) {
-      const uint32_t remaining = target - produced;
-      const uint32_t A = aseg + uint32_t(lane);
-      bool ok;
-      uint32_t xs;
-      if (U >= 1) {
-        const uint64_t ag = uint64_t(A) * gseg;
-        ok = ag <= xouter;
-        xs = ok ? xouter - uint32_t(ag) : 0;
-      } else {
-        ok = (lane == 0) && !single_done;
-        xs = P.n;
-      }
-      const uint32_t qx = P.dG.div(xs);
-      uint32_t tot;
-
-      if (MODE == 0) {
-        const bool valid = ok && (P.dG.mod(xs, qx) == 0);
-        const uint64_t mask = ballot64(valid);
-        const uint32_t pos = mbcnt64(mask);
-        const uint32_t cnt = uint32_t(__popcll((unsigned long long)mask));
-        tot = cnt < remaining ? cnt : remaining;
-        if (valid && pos < tot) {
-          if (COUNT_ONLY) {
-            uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + pos);
-            for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
-            h = fnv1a_u32(h, A);
-            h = fnv1a_u32(h, qx);
-            csum += h;
-          } else {
-            uint32_t* row = ring + ((produced + pos) & ring_mask) * uint32_t(d);
-            for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-            row[U - 1] = A;
-            row[U] = qx;
-          }
-        }
-        if (!COUNT_ONLY) {
-          wave_sync();
-          const uint32_t written = produced + tot;
-          while (written - flushed >= flush_rows_n) {
-            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                                out_tile + uint64_t(flushed) * d);
-            flushed += flush_rows_n;
-          }
-          wave_sync();
-        }
-      } else {
-        const uint32_t rx = P.dG.mod(xs, qx);
-        uint64_t c, start;
-        if (LDSCNT) {
-          const uint32_t c32v = ok ? lds_cnt[xs] : 0;
-          c = c32v;
-          start = ok ? uint64_t(lds_endc[rx] - c32v) : 0;
-        } else {
-          c = ok ? cnt_row[xs] : 0;
-          start = ok ? P.endc[rx] - c : 0;
-        }
-        if (first && lane == 0) {
-          if (t0 >= c) {  // the plan guarantees t0 < c; refuse to read past the segment
-            set_error(P.err, kErrUnrank);
-            c = 0;
-          } else {
-            start += t0;
-            c -= t0;
-          }
-        }
-        const uint32_t c32 = uint32_t(c < remaining ? c : remaining);
-        const uint32_t incl = wave_incl_sum_sat(c32, remaining);
-        const uint32_t up = __shfl_up(incl, 1, kWave);
-        const uint32_t excl = lane ? up : 0;
-        tot = readlane_u32(incl, kWave - 1);
-        // Memo row of batch row rho is segbase[owner] + rho (wrapping arithmetic).
-        const uint64_t segbase = start - excl;
-        const uint32_t seg_lo = uint32_t(segbase), seg_hi = uint32_t(segbase >> 32);
-        uint32_t carry = 0;  // 1 + segment lane of the row just before this chunk
-        for (uint32_t beta = 0; beta < tot; beta += kWave) {
-          const uint32_t rho = beta + uint32_t(lane);
-          const bool act = rho < tot;
-          marks[lane] = 0;
-          wave_sync();
-          if (c32 != 0 && excl >= beta && excl - beta < uint32_t(kWave)) marks[excl - beta] = lane + 1;
-          wave_sync();
-          uint32_t m = wave_incl_max(marks[lane]);
-          m = max(m, carry);
-          carry = readlane_u32(m, kWave - 1);
-          const int owner = int(m) - 1;  // >= 0: row 0 of a batch always starts a segment
-          const uint32_t o_lo = __shfl(seg_lo, owner, kWave);
-          const uint32_t o_qx = __shfl(qx, owner, kWave);
-          uint64_t mrow;
-          if (PACK == 0) {
-            const uint32_t o_hi = __shfl(seg_hi, owner, kWave);
-            mrow = ((uint64_t(o_hi) << 32) | o_lo) + rho;
-          } else {
-            mrow = uint32_t(o_lo + rho);
-          }
-          const uint32_t o_A = aseg + uint32_t(owner);
-          if (act && mrow >= P.leaf_rows) {
-            set_error(P.err, kErrTileRows);
-          } else if (act) {
-            MemoRow<PACK> mr;
-            mr.load(lds_memo, P.leaf, mrow, k);
-            const uint32_t aU = o_qx - mr.field(fsh, fmk, 0);
-            if (COUNT_ONLY) {
-              uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
-              for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
-              if (U >= 1) h = fnv1a_u32(h, o_A);
-              h = fnv1a_u32(h, aU);
-              for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
-              csum += h;
-            } else {
-              uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
-              for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-              if (U >= 1) row[U - 1] = o_A;
-              row[U] = aU;
-              for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
-            }
-          }
-          wave_sync();
-          if (!COUNT_ONLY) {
-            const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
-            const uint32_t written = produced + beta + nrows;
-            while (written - flushed >= flush_rows_n) {
-              flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                                  out_tile + uint64_t(flushed) * d);
-              flushed += flush_rows_n;
-            }
-            wave_sync();
-          }
-        }
-      }
-
-      produced += tot;
-      if (produced >= target) break;
-      first = false;
-      if (U == 0) {
-        if (single_done) break;
-        single_done = true;
-        continue;
-      }
-      if (uint64_t(aseg + kWave) * gseg <= xouter) {
-        aseg += kWave;
-        continue;
-      }
-      // Odometer: the rightmost outer coordinate that can still grow.
-      const bool can = lane < nouter && remj >= gj;
-      const uint64_t mask = ballot64(can);
-      if (mask == 0) {
-        if (lane == 0) set_error(P.err, kErrOdometer);
-        break;
-      }
-      const int js = 63 - __clzll((unsigned long long)mask);
-      if (lane == js) {
-        aj += 1;
-        remj -= gj;
-      }
-      const uint32_t nrem = readlane_u32(remj, js);
-      if (lane > js && lane < nouter) {
-        aj = 0;
-        remj = nrem;
-      }
-      xouter = nrem;
-      aseg = 0;
-    }
-
-    if (!COUNT_ONLY && produced > flushed) {
-      flush_rows<ALIGN16>(ring, flushed & ring_mask, produced - flushed, d,
-                          out_tile + uint64_t(flushed) * d);
-    }
-    wave_sync();
-    if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
+    write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(A, tile, tstates + ti * S, ring, marks,
+                                                    lds_memo, lds_cnt, lds_endc, gj, fsh, fmk,
+                                                    csum);
   }
 
   if (COUNT_ONLY) {
@@ -457,6 +532,194 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
       atomicAdd(reinterpret_cast<unsigned long long*>(P.checksum),
                 static_cast<unsigned long long>(csum));
   }
+}
+
+// ---------------------------------------------------------------------------
+// Batched write pass: one persistent launch over the work units of many
+// queries.  A workgroup takes units (slices [tile_lo, tile_hi) of one query)
+// from a global counter, the largest units first; for each it copies the
+// query's descriptor into LDS, runs the same prologue as k_write (packed memo,
+// segment counts and class ends, slice starts), lets its wavefronts take the
+// slices from an LDS counter, and records the query's completion time when
+// its last slice is done.
+constexpr uint32_t kDescWords = uint32_t(sizeof(EnumParams) / 4);
+
+__device__ inline uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline uint64_t rfl64(uint64_t v) {
+  return (uint64_t(rfl(uint32_t(v >> 32))) << 32) | rfl(uint32_t(v));
+}
+template <class T>
+__device__ inline T* rflp(T* p) {
+  return reinterpret_cast<T*>(rfl64(reinterpret_cast<uint64_t>(p)));
+}
+
+// The descriptor fields read from LDS, made wave-uniform (scalar registers).
+__device__ inline TileArgs uniform_args(const TileArgs& a) {
+  TileArgs A;
+  A.n = rfl(a.n);
+  A.d = rfl(a.d);
+  A.U = rfl(a.U);
+  A.k = rfl(a.k);
+  A.gseg = rfl(a.gseg);
+  A.ring = rfl(a.ring);
+  A.flush = rfl(a.flush);
+  A.total = rfl64(a.total);
+  A.rows_per_tile = rfl64(a.rows_per_tile);
+  A.cnt_row = rflp(a.cnt_row);
+  A.endc = rflp(a.endc);
+  A.leaf = rflp(a.leaf);
+  A.leaf_rows = rfl64(a.leaf_rows);
+  A.out = rflp(a.out);
+  A.err = rflp(a.err);
+  A.dG.d = rfl(a.dG.d);
+  A.dG.m = rfl(a.dG.m);
+  A.dG.sh1 = rfl(a.dG.sh1);
+  A.dG.sh2 = rfl(a.dG.sh2);
+  return A;
+}
+
+template <bool COUNT_ONLY>
+__global__ __launch_bounds__(kWriteWaves * kWave) void k_write_batch(
+    const EnumParams* __restrict__ qp, const uint64_t* __restrict__ qout,
+    const BatchUnit* __restrict__ units, uint32_t nunits, uint32_t* __restrict__ queue,
+    uint32_t* __restrict__ done_tiles, uint64_t* __restrict__ t_done, uint32_t* out, BatchLds L) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  __shared__ uint32_t s_unit, next_slot;
+  const int lane = lane_id();
+  const int wave = int(threadIdx.x / kWave);
+  uint32_t* ring = lds + L.waves + uint32_t(wave) * L.wave_words;
+  uint32_t* marks = ring + L.ring_words;
+  const uint32_t* lds_memo = lds + L.memo;
+  uint32_t* lds_cnt = lds + L.cnt;
+  uint32_t* lds_endc = lds + L.endc;
+  uint32_t* tstates = lds + L.states;
+  const EnumParams& P = *reinterpret_cast<const EnumParams*>(lds + L.desc);
+
+  for (;;) {
+    if (threadIdx.x == 0) s_unit = atomicAdd(queue, 1u);
+    __syncthreads();
+    const uint32_t u = s_unit;
+    if (u >= nunits) break;
+    const uint32_t q = rfl(units[u].q);
+    const uint32_t tlo = rfl(units[u].tile_lo), thi = rfl(units[u].tile_hi);
+    const uint64_t obase = rfl64(qout[q]);
+    {
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(qp + q);
+      for (uint32_t i = threadIdx.x; i < kDescWords; i += blockDim.x) lds[L.desc + i] = src[i];
+    }
+    __syncthreads();
+    const int U = int(rfl(uint32_t(P.U))), k = int(rfl(uint32_t(P.k))), d = int(rfl(uint32_t(P.d)));
+    const int pack = int(rfl(uint32_t(P.pack))), ldscnt = int(rfl(uint32_t(P.lds_cnt)));
+    const uint32_t S = uint32_t(U + 2);
+    const uint32_t ntl = thi - tlo;
+    // Prologue: every global load for this unit, before its first store.
+    if (k >= 1 && pack > 0) {
+      const uint32_t* leaf = rflp(P.leaf);
+      const uint64_t words = rfl64(P.memo_words);
+      const uint64_t nvec = words / 4;
+      const uint4* src = reinterpret_cast<const uint4*>(leaf);
+      uint4* dst = reinterpret_cast<uint4*>(lds + L.memo);
+      for (uint64_t i = threadIdx.x; i < nvec; i += blockDim.x) dst[i] = src[i];
+      for (uint64_t w = nvec * 4 + threadIdx.x; w < words; w += blockDim.x)
+        lds[L.memo + w] = leaf[w];
+    }
+    if (k >= 1 && ldscnt) {
+      const uint64_t N = uint64_t(rfl(P.n)) + 1;
+      const uint64_t* cu = rflp(P.table) + uint64_t(U) * N;
+      const uint64_t* endc = rflp(P.endc);
+      const uint32_t nclass = rfl(P.nclass);
+      for (uint64_t x = threadIdx.x; x < N; x += blockDim.x) lds_cnt[x] = uint32_t(cu[x]);
+      for (uint32_t r = threadIdx.x; r < nclass; r += blockDim.x) lds_endc[r] = uint32_t(endc[r]);
+    }
+    {
+      const uint32_t* st = rflp(P.tiles) + uint64_t(tlo) * S;
+      for (uint32_t i = threadIdx.x; i < ntl * S; i += blockDim.x) tstates[i] = st[i];
+    }
+    if (threadIdx.x == 0) next_slot = 0;
+    const uint32_t gj = lane < d ? P.g.g[lane] : 0;
+    const uint32_t fsh = lane <= k ? P.fshift[lane] : 0;
+    const uint32_t fmk = lane <= k ? P.fmask[lane] : 0;
+    TileArgs A = uniform_args(tile_args(P));
+    A.out = out + obase;
+    __syncthreads();
+
+    uint64_t csum = 0;
+    for (;;) {
+      uint32_t slot_l = 0;
+      if (lane == 0) slot_l = atomicAdd(&next_slot, 1u);
+      const uint32_t ti = rfl(slot_l);
+      if (ti >= ntl) break;
+      const uint64_t tile = tlo + ti;
+      const uint32_t* st = tstates + ti * S;
+#define ZSET_TILE(MODE, PACK, LDSCNT)                                                         \
+  write_tile<MODE, COUNT_ONLY, true, PACK, LDSCNT>(A, tile, st, ring, marks, lds_memo, lds_cnt, \
+                                                    lds_endc, gj, fsh, fmk, csum)
+      if (k == 0) {
+        ZSET_TILE(0, 0, false);
+      } else if (pack == 1) {
+        if (ldscnt) ZSET_TILE(1, 1, true); else ZSET_TILE(1, 1, false);
+      } else if (pack == 2) {
+        if (ldscnt) ZSET_TILE(1, 2, true); else ZSET_TILE(1, 2, false);
+      } else {
+        if (ldscnt) ZSET_TILE(1, 0, true); else ZSET_TILE(1, 0, false);
+      }
+#undef ZSET_TILE
+    }
+    if (COUNT_ONLY) {
+#pragma unroll
+      for (int off = kWave / 2; off >= 1; off >>= 1) csum += __shfl_xor(csum, off, kWave);
+      if (lane == 0 && csum != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(rflp(P.checksum)),
+                  static_cast<unsigned long long>(csum));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const uint32_t before = atomicAdd(done_tiles + q, ntl);
+      if (uint64_t(before) + ntl == rfl64(P.ntiles)) t_done[q] = wall_clock64();
+    }
+  }
+}
+
+// Clears the per-run state of a batch (a kernel, not a memset node, so that
+// it can sit in a captured graph) and stamps the start time.
+__global__ __launch_bounds__(256) void k_batch_reset(uint32_t* queue, int* err,
+                                                     uint32_t* done_tiles, uint64_t* checksums,
+                                                     uint64_t* t_done, uint64_t* t_start,
+                                                     uint32_t nq) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i == 0) {
+    *queue = 0;
+    *err = 0;
+    *t_start = wall_clock64();
+  }
+  if (i < nq) {
+    done_tiles[i] = 0;
+    checksums[i] = 0;
+    t_done[i] = 0;
+  }
+}
+
+// d = 1 queries of a batch: at most one row each.
+__global__ __launch_bounds__(256) void k_single_batch(const EnumParams* __restrict__ qp,
+                                                      const uint64_t* __restrict__ qout,
+                                                      const uint32_t* __restrict__ idx,
+                                                      uint32_t count, uint32_t* out,
+                                                      int count_only, uint64_t* t_done) {
+  const uint32_t i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t q = idx[i];
+  const EnumParams& P = qp[q];
+  const uint32_t g = P.g.g[0];
+  if (P.n % g == 0) {
+    if (count_only) {
+      uint64_t h = fnv1a_u64(kFnvOffset, 0);
+      h = fnv1a_u32(h, P.n / g);
+      *P.checksum += h;
+    } else {
+      out[qout[q]] = P.n / g;
+    }
+  }
+  t_done[q] = wall_clock64();
 }
 
 // d = 1: Z(n; g_1) is {n / g_1} when g_1 divides n.
@@ -566,6 +829,73 @@ hipError_t launch_plan(const EnumParams& P, hipStream_t s) {
 
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s) {
   return dispatch<LaunchF>(P, count_only, align16, s);
+}
+
+int write_batch_waves() { return kWriteWaves; }
+
+hipError_t launch_batch_reset(uint32_t* queue, int* err, uint32_t* done_tiles,
+                              uint64_t* checksums, uint64_t* t_done, uint64_t* t_start,
+                              uint32_t nq, hipStream_t s) {
+  const uint32_t blocks = (nq + 255) / 256 + 1;
+  hipLaunchKernelGGL(k_batch_reset, dim3(blocks), dim3(256), 0, s, queue, err, done_tiles,
+                     checksums, t_done, t_start, nq);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_batch(const EnumParams* qp, const uint64_t* tile_base,
+                             const uint32_t* plan_q, uint32_t nplan, uint64_t total_tiles,
+                             hipStream_t s) {
+  if (total_tiles == 0 || nplan == 0) return hipSuccess;
+  const uint64_t blocks = (total_tiles + 255) / 256;
+  hipLaunchKernelGGL(k_plan_batch, dim3(uint32_t(blocks)), dim3(256), 0, s, qp, tile_base, plan_q,
+                     nplan, total_tiles);
+  return hipGetLastError();
+}
+
+template <bool CO>
+hipError_t prepare_write_batch_t(const BatchLds& L) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_write_batch<CO>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(size_t(L.total_words) * 4));
+}
+
+hipError_t prepare_write_batch(const BatchLds& L, bool count_only) {
+  return count_only ? prepare_write_batch_t<true>(L) : prepare_write_batch_t<false>(L);
+}
+
+hipError_t write_batch_occupancy(const BatchLds& L, bool count_only, int* per_cu) {
+  hipError_t e = prepare_write_batch(L, count_only);
+  if (e != hipSuccess) return e;
+  const size_t lds = size_t(L.total_words) * 4;
+  if (count_only)
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_write_batch<true>,
+                                                        kWriteWaves * kWave, lds);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_write_batch<false>,
+                                                      kWriteWaves * kWave, lds);
+}
+
+hipError_t launch_write_batch(const EnumParams* qp, const uint64_t* qout, const BatchUnit* units,
+                              uint32_t nunits, uint32_t* queue, uint32_t* done_tiles,
+                              uint64_t* t_done, uint32_t* out, const BatchLds& L,
+                              uint32_t blocks, bool count_only, hipStream_t s) {
+  if (nunits == 0) return hipSuccess;
+  const size_t lds = size_t(L.total_words) * 4;
+  if (count_only)
+    hipLaunchKernelGGL(k_write_batch<true>, dim3(blocks), dim3(kWriteWaves * kWave), lds, s, qp,
+                       qout, units, nunits, queue, done_tiles, t_done, out, L);
+  else
+    hipLaunchKernelGGL(k_write_batch<false>, dim3(blocks), dim3(kWriteWaves * kWave), lds, s, qp,
+                       qout, units, nunits, queue, done_tiles, t_done, out, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_single_batch(const EnumParams* qp, const uint64_t* qout, const uint32_t* idx,
+                               uint32_t count, uint32_t* out, bool count_only, uint64_t* t_done,
+                               hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_single_batch, dim3((count + 255) / 256), dim3(256), 0, s, qp, qout, idx,
+                     count, out, int(count_only), t_done);
+  return hipGetLastError();
 }
 
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,

@@ -15,7 +15,8 @@
 // 2.2, elementwise parallelism); inside a batch every copied row is its own
 // work item (factorizationwise parallelism, Alg 2.9).
 //
-// Two schedules compute the same natural-order memo:
+// For k = 1 the recurrence's solution is closed (k_memo_k1).  For k >= 2 two
+// schedules compute the same natural-order memo:
 //  * k_memo_chain_wave: one wavefront keeps the whole memo in LDS and saves
 //    the cardinalities |Z_{>=i}(p)| as it goes (Section 2.3), in a ring of the
 //    last W elements, so a batch costs a few LDS round trips and no barrier.
@@ -30,6 +31,8 @@
 // Z(x; G, h) = {(a, m) : m in Memo[x - a G]} are one contiguous run that
 // starts at end[x mod G] - |Z(x; G, h)|, in ascending lex order, and each
 // memo row carries floor(p / G) so that a = floor(x / G) - floor(p / G).
+#include <cstring>
+
 #include "zset_internal.h"
 
 namespace zset {
@@ -60,13 +63,10 @@ __device__ inline uint32_t wave_incl_sum_u32(uint32_t v) {
 // Dynamic LDS layout (uint32): M[R*k] | GE[W*k] | OFF[W]; W a power of two
 // >= max(h) + step.
 template <int KMAX>
-__global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32_t top,
-                                                            uint32_t step, uint32_t W,
-                                                            uint32_t R,
-                                                            uint32_t* __restrict__ nat,
-                                                            uint64_t* __restrict__ off_out,
-                                                            int* __restrict__ err) {
-  extern __shared__ uint32_t lds[];
+__device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32_t top,
+                                       uint32_t step, uint32_t W, uint32_t R,
+                                       uint32_t* __restrict__ nat, uint64_t* __restrict__ off_out,
+                                       int* __restrict__ err, uint32_t* lds) {
   uint32_t* M = lds;
   uint32_t* GE = M + size_t(R) * k;
   uint32_t* OFF = GE + size_t(W) * k;
@@ -96,8 +96,8 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32
     for (int i = 0; i < KMAX; ++i) {
       s[i] = 0;
       so[i] = 0;
-      if (i < k && valid && p >= h.g[i]) {
-        const uint32_t slot = (p - h.g[i]) & Wm;
+      if (i < k && valid && p >= hg[i]) {
+        const uint32_t slot = (p - hg[i]) & Wm;
         s[i] = GE[slot * k + i];
         so[i] = OFF[slot];
       }
@@ -151,6 +151,66 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32
   uint4* dstv = reinterpret_cast<uint4*>(nat);
   for (uint32_t v = lane; v < nvec; v += kWave) dstv[v] = src[v];
   for (uint32_t w = nvec * 4 + lane; w < words; w += kWave) nat[w] = M[w];
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32_t top,
+                                                            uint32_t step, uint32_t W,
+                                                            uint32_t R,
+                                                            uint32_t* __restrict__ nat,
+                                                            uint64_t* __restrict__ off_out,
+                                                            int* __restrict__ err) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t hg[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) hg[i] = h.g[i];
+  memo_chain_wave<KMAX>(hg, k, top, step, W, R, nat, off_out, err, lds);
+}
+
+// Batched: workgroup b (one wavefront) builds the memo of jobs[b].
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void k_memo_chain_batch(const MemoJob* __restrict__ jobs,
+                                                             int* __restrict__ err) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  const MemoJob& J = jobs[blockIdx.x];
+  uint32_t hg[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) hg[i] = __builtin_amdgcn_readfirstlane(J.h[i]);
+  const int k = __builtin_amdgcn_readfirstlane(J.k);
+  const uint32_t top = __builtin_amdgcn_readfirstlane(J.top);
+  const uint32_t step = __builtin_amdgcn_readfirstlane(J.step);
+  const uint32_t W = __builtin_amdgcn_readfirstlane(J.W);
+  const uint32_t R = __builtin_amdgcn_readfirstlane(J.R);
+  memo_chain_wave<KMAX>(hg, k, top, step, W, R, J.nat, J.off, err, lds);
+}
+
+// k = 1: the recurrence Memo[p] = incr_1(Memo[p - h]) from Memo[0] = {()}
+// has the solution Memo[p] = {(p / h)} when h divides p and {} otherwise
+// (induction on p), so every element is independent: row j (the element
+// p = j h) holds j and off[p] = ceil(p / h).  One pass, no batches.
+__device__ inline void memo_k1_item(uint32_t h, uint32_t top, uint32_t R, uint64_t i,
+                                    uint32_t* __restrict__ nat, uint64_t* __restrict__ off) {
+  if (i <= top) off[i] = (i + h - 1) / h;
+  if (i < R) nat[i] = uint32_t(i);
+}
+
+__global__ __launch_bounds__(256) void k_memo_k1(uint32_t h, uint32_t top, uint32_t R,
+                                                 uint32_t* __restrict__ nat,
+                                                 uint64_t* __restrict__ off) {
+  memo_k1_item(h, top, R, uint64_t(blockIdx.x) * 256 + threadIdx.x, nat, off);
+}
+
+// Batched: the workgroups of job j are [jobs[j].block0, jobs[j + 1].block0).
+__global__ __launch_bounds__(256) void k_memo_k1_batch(const MemoJob* __restrict__ jobs,
+                                                       uint32_t njobs) {
+  uint32_t lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (jobs[mid].block0 <= blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const MemoJob& J = jobs[lo];
+  memo_k1_item(J.h[0], J.top, J.R, uint64_t(blockIdx.x - J.block0) * 256 + threadIdx.x, J.nat,
+               J.off);
 }
 
 // Sources of every destination row, from the count table.  Row j of Memo[p]
@@ -207,39 +267,50 @@ __global__ __launch_bounds__(256) void k_memo_batch(int k, const uint64_t* __res
 // pos(p) + t with pos(p) = end[p mod G] - cu[p]; it is stored as the fields
 // (floor(p / G), m_1..m_k): k+1 plain words (pack 0), or packed into one 32-
 // or 64-bit word at the bit offsets of the write pass (pack 1, 2).
-__global__ __launch_bounds__(256) void k_memo_leaf(int k, uint32_t n, DivMod32 dG,
-                                                   const uint64_t* __restrict__ off,
-                                                   const uint32_t* __restrict__ nat,
-                                                   const uint64_t* __restrict__ cu,
-                                                   const uint64_t* __restrict__ endc,
-                                                   uint32_t* __restrict__ leaf,
-                                                   uint64_t leaf_rows, EnumParams P,
-                                                   int* __restrict__ err) {
-  const uint64_t p64 = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p64 > n) return;
-  const uint32_t p = uint32_t(p64);
-  const uint32_t q = dG.div(p);
-  const uint32_t rho = dG.mod(p, q);
-  const uint64_t pos = endc[rho] - cu[p];
-  const uint64_t o = off[p];
-  const uint64_t cnt = off[p + 1] - o;
-  if (pos > leaf_rows || cnt > leaf_rows - pos) {
+__device__ inline void memo_leaf_element(const LeafJob& J, uint32_t p, int* __restrict__ err) {
+  const int k = J.k;
+  const uint32_t q = J.dG.div(p);
+  const uint32_t rho = J.dG.mod(p, q);
+  const uint64_t pos = J.endc[rho] - J.cu[p];
+  const uint64_t o = J.off[p];
+  const uint64_t cnt = J.off[p + 1] - o;
+  if (pos > J.leaf_rows || cnt > J.leaf_rows - pos) {
     set_error(err, kErrMemoTotal);
     return;
   }
   for (uint64_t t = 0; t < cnt; ++t) {
-    const uint32_t* src = nat + (o + t) * k;
-    if (P.pack == 0) {
-      uint32_t* dst = leaf + (pos + t) * (k + 1);
+    const uint32_t* src = J.nat + (o + t) * k;
+    if (J.pack == 0) {
+      uint32_t* dst = J.leaf + (pos + t) * (k + 1);
       dst[0] = q;
       for (int c = 0; c < k; ++c) dst[1 + c] = src[c];
     } else {
-      uint64_t w = uint64_t(q) << P.fshift[0];
-      for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << P.fshift[1 + c];
-      if (P.pack == 1) leaf[pos + t] = uint32_t(w);
-      else reinterpret_cast<uint64_t*>(leaf)[pos + t] = w;
+      uint64_t w = uint64_t(q) << J.fshift[0];
+      for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << J.fshift[1 + c];
+      if (J.pack == 1) J.leaf[pos + t] = uint32_t(w);
+      else reinterpret_cast<uint64_t*>(J.leaf)[pos + t] = w;
     }
   }
+}
+
+__global__ __launch_bounds__(256) void k_memo_leaf(LeafJob J, int* __restrict__ err) {
+  const uint64_t p64 = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p64 > J.n) return;
+  memo_leaf_element(J, uint32_t(p64), err);
+}
+
+// Batched: the workgroups of job j are [jobs[j].block0, jobs[j + 1].block0).
+__global__ __launch_bounds__(256) void k_memo_leaf_batch(const LeafJob* __restrict__ jobs,
+                                                         uint32_t njobs, int* __restrict__ err) {
+  uint32_t lo = 0, hi = njobs - 1;  // last job whose block0 <= blockIdx.x
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi + 1) / 2;
+    if (jobs[mid].block0 <= blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const LeafJob& J = jobs[lo];
+  const uint64_t p64 = uint64_t(blockIdx.x - J.block0) * 256 + threadIdx.x;
+  if (p64 > J.n) return;
+  memo_leaf_element(J, uint32_t(p64), err);
 }
 
 }  // namespace
@@ -268,6 +339,22 @@ hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32
   return go(k_memo_chain_wave<kMaxD>);
 }
 
+uint32_t memo_k1_blocks(uint64_t top) { return uint32_t((top + 1 + 255) / 256); }
+
+hipError_t launch_memo_k1(uint32_t h, uint64_t top, uint64_t R, uint32_t* nat, uint64_t* off,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_memo_k1, dim3(memo_k1_blocks(top)), dim3(256), 0, s, h, uint32_t(top),
+                     uint32_t(R), nat, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_memo_k1_batch(const MemoJob* jobs, uint32_t njobs, uint32_t blocks,
+                                hipStream_t s) {
+  if (njobs == 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_memo_k1_batch, dim3(blocks), dim3(256), 0, s, jobs, njobs);
+  return hipGetLastError();
+}
+
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s) {
@@ -288,14 +375,55 @@ hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b
   return hipSuccess;
 }
 
-hipError_t launch_memo_leaf(int k, uint64_t n, uint32_t G, const uint64_t* off,
-                            const uint32_t* nat, const uint64_t* cu, const uint64_t* endc,
-                            uint32_t* leaf, uint64_t leaf_rows, const EnumParams& P, int* err,
-                            hipStream_t s) {
-  const uint32_t blocks = uint32_t((n + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_memo_leaf, dim3(blocks), dim3(256), 0, s, k, uint32_t(n),
-                     DivMod32::make(G), off, nat, cu, endc, leaf, leaf_rows, P, err);
+LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const uint32_t* nat,
+                      const uint64_t* cu, const uint64_t* endc, uint32_t* leaf,
+                      uint64_t leaf_rows, const EnumParams& P) {
+  LeafJob J;
+  std::memset(&J, 0, sizeof J);
+  J.k = k;
+  J.n = uint32_t(n);
+  J.dG = DivMod32::make(G);
+  J.off = off;
+  J.nat = nat;
+  J.cu = cu;
+  J.endc = endc;
+  J.leaf = leaf;
+  J.leaf_rows = leaf_rows;
+  J.pack = P.pack;
+  for (int c = 0; c <= k; ++c) J.fshift[c] = P.fshift[c];
+  return J;
+}
+
+hipError_t launch_memo_leaf(const LeafJob& J, int* err, hipStream_t s) {
+  const uint32_t blocks = uint32_t((uint64_t(J.n) + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_memo_leaf, dim3(blocks), dim3(256), 0, s, J, err);
   return hipGetLastError();
+}
+
+hipError_t launch_memo_leaf_batch(const LeafJob* jobs, uint32_t njobs, uint32_t blocks,
+                                  int* err, hipStream_t s) {
+  if (njobs == 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_memo_leaf_batch, dim3(blocks), dim3(256), 0, s, jobs, njobs, err);
+  return hipGetLastError();
+}
+
+template <int KMAX>
+hipError_t chain_batch_t(const MemoJob* jobs, uint32_t njobs, size_t lds, int* err,
+                         hipStream_t s, bool prepare) {
+  auto kern = k_memo_chain_batch<KMAX>;
+  if (prepare)
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipLaunchKernelGGL(kern, dim3(njobs), dim3(kWave), lds, s, jobs, err);
+  return hipGetLastError();
+}
+
+// kmax_class: 8 for k <= 8, 32 otherwise.
+hipError_t launch_memo_chain_batch(const MemoJob* jobs, uint32_t njobs, int kmax_class,
+                                   size_t lds_bytes, int* err, hipStream_t s, bool prepare) {
+  if (njobs == 0) return hipSuccess;
+  if (kmax_class <= 8) return chain_batch_t<8>(jobs, njobs, lds_bytes, err, s, prepare);
+  return chain_batch_t<kMaxD>(jobs, njobs, lds_bytes, err, s, prepare);
 }
 
 }  // namespace zset

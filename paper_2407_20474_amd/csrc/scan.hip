@@ -96,7 +96,27 @@ __global__ __launch_bounds__(kScanThreads) void k_class_ends(const uint64_t* __r
   });
 }
 
+// Batched: workgroup b lays out the class ends of jobs[b].
+__global__ __launch_bounds__(kScanThreads) void k_class_ends_batch(
+    const ClassJob* __restrict__ jobs) {
+  const ClassJob& J = jobs[blockIdx.x];
+  const uint64_t* CU = J.cu;
+  const uint32_t n = J.n;
+  const DivMod32 dG = J.dG;
+  scan_chunks(J.nclass, J.endc, true, [&](uint64_t r) {
+    const uint32_t rr = uint32_t(r);
+    const uint32_t q = dG.div(n - rr);
+    return CU[uint64_t(rr) + uint64_t(q) * dG.d];
+  });
+}
+
 }  // namespace
+
+hipError_t launch_class_ends_batch(const ClassJob* jobs, uint32_t njobs, hipStream_t s) {
+  if (njobs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_class_ends_batch, dim3(njobs), dim3(kScanThreads), 0, s, jobs);
+  return hipGetLastError();
+}
 
 hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t count, uint64_t* out,
                                  hipStream_t s) {

@@ -42,16 +42,76 @@ struct EnumParams {
   uint32_t write_blocks;    // workgroups of the write pass; slice t goes to workgroup t mod NB
 };
 
+// One query's share of a batched launch.
+struct CountJob {
+  uint64_t* table;          // (d+1) x N
+  uint64_t* sums;           // d+1 row sums
+  uint64_t* total;          // C[0][n]
+  uint32_t N;               // n + 1
+  int d;
+  uint32_t g[kMaxD];
+};
+
+struct MemoJob {
+  uint32_t h[kMaxD];        // memo generators
+  int k;
+  uint32_t top, step, W, R; // elements, batch width, ring size, rows
+  uint32_t* nat;            // R x k natural-order rows
+  uint64_t* off;            // top + 1 offsets
+  uint32_t block0;          // batched k = 1 pass: first workgroup of this job
+};
+
+struct LeafJob {
+  int k;
+  uint32_t n;
+  DivMod32 dG;              // division by g_U
+  const uint64_t* off;
+  const uint32_t* nat;
+  const uint64_t* cu;       // count-table row U
+  const uint64_t* endc;
+  uint32_t* leaf;
+  uint64_t leaf_rows;
+  int pack;
+  uint32_t block0;          // batched: first workgroup of this job
+  uint32_t fshift[kMaxD + 1];
+};
+
+struct ClassJob {
+  const uint64_t* cu;       // count-table row U
+  uint64_t* endc;
+  uint32_t n;
+  uint32_t nclass;
+  DivMod32 dG;
+};
+
+// A batched write-pass work unit: slices [tile_lo, tile_hi) of query q.
+struct BatchUnit {
+  uint32_t q, tile_lo, tile_hi, pad;
+};
+
+// LDS layout (uint32 words) of the batched write pass.
+struct BatchLds {
+  uint32_t desc, memo, cnt, endc, states, waves;  // region offsets
+  uint32_t wave_words;      // per wavefront: staging ring + 64 marks
+  uint32_t ring_words;      // staging ring words (ring rows x largest d)
+  uint32_t total_words;
+};
+
 // count_table.hip
 // Count table (d+1) x (n+1); when sums is non-NULL also sums[j] = sum_x C[j][x].
 hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens, int d,
                               uint64_t* sums, hipStream_t s);
+uint32_t count_table_lds_max();
+hipError_t prepare_count_table_batch(uint32_t max_lds_n);
+hipError_t launch_count_table_batch(const CountJob* jobs, uint32_t njobs, uint32_t max_lds_n,
+                                    bool lds, hipStream_t s);
 
 // scan.hip
 hipError_t launch_exclusive_scan(const uint64_t* in, uint64_t count, uint64_t* out,
                                  hipStream_t s);
 hipError_t launch_class_ends(const uint64_t* count_row_u, uint64_t n, uint32_t G,
                              uint64_t* endc, uint32_t* nclass_out, hipStream_t s);
+hipError_t launch_class_ends_batch(const ClassJob* jobs, uint32_t njobs, hipStream_t s);
 
 // memo.hip
 size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W);
@@ -61,10 +121,21 @@ hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);
-hipError_t launch_memo_leaf(int k, uint64_t n, uint32_t G, const uint64_t* off,
-                            const uint32_t* nat, const uint64_t* cu, const uint64_t* endc,
-                            uint32_t* leaf, uint64_t leaf_rows, const EnumParams& P, int* err,
-                            hipStream_t s);
+LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const uint32_t* nat,
+                      const uint64_t* cu, const uint64_t* endc, uint32_t* leaf,
+                      uint64_t leaf_rows, const EnumParams& P);
+hipError_t launch_memo_leaf(const LeafJob& J, int* err, hipStream_t s);
+hipError_t launch_memo_leaf_batch(const LeafJob* jobs, uint32_t njobs, uint32_t blocks,
+                                  int* err, hipStream_t s);
+// k = 1: the closed solution of the recurrence, one parallel pass.
+uint32_t memo_k1_blocks(uint64_t top);
+hipError_t launch_memo_k1(uint32_t h, uint64_t top, uint64_t R, uint32_t* nat, uint64_t* off,
+                          hipStream_t s);
+hipError_t launch_memo_k1_batch(const MemoJob* jobs, uint32_t njobs, uint32_t blocks,
+                                hipStream_t s);
+// prepare = true only sets the launch attributes (before graph capture).
+hipError_t launch_memo_chain_batch(const MemoJob* jobs, uint32_t njobs, int kmax_class,
+                                   size_t lds_bytes, int* err, hipStream_t s, bool prepare);
 
 // enumerate.hip
 size_t write_lds_bytes(const EnumParams& P);
@@ -75,5 +146,24 @@ hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipS
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,
                          uint64_t* checksum, hipStream_t s);
 hipError_t launch_reverse(uint32_t* out, uint64_t rows, int d, hipStream_t s);
+
+// Batched forms (batch.hip drives them).  qp: one EnumParams per query;
+// qout: each query's first output word.
+int write_batch_waves();
+hipError_t launch_batch_reset(uint32_t* queue, int* err, uint32_t* done_tiles,
+                              uint64_t* checksums, uint64_t* t_done, uint64_t* t_start,
+                              uint32_t nq, hipStream_t s);
+hipError_t launch_plan_batch(const EnumParams* qp, const uint64_t* tile_base,
+                             const uint32_t* plan_q, uint32_t nplan, uint64_t total_tiles,
+                             hipStream_t s);
+hipError_t prepare_write_batch(const BatchLds& L, bool count_only);
+hipError_t write_batch_occupancy(const BatchLds& L, bool count_only, int* per_cu);
+hipError_t launch_write_batch(const EnumParams* qp, const uint64_t* qout, const BatchUnit* units,
+                              uint32_t nunits, uint32_t* queue, uint32_t* done_tiles,
+                              uint64_t* t_done, uint32_t* out, const BatchLds& L,
+                              uint32_t blocks, bool count_only, hipStream_t s);
+hipError_t launch_single_batch(const EnumParams* qp, const uint64_t* qout, const uint32_t* idx,
+                               uint32_t count, uint32_t* out, bool count_only, uint64_t* t_done,
+                               hipStream_t s);
 
 }  // namespace zset

@@ -42,3 +42,46 @@ def random_small_query(rng: np.random.Generator, dmax: int = 6, gmax: int = 40,
 def load_workloads() -> dict:
     with open(WORKLOADS) as f:
         return json.load(f)
+
+
+def draw_query_specs(seed: int, count: int, dlo: int = 3, dhi: int = 8, glo: int = 5,
+                     ghi: int = 150, log_lo: float = 2.0, log_hi: float = 7.0):
+    """Random (generators, row target) pairs of a batch of independent queries:
+    d uniform in [dlo, dhi], distinct generators uniform in [glo, ghi] with gcd 1
+    (redrawn on the same stream), sorted ascending, and a row target
+    ceil(10^u) with u uniform in [log_lo, log_hi] (log-uniform sizes).  Each
+    query's n -- the smallest element whose |Z(n)| reaches the target -- is
+    fixed by tests/golden/make_workloads.py."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    pool = np.arange(glo, ghi + 1)
+    for _ in range(count):
+        d = int(rng.integers(dlo, dhi + 1))
+        while True:
+            g = rng.choice(pool, size=d, replace=False)
+            if reduce(math.gcd, (int(x) for x in g)) == 1:
+                break
+        target = int(math.ceil(10.0 ** rng.uniform(log_lo, log_hi)))
+        specs.append((sorted(int(x) for x in g), target))
+    return specs
+
+
+def load_query_file(path: str):
+    """Rows 'n rows g_1 ... g_d' of a stored query list -> [(n, gens, rows)]."""
+    out = []
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            v = [int(x) for x in line.split()]
+            out.append((v[0], v[2:], v[1]))
+    return out
+
+
+BATCH_QUERIES = os.path.join(ROOT, "tests", "golden", "batch_queries.txt")
+
+
+def load_batch_queries():
+    """The 4096-query batched workload: [(n, gens, rows)]."""
+    return load_query_file(BATCH_QUERIES)

@@ -23,6 +23,8 @@ MAX_D = 32
 SYMBOLS = (
     "zset_default_opts", "zset_count", "zset_count_table", "zset_memo_build",
     "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
+    "zset_batch_default_opts", "zset_batch_create", "zset_batch_info", "zset_batch_run",
+    "zset_batch_times", "zset_batch_free",
     "zset_strerror", "zset_selftest_host", "zset_last_error",
 )
 
@@ -40,6 +42,24 @@ class Stats(ctypes.Structure):
                 ("memo_rows", ctypes.c_uint64), ("memo_bytes", ctypes.c_uint64),
                 ("tiles", ctypes.c_uint64), ("rows_per_tile", ctypes.c_uint64),
                 ("k", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("count_only", ctypes.c_int), ("max_chain_steps", ctypes.c_uint32),
+                ("unit_tiles", ctypes.c_uint32), ("use_graph", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("total_us", ctypes.c_double), ("count_us", ctypes.c_double),
+                ("memo_us", ctypes.c_double), ("plan_us", ctypes.c_double),
+                ("write_us", ctypes.c_double), ("rows", ctypes.c_uint64),
+                ("words", ctypes.c_uint64), ("tiles", ctypes.c_uint64),
+                ("units", ctypes.c_uint32), ("memo_queries", ctypes.c_uint32),
+                ("write_blocks", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -83,13 +103,25 @@ def load():
     lib.zset_enumerate_ex.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
                                       _u64p, _u64p, ctypes.POINTER(Stats)]
+    lib.zset_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
+    lib.zset_batch_default_opts.restype = None
+    _i32p = ctypes.POINTER(ctypes.c_int)
+    lib.zset_batch_create.argtypes = [ctypes.c_int, _u64p, _i32p, _u32p, _i32p, _u64p,
+                                      ctypes.POINTER(BatchOpts), ctypes.POINTER(ctypes.c_void_p)]
+    lib.zset_batch_info.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p, _i32p, _u64p]
+    lib.zset_batch_run.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, _u64p,
+                                   ctypes.POINTER(BatchStats)]
+    lib.zset_batch_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
+    lib.zset_batch_free.argtypes = [ctypes.c_void_p]
+    lib.zset_batch_free.restype = None
     lib.zset_strerror.argtypes = [ctypes.c_int]
     lib.zset_strerror.restype = ctypes.c_char_p
     lib.zset_selftest_host.argtypes = []
     lib.zset_last_error.argtypes = []
     lib.zset_last_error.restype = ctypes.c_char_p
     for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
-                 "zset_enumerate", "zset_enumerate_ex", "zset_selftest_host"):
+                 "zset_enumerate", "zset_enumerate_ex", "zset_batch_create", "zset_batch_info",
+                 "zset_batch_run", "zset_batch_times", "zset_selftest_host"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -239,3 +271,101 @@ def enumerate(n: int, gens, out=None):
     _check(load().zset_enumerate(n, g.ctypes.data_as(_u32p), d, out.data_ptr()),
            "zset_enumerate")
     return out[:rows]
+
+
+@dataclass
+class BatchResult:
+    checksums: np.ndarray   # per query (count-only batches; zeros otherwise)
+    stats: dict
+    out: object = None      # int32 CUDA tensor of total_words elements
+
+
+class Batch:
+    """Many independent queries planned once (zset_batch_create) and run by one
+    persistent write launch per run (zset_batch_run).  `queries` is a list of
+    (n, gens); `k` and `rows_per_tile` are None (automatic) or one value per
+    query (-1 / 0 = automatic)."""
+
+    def __init__(self, queries, *, k=None, rows_per_tile=None, count_only: bool = False,
+                 max_chain_steps: int = 0, unit_tiles: int = 0, use_graph: bool = True,
+                 stream=None):
+        self.nq = len(queries)
+        if self.nq == 0:
+            raise ValueError("a batch needs at least one query")
+        ns = np.ascontiguousarray([int(n) for n, _ in queries], dtype=np.uint64)
+        gl = [_gens(g) for _, g in queries]
+        ds = np.ascontiguousarray([len(g) for g in gl], dtype=np.int32)
+        gens = np.ascontiguousarray(np.concatenate(gl) if gl else np.zeros(0), dtype=np.uint32)
+        self.d = ds.astype(np.int64)
+        self.gens = [list(map(int, g)) for g in gl]
+        self.n = ns.astype(np.int64)
+        kk = None if k is None else np.ascontiguousarray(k, dtype=np.int32)
+        tt = None if rows_per_tile is None else np.ascontiguousarray(rows_per_tile,
+                                                                     dtype=np.uint64)
+        opts = BatchOpts()
+        load().zset_batch_default_opts(ctypes.byref(opts))
+        opts.count_only = 1 if count_only else 0
+        opts.max_chain_steps = max_chain_steps
+        opts.unit_tiles = unit_tiles
+        opts.use_graph = 1 if use_graph else 0
+        opts.stream = _stream_handle(stream)
+        self.count_only = count_only
+        handle = ctypes.c_void_p(None)
+        _i32p = ctypes.POINTER(ctypes.c_int)
+        _check(load().zset_batch_create(
+            self.nq, ns.ctypes.data_as(_u64p), ds.ctypes.data_as(_i32p),
+            gens.ctypes.data_as(_u32p),
+            kk.ctypes.data_as(_i32p) if kk is not None else None,
+            tt.ctypes.data_as(_u64p) if tt is not None else None,
+            ctypes.byref(opts), ctypes.byref(handle)), "zset_batch_create")
+        self._handle = handle
+        total = ctypes.c_uint64()
+        self.rows = np.zeros(self.nq, dtype=np.uint64)
+        self.offsets = np.zeros(self.nq, dtype=np.uint64)
+        self.k = np.zeros(self.nq, dtype=np.int32)
+        self.tiles = np.zeros(self.nq, dtype=np.uint64)
+        _check(load().zset_batch_info(self._handle, ctypes.byref(total),
+                                      self.rows.ctypes.data_as(_u64p),
+                                      self.offsets.ctypes.data_as(_u64p),
+                                      self.k.ctypes.data_as(_i32p),
+                                      self.tiles.ctypes.data_as(_u64p)), "zset_batch_info")
+        self.total_words = int(total.value)
+
+    def alloc(self):
+        import torch
+        return torch.empty(max(self.total_words, 4), dtype=torch.int32, device="cuda")
+
+    def run(self, out=None) -> BatchResult:
+        if out is None and not self.count_only:
+            out = self.alloc()
+        cs = np.zeros(self.nq, dtype=np.uint64)
+        st = BatchStats()
+        ptr = out.data_ptr() if out is not None else None
+        cap = out.numel() if out is not None else 0
+        _check(load().zset_batch_run(self._handle, ptr, cap, cs.ctypes.data_as(_u64p),
+                                     ctypes.byref(st)), "zset_batch_run")
+        return BatchResult(checksums=cs, stats=st.as_dict(), out=out)
+
+    def rows_of(self, out, q: int):
+        """Query q's rows in `out` as an int32 (|Z_q|, d_q) view."""
+        o, r, d = int(self.offsets[q]), int(self.rows[q]), int(self.d[q])
+        return out[o:o + r * d].view(r, d)
+
+    def times(self) -> np.ndarray:
+        """Per-query completion times of the last run, microseconds from its start."""
+        t = np.zeros(self.nq, dtype=np.float64)
+        _check(load().zset_batch_times(self._handle,
+                                       t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "zset_batch_times")
+        return t
+
+    def free(self):
+        if self._handle is not None and self._handle.value:
+            load().zset_batch_free(self._handle)
+        self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

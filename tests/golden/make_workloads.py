@@ -9,6 +9,10 @@ oracle's count table (oracle/ only -- nothing here touches the HIP path).
              |Z(n)| >= 2e8; k = 2
   sweep      d = 5, 7, 9 (seed = d), g distinct in [10, 200], gcd 1, sorted;
              |Z(n)| >= 10^8 * sqrt(10) (log-midpoint of [1e8, 1e9]); k = 0..3
+
+and tests/golden/batch_queries.txt: the batched workload, 4096 independent
+queries (seed 4) with d uniform in {3..8}, distinct generators in [5, 150]
+with gcd 1, sorted, and |Z(n)| log-uniform in [1e2, 1e7] (inputs.draw_query_specs).
 """
 import json
 import math
@@ -22,7 +26,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import oracle  # noqa: E402
-from paper_2407_20474_amd.inputs import draw_gens  # noqa: E402
+from paper_2407_20474_amd.inputs import BATCH_QUERIES, draw_gens, draw_query_specs  # noqa: E402
 
 
 def smallest_n(g, target, nmax):
@@ -32,6 +36,27 @@ def smallest_n(g, target, nmax):
         raise ValueError(f"no n <= {nmax} reaches {target} for {g}")
     n = int(hit[0])
     return n, int(ways[n])
+
+
+def smallest_n_grow(g, target):
+    """smallest_n with the table bound doubled until the target is reached."""
+    nmax = 256
+    while True:
+        try:
+            return smallest_n(g, target, nmax)
+        except ValueError:
+            nmax *= 2
+
+
+def write_batch():
+    specs = draw_query_specs(4, 4096)
+    lines = ["# n rows g_1 ... g_d  (seed 4: d in {3..8}, g in [5, 150], |Z| log-uniform "
+             "in [1e2, 1e7])"]
+    for g, target in specs:
+        n, rows = smallest_n_grow(g, target)
+        lines.append(" ".join(str(v) for v in [n, rows] + g))
+    with open(BATCH_QUERIES, "w") as f:
+        f.write("\n".join(lines) + "\n")
 
 
 def main():
@@ -52,6 +77,7 @@ def main():
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out, indent=1))
+    write_batch()
 
 
 if __name__ == "__main__":

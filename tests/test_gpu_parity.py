@@ -60,7 +60,8 @@ def assert_same(got, want, what):
 def test_count_table_matches_oracle():
     rng = np.random.default_rng(11)
     cases = [(2000, [7, 11, 13, 17]), (10130, [13, 34, 37, 54, 65, 83]), (0, [5]),
-             (3000, [1, 1, 2]), (500, [600, 7, 3])]
+             (3000, [1, 1, 2]), (500, [600, 7, 3]), (16383, [5, 9, 4]), (16384, [5, 9, 4]),
+             (20000, [3, 5, 7]), (77847, [14, 99, 135, 161, 163])]
     for _ in range(20):
         cases.append(inputs.random_small_query(rng, nmax=3000))
     for n, g in cases:
@@ -260,4 +261,38 @@ def test_large_config_full_size_bit_exact():
     assert c.rows == rows
     assert c.checksum == oracle.checksum(want)
     del out
+    torch.cuda.empty_cache()
+
+
+# --------------------------------------------------------------------------
+# Memo-dimension sweep at full size: d = 5, 7, 9, |Z| ~ 3.16e8, k = 0..3
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("idx", [0, 1, 2])
+def test_sweep_config_full_size(idx):
+    w = inputs.load_workloads()["sweep"][idx]
+    n, g, rows = w["n"], w["gens"], w["rows"]
+    d = len(g)
+    say(f"sweep d={d}: n={n} g={g} rows={rows}: oracle (threads)")
+    table = oracle.count_table(n, g)
+    want = np.empty((rows, d), dtype=np.uint32)
+    nthreads = min(16, os.cpu_count() or 1)
+    _, got_rows = oracle.enumerate_rows_threads(n, g, 0, n // g[0] + 1, nthreads,
+                                                table=table, out=want)
+    assert got_rows == rows
+    want_sum = oracle.checksum(want)
+    for k in w["ks"]:
+        say(f"sweep d={d}: count-only k={k}")
+        c = zset.enumerate_ex(n, g, k=k, count_only=True)
+        assert c.rows == rows and c.checksum == want_sum, (d, k)
+    k = 2
+    say(f"sweep d={d}: materialise k={k}")
+    out = torch.empty((rows, d), dtype=torch.int32, device="cuda")
+    r = zset.enumerate_ex(n, g, out=out, k=k)
+    assert r.rows == rows
+    chunk = 20_000_000
+    for s in range(0, rows, chunk):
+        e = min(rows, s + chunk)
+        assert_same(out[s:e].cpu().numpy().view(np.uint32), want[s:e], f"sweep d={d} [{s},{e})")
+    del out, want
     torch.cuda.empty_cache()
