@@ -63,6 +63,10 @@ struct Ctx {
   DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount;
   uint64_t* pinned = nullptr;  // host readback area
   hipEvent_t ev[6] = {};
+  // Side stream for a memo recurrence that runs beside the count table, with
+  // its fork event and start / end events.
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, memo0 = nullptr, memo1 = nullptr;
 };
 
 std::map<int, Ctx*> g_ctx;
@@ -94,6 +98,12 @@ zset_status get_ctx(Ctx** out) {
       (void)hipGetLastError();
       return fail(ZSET_EDEVICE, "hipEventCreate failed");
     }
+  }
+  if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&c->memo0) != hipSuccess || hipEventCreate(&c->memo1) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ZSET_EDEVICE, "side stream or event creation failed");
   }
   zset_status st = ensure(c->misc, kMiscWords * sizeof(uint64_t));
   if (st != ZSET_OK) return st;
@@ -196,7 +206,7 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint
   int* err = reinterpret_cast<int*>(c->misc.p);
   if (!force_global && W != 0 && R < (uint64_t(1) << 30) &&
       memo_wave_lds_bytes(k, R, W) <= size_t(max_lds_bytes(c))) {
-    ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, nat, off, err, s));
+    ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, R, nat, off, err, s));
     return ZSET_OK;
   }
   ZSET_HIP(launch_exclusive_scan(ge, top, off, s));
@@ -405,9 +415,54 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
 
-  // 1. Count table, row sums (memo sizes), total.
+  // 1. Count table, row sums (memo sizes), total.  When k >= 1 is fixed by the
+  // caller, the memo recurrence needs nothing from the count table: it starts
+  // at once on the side stream, beside the count table and the readback below,
+  // with room for as many memo rows as LDS holds.  If the memo turns out larger
+  // (known once the row sums are back), it is rebuilt below.
   ZSET_HIP(hipEventRecord(c->ev[0], s));
   ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
+  struct SideJoin {  // every return after an early launch waits for the side stream
+    Ctx* c = nullptr;
+    ~SideJoin() {
+      if (c) (void)hipStreamSynchronize(c->side);
+    }
+  } side_join;
+  bool early = false;
+  uint64_t early_cap = 0;
+  {
+    const char* path = std::getenv("ZSET_MEMO_PATH");
+    const bool force_global = path && std::strcmp(path, "global") == 0;
+    if (!memo && opts.k >= 1 && d >= 2 && !force_global) {
+      const int kk = opts.k, L0 = d - kk;
+      uint32_t b = gens[L0], hmax = gens[L0];
+      for (int i = L0; i < d; ++i) {
+        b = std::min(b, gens[i]);
+        hmax = std::max(hmax, gens[i]);
+      }
+      const uint32_t step = std::min<uint32_t>(b, kWave);
+      const uint64_t Wl = uint64_t(hmax) + step;
+      if (Wl < (uint64_t(1) << 30) && kk >= 2) {
+        const uint32_t W = next_pow2(uint32_t(Wl));
+        early_cap = std::min<uint64_t>(memo_wave_capacity(kk, W, size_t(max_lds_bytes(c))),
+                                       (uint64_t(1) << 30) - 1);
+        if (early_cap > 0) {
+          if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+          if ((st = ensure(c->nat, size_t(early_cap) * kk * sizeof(uint32_t))) != ZSET_OK)
+            return st;
+          ZSET_HIP(hipEventRecord(c->fork, s));
+          ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
+          side_join.c = c;
+          ZSET_HIP(hipEventRecord(c->memo0, c->side));
+          ZSET_HIP(launch_memo_chain_wave(gens + L0, kk, N, step, W, early_cap, 0,
+                                          reinterpret_cast<uint32_t*>(c->nat.p),
+                                          reinterpret_cast<uint64_t*>(c->off.p), err, c->side));
+          ZSET_HIP(hipEventRecord(c->memo1, c->side));
+          early = true;
+        }
+      }
+    }
+  }
   ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
   ZSET_HIP(hipEventRecord(c->ev[1], s));
   ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 1) * sizeof(uint64_t),
@@ -481,7 +536,13 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       if (memo) {
         off = memo->off;
         nat = memo->nat;
+      } else if (early && Rn <= early_cap) {
+        // The side-stream recurrence holds the whole memo.
+        ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
+        off = reinterpret_cast<const uint64_t*>(c->off.p);
+        nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       } else {
+        if (early) ZSET_HIP(hipEventSynchronize(c->memo1));  // before any buffer is regrown
         if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
         if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
         uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
@@ -582,6 +643,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     ZSET_HIP(hipEventRecord(c->ev[4], s));
   }
   ZSET_HIP(hipEventRecord(c->ev[5], s));
+  if (early) ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
   if (!count_only && opts.order == 1 && total > 1) ZSET_HIP(launch_reverse(out, total, d, s));
   ZSET_HIP(hipMemcpyAsync(c->pinned, misc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   ZSET_HIP(hipStreamSynchronize(s));
@@ -595,6 +657,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     memo_us = elapsed_us(c->ev[2], c->ev[3]);
     plan_us = elapsed_us(c->ev[3], c->ev[4]);
     write_us = elapsed_us(c->ev[4], c->ev[5]);
+    if (early && k >= 1 && total > 0 && d > 1) memo_us += elapsed_us(c->memo0, c->memo1);
     stats->memo_us = memo ? 0.0 : memo_us;
     stats->plan_us = plan_us;
     stats->write_us = write_us;

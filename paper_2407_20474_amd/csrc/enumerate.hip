@@ -239,8 +239,11 @@ __device__ inline TileArgs tile_args(const EnumParams& P) {
 
 // One slice: rows [tile * T, tile * T + target) of the query, starting from
 // the slice start `st` (first U coordinates and t0).  Shared by the
-// single-query and the batched write kernels.
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+// single-query and the batched write kernels.  NO >= 0 and KF >= 1 fix the
+// outer-prefix length (U - 1) and k at compile time, so that a row is
+// assembled with no loop and with the prefix and field shifts held in scalar
+// registers; -1 leaves them to run time.
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO = -1, int KF = -1>
 __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32_t* st,
                                   uint32_t* ring, uint32_t* marks, const uint32_t* lds_memo,
                                   const uint32_t* lds_cnt, const uint32_t* lds_endc, uint32_t gj,
@@ -273,6 +276,15 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
   uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
 
+  constexpr bool kSpec = NO >= 0 && KF >= 1;
+  uint32_t hsh[kSpec ? KF + 1 : 1], hmk[kSpec ? KF + 1 : 1];
+  if constexpr (kSpec) {
+#pragma unroll
+    for (int c2 = 0; c2 <= KF; ++c2) {
+      hsh[c2] = readlane_u32(fsh, c2);
+      hmk[c2] = readlane_u32(fmk, c2);
+    }
+  }
   uint32_t produced = 0, flushed = 0;
   bool first = true;
   bool single_done = false;
@@ -280,6 +292,11 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
 
   while (produced < target) {
     const uint32_t remaining = target - produced;
+    uint32_t hpre[kSpec && NO > 0 ? NO : 1];
+    if constexpr (kSpec) {
+#pragma unroll
+      for (int j = 0; j < NO; ++j) hpre[j] = readlane_u32(aj, j);
+    }
     const uint32_t A = aseg + uint32_t(lane);
     bool ok;
     uint32_t xs;
@@ -379,7 +396,10 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
         } else if (act) {
           MemoRow<PACK> mr;
           mr.load(lds_memo, P.leaf, mrow, k);
-          const uint32_t aU = o_qx - mr.field(fsh, fmk, 0);
+          uint32_t f0;
+          if constexpr (kSpec) f0 = uint32_t(mr.w >> hsh[0]) & hmk[0];
+          else f0 = mr.field(fsh, fmk, 0);
+          const uint32_t aU = o_qx - f0;
           if (COUNT_ONLY) {
             uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
             for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
@@ -387,6 +407,15 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
             h = fnv1a_u32(h, aU);
             for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
             csum += h;
+          } else if constexpr (kSpec) {
+            constexpr uint32_t kD = uint32_t(NO + 2 + KF);
+            uint32_t* row = ring + ((produced + rho) & ring_mask) * kD;
+#pragma unroll
+            for (int j = 0; j < NO; ++j) row[j] = hpre[j];
+            row[NO] = o_A;
+            row[NO + 1] = aU;
+#pragma unroll
+            for (int c2 = 1; c2 <= KF; ++c2) row[NO + 1 + c2] = uint32_t(mr.w >> hsh[c2]) & hmk[c2];
           } else {
             uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
             for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
@@ -450,7 +479,7 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int lane = lane_id();
@@ -520,9 +549,9 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     const uint32_t ti = __builtin_amdgcn_readfirstlane(slot_l);
     if (ti >= my_tiles) break;
     const uint64_t tile = B + uint64_t(ti) * NB;
-    write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(A, tile, tstates + ti * S, ring, marks,
-                                                    lds_memo, lds_cnt, lds_endc, gj, fsh, fmk,
-                                                    csum);
+    write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(A, tile, tstates + ti * S, ring,
+                                                                marks, lds_memo, lds_cnt, lds_endc,
+                                                                gj, fsh, fmk, csum);
   }
 
   if (COUNT_ONLY) {
@@ -750,9 +779,9 @@ __global__ __launch_bounds__(256) void k_reverse_rows(uint32_t* out, uint64_t ro
   }
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 hipError_t launch_write_t(const EnumParams& P, hipStream_t s) {
-  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>;
+  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
   const size_t lds = write_lds_bytes(P);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -761,9 +790,9 @@ hipError_t launch_write_t(const EnumParams& P, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 hipError_t occupancy_t(const EnumParams& P, int* per_cu) {
-  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>;
+  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
   const size_t lds = write_lds_bytes(P);
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
@@ -771,23 +800,44 @@ hipError_t occupancy_t(const EnumParams& P, int* per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, kWriteWaves * kWave, lds);
 }
 
+// Outer-prefix length and k compiled in for the common materialising shapes
+// (memo packed and segment counts in LDS, 16-byte-aligned output).
+constexpr int kSpecMaxOuter = 3, kSpecMaxK = 3;
+
+template <template <int, bool, bool, int, bool, int, int> class F, int PK, class... A>
+hipError_t dispatch_spec(const EnumParams& P, A... args) {
+  const int no = P.U - 1, kf = P.k;
+#define ZSET_SPEC(NO_, KF_) \
+  if (no == NO_ && kf == KF_) return F<1, false, true, PK, true, NO_, KF_>::run(P, args...);
+  ZSET_SPEC(0, 1) ZSET_SPEC(0, 2) ZSET_SPEC(0, 3)
+  ZSET_SPEC(1, 1) ZSET_SPEC(1, 2) ZSET_SPEC(1, 3)
+  ZSET_SPEC(2, 1) ZSET_SPEC(2, 2) ZSET_SPEC(2, 3)
+  ZSET_SPEC(3, 1) ZSET_SPEC(3, 2) ZSET_SPEC(3, 3)
+#undef ZSET_SPEC
+  return F<1, false, true, PK, true, -1, -1>::run(P, args...);
+}
+
 // Dispatch on the run-time choices to the matching instantiation.
-template <template <int, bool, bool, int, bool> class F, class... A>
+template <template <int, bool, bool, int, bool, int, int> class F, class... A>
 hipError_t dispatch(const EnumParams& P, bool count_only, bool align16, A... args) {
   if (P.k == 0) {
-    if (count_only) return F<0, true, false, 0, false>::run(P, args...);
-    return align16 ? F<0, false, true, 0, false>::run(P, args...)
-                   : F<0, false, false, 0, false>::run(P, args...);
+    if (count_only) return F<0, true, false, 0, false, -1, -1>::run(P, args...);
+    return align16 ? F<0, false, true, 0, false, -1, -1>::run(P, args...)
+                   : F<0, false, false, 0, false, -1, -1>::run(P, args...);
   }
-#define ZSET_PACK_CASES(PK)                                                          \
-  if (P.lds_cnt) {                                                                   \
-    if (count_only) return F<1, true, false, PK, true>::run(P, args...);             \
-    return align16 ? F<1, false, true, PK, true>::run(P, args...)                    \
-                   : F<1, false, false, PK, true>::run(P, args...);                  \
-  }                                                                                  \
-  if (count_only) return F<1, true, false, PK, false>::run(P, args...);              \
-  return align16 ? F<1, false, true, PK, false>::run(P, args...)                     \
-                 : F<1, false, false, PK, false>::run(P, args...);
+  const bool spec = !count_only && align16 && P.lds_cnt && P.U >= 1 &&
+                    P.U - 1 <= kSpecMaxOuter && P.k <= kSpecMaxK;
+  if (spec && P.pack == 1) return dispatch_spec<F, 1>(P, args...);
+  if (spec && P.pack == 2) return dispatch_spec<F, 2>(P, args...);
+#define ZSET_PACK_CASES(PK)                                                              \
+  if (P.lds_cnt) {                                                                       \
+    if (count_only) return F<1, true, false, PK, true, -1, -1>::run(P, args...);         \
+    return align16 ? F<1, false, true, PK, true, -1, -1>::run(P, args...)                \
+                   : F<1, false, false, PK, true, -1, -1>::run(P, args...);              \
+  }                                                                                      \
+  if (count_only) return F<1, true, false, PK, false, -1, -1>::run(P, args...);          \
+  return align16 ? F<1, false, true, PK, false, -1, -1>::run(P, args...)                 \
+                 : F<1, false, false, PK, false, -1, -1>::run(P, args...);
   switch (P.pack) {
     case 1: { ZSET_PACK_CASES(1) }
     case 2: { ZSET_PACK_CASES(2) }
@@ -796,16 +846,16 @@ hipError_t dispatch(const EnumParams& P, bool count_only, bool align16, A... arg
 #undef ZSET_PACK_CASES
 }
 
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 struct LaunchF {
   static hipError_t run(const EnumParams& P, hipStream_t s) {
-    return launch_write_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(P, s);
+    return launch_write_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(P, s);
   }
 };
-template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT>
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 struct OccF {
   static hipError_t run(const EnumParams& P, int* per_cu) {
-    return occupancy_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT>(P, per_cu);
+    return occupancy_t<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(P, per_cu);
   }
 };
 

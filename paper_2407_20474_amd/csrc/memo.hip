@@ -60,16 +60,18 @@ __device__ inline uint32_t wave_incl_sum_u32(uint32_t v) {
 // the list sizes gives each element its output location, and each lane then
 // copies-and-increments its element's source blocks.  The natural offsets are
 // written to off_out as they are found.
-// Dynamic LDS layout (uint32): M[R*k] | GE[W*k] | OFF[W]; W a power of two
-// >= max(h) + step.
+// Dynamic LDS layout (uint32): GE[W*k] | OFF[W] | M[Rcap*k], W a power of two
+// >= max(h) + step and M 16-byte aligned.  A memo that would outgrow Rcap rows
+// stops and marks off_out[top] = ~0 (the caller then uses the global
+// schedule); Rexp, when non-zero, is the row count the count table predicts.
 template <int KMAX>
 __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32_t top,
-                                       uint32_t step, uint32_t W, uint32_t R,
+                                       uint32_t step, uint32_t W, uint32_t Rcap, uint32_t Rexp,
                                        uint32_t* __restrict__ nat, uint64_t* __restrict__ off_out,
                                        int* __restrict__ err, uint32_t* lds) {
-  uint32_t* M = lds;
-  uint32_t* GE = M + size_t(R) * k;
+  uint32_t* GE = lds;
   uint32_t* OFF = GE + size_t(W) * k;
+  uint32_t* M = lds + memo_ring_words(k, W);
   const uint32_t lane = threadIdx.x;
   const uint32_t Wm = W - 1;
 
@@ -114,6 +116,10 @@ __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32
     const uint32_t size = valid ? acc : 0;
     const uint32_t incl = wave_incl_sum_u32(size);
     const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
+    if (uint64_t(running) + tot > Rcap) {  // the memo outgrows its LDS: report and stop
+      if (lane == 0) off_out[top] = ~uint64_t(0);
+      return;
+    }
     const uint32_t off_p = running + incl - size;
     if (valid) {
       OFF[p & Wm] = off_p;
@@ -143,9 +149,9 @@ __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32
   }
   if (lane == 0) {
     off_out[top] = running;
-    if (running != R) set_error(err, kErrMemoTotal);
+    if (Rexp != 0 && running != Rexp) set_error(err, kErrMemoTotal);
   }
-  const uint32_t words = R * uint32_t(k);
+  const uint32_t words = running * uint32_t(k);
   const uint32_t nvec = words / 4;
   const uint4* src = reinterpret_cast<const uint4*>(M);
   uint4* dstv = reinterpret_cast<uint4*>(nat);
@@ -156,7 +162,7 @@ __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32
 template <int KMAX>
 __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32_t top,
                                                             uint32_t step, uint32_t W,
-                                                            uint32_t R,
+                                                            uint32_t Rcap, uint32_t Rexp,
                                                             uint32_t* __restrict__ nat,
                                                             uint64_t* __restrict__ off_out,
                                                             int* __restrict__ err) {
@@ -164,7 +170,7 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32
   uint32_t hg[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) hg[i] = h.g[i];
-  memo_chain_wave<KMAX>(hg, k, top, step, W, R, nat, off_out, err, lds);
+  memo_chain_wave<KMAX>(hg, k, top, step, W, Rcap, Rexp, nat, off_out, err, lds);
 }
 
 // Batched: workgroup b (one wavefront) builds the memo of jobs[b].
@@ -181,7 +187,7 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_batch(const MemoJob* __res
   const uint32_t step = __builtin_amdgcn_readfirstlane(J.step);
   const uint32_t W = __builtin_amdgcn_readfirstlane(J.W);
   const uint32_t R = __builtin_amdgcn_readfirstlane(J.R);
-  memo_chain_wave<KMAX>(hg, k, top, step, W, R, J.nat, J.off, err, lds);
+  memo_chain_wave<KMAX>(hg, k, top, step, W, R, R, J.nat, J.off, err, lds);
 }
 
 // k = 1: the recurrence Memo[p] = incr_1(Memo[p - h]) from Memo[0] = {()}
@@ -316,21 +322,27 @@ __global__ __launch_bounds__(256) void k_memo_leaf_batch(const LeafJob* __restri
 }  // namespace
 
 size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W) {
-  return (size_t(R) * k + size_t(W) * (k + 1)) * sizeof(uint32_t);
+  return (size_t(R) * k + memo_ring_words(k, W)) * sizeof(uint32_t);
+}
+
+uint64_t memo_wave_capacity(int k, uint32_t W, size_t lds_bytes) {
+  const size_t words = lds_bytes / sizeof(uint32_t);
+  const size_t ring = memo_ring_words(k, W);
+  return words > ring ? (words - ring) / size_t(k) : 0;
 }
 
 hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32_t step,
-                                  uint32_t W, uint64_t R, uint32_t* nat, uint64_t* off_out,
-                                  int* err, hipStream_t s) {
+                                  uint32_t W, uint64_t Rcap, uint64_t Rexp, uint32_t* nat,
+                                  uint64_t* off_out, int* err, hipStream_t s) {
   Gens hg{};
   for (int i = 0; i < k; ++i) hg.g[i] = h[i];
-  const size_t lds = memo_wave_lds_bytes(k, R, W);
+  const size_t lds = memo_wave_lds_bytes(k, Rcap, W);
   auto go = [&](auto kern) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(1), dim3(kWave), lds, s, hg, k, uint32_t(top), step, W,
-                       uint32_t(R), nat, off_out, err);
+                       uint32_t(Rcap), uint32_t(Rexp), nat, off_out, err);
     return hipGetLastError();
   };
   if (k <= 2) return go(k_memo_chain_wave<2>);

@@ -114,10 +114,18 @@ hipError_t launch_class_ends(const uint64_t* count_row_u, uint64_t n, uint32_t G
 hipError_t launch_class_ends_batch(const ClassJob* jobs, uint32_t njobs, hipStream_t s);
 
 // memo.hip
+// Words of the one-wavefront recurrence's cardinality rings (GE and OFF),
+// rounded up so that the memo rows after them start 16-byte aligned.
+__host__ __device__ inline uint32_t memo_ring_words(int k, uint32_t W) {
+  return (W * uint32_t(k + 1) + 3u) & ~3u;
+}
 size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W);
+// Rows of memo that fit beside the rings in lds_bytes of LDS.
+uint64_t memo_wave_capacity(int k, uint32_t W, size_t lds_bytes);
+// Rcap: rows the LDS holds; Rexp: expected rows (0 = not known yet).
 hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32_t step,
-                                  uint32_t W, uint64_t R, uint32_t* nat, uint64_t* off_out,
-                                  int* err, hipStream_t s);
+                                  uint32_t W, uint64_t Rcap, uint64_t Rexp, uint32_t* nat,
+                                  uint64_t* off_out, int* err, hipStream_t s);
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);
