@@ -71,6 +71,9 @@ struct Ctx {
 
 std::map<int, Ctx*> g_ctx;
 
+// Slice start states each write workgroup keeps in LDS, at least.
+constexpr uint32_t kMinTileStates = 16;
+
 // misc layout (uint64 words): [0] status word (int), [1] checksum, [2..34] row sums
 constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2;
 constexpr size_t kMiscWords = kMiscRowSums + kMaxD + 1;
@@ -524,7 +527,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     P.dG = DivMod32::make(G);
     P.ring = d <= 16 ? 128 : 64;
     P.flush = P.ring / 2;
-    P.max_tiles = uint32_t(std::min(512, std::max(16, 4096 / (U + 2))));
+    P.max_tiles = kMinTileStates;  // grown below to what LDS leaves at this occupancy
 
     // 3. Memo (k >= 1): natural-order rows, then the leaf-order layout.
     ZSET_HIP(hipEventRecord(c->ev[2], s));
@@ -620,6 +623,18 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     ntiles = (total + T_rows - 1) / T_rows;
     if (ntiles > 0xffffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
     {
+      // Give each resident workgroup room for the start states of all of its
+      // slices when the LDS left over at this occupancy allows, so that the
+      // grid stays one resident round.
+      const uint64_t resident = uint64_t(cus) * per_cu;
+      const uint64_t need = (ntiles + resident - 1) / resident;
+      const size_t budget = size_t(max_lds_bytes(c)) / size_t(per_cu);
+      const size_t base = write_lds_bytes(P);  // with kMinTileStates states
+      const uint64_t per_state = uint64_t(U + 2) * sizeof(uint32_t);
+      uint64_t fit = P.max_tiles;
+      if (budget > base + 16) fit += (budget - base - 16) / per_state;
+      P.max_tiles = uint32_t(std::min<uint64_t>(std::max<uint64_t>(need, kMinTileStates),
+                                                std::min<uint64_t>(fit, 1u << 20)));
       uint64_t blocks = uint64_t(cus) * per_cu;
       const uint64_t min_blocks = (ntiles + P.max_tiles - 1) / P.max_tiles;
       const uint64_t max_blocks = (ntiles + wpb - 1) / wpb;

@@ -252,6 +252,10 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   const int d = int(P.d), U = int(P.U), k = int(P.k);
   const uint32_t ring_mask = P.ring - 1;
   const uint32_t flush_rows_n = P.flush;
+  // A batch or chunk yields up to 64 rows; with flush + 64 <= ring they are
+  // staged at once, else in two halves with a flush check between them.
+  const uint32_t nphase = (P.flush + uint32_t(kWave) <= P.ring) ? 1u : 2u;
+  const uint32_t phase_rows = uint32_t(kWave) / nphase;
   const int nouter = U >= 1 ? U - 1 : 0;  // coordinates 0..U-2 form the outer prefix
   const uint32_t gseg = P.gseg;
   const uint64_t* cnt_row = P.cnt_row;
@@ -317,29 +321,34 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
       const uint32_t pos = mbcnt64(mask);
       const uint32_t cnt = uint32_t(__popcll((unsigned long long)mask));
       tot = cnt < remaining ? cnt : remaining;
-      if (valid && pos < tot) {
-        if (COUNT_ONLY) {
+      if (COUNT_ONLY) {
+        if (valid && pos < tot) {
           uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + pos);
           for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
           h = fnv1a_u32(h, A);
           h = fnv1a_u32(h, qx);
           csum += h;
-        } else {
-          uint32_t* row = ring + ((produced + pos) & ring_mask) * uint32_t(d);
-          for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-          row[U - 1] = A;
-          row[U] = qx;
         }
-      }
-      if (!COUNT_ONLY) {
-        wave_sync();
-        const uint32_t written = produced + tot;
-        while (written - flushed >= flush_rows_n) {
-          flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                              out_tile + uint64_t(flushed) * d);
-          flushed += flush_rows_n;
+      } else {
+        // Staged in `nphase` parts so that the ring never holds more than
+        // flush + 64 / nphase unflushed rows.
+        for (uint32_t ph = 0; ph < nphase; ++ph) {
+          const uint32_t plo = ph * phase_rows, phi = plo + phase_rows;
+          if (valid && pos < tot && pos >= plo && pos < phi) {
+            uint32_t* row = ring + ((produced + pos) & ring_mask) * uint32_t(d);
+            for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+            row[U - 1] = A;
+            row[U] = qx;
+          }
+          wave_sync();
+          const uint32_t written = produced + (tot < phi ? tot : phi);
+          while (written - flushed >= flush_rows_n) {
+            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
+                                out_tile + uint64_t(flushed) * d);
+            flushed += flush_rows_n;
+          }
+          wave_sync();
         }
-        wave_sync();
       }
     } else {
       const uint32_t rx = P.dG.mod(xs, qx);
@@ -391,49 +400,60 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
           mrow = uint32_t(o_lo + rho);
         }
         const uint32_t o_A = aseg + uint32_t(owner);
-        if (act && mrow >= P.leaf_rows) {
-          set_error(P.err, kErrTileRows);
-        } else if (act) {
-          MemoRow<PACK> mr;
+        const bool bad = act && mrow >= P.leaf_rows;
+        if (bad) set_error(P.err, kErrTileRows);
+        const bool live = act && !bad;
+        MemoRow<PACK> mr;
+        uint32_t aU = 0;
+        if (live) {
           mr.load(lds_memo, P.leaf, mrow, k);
           uint32_t f0;
           if constexpr (kSpec) f0 = uint32_t(mr.w >> hsh[0]) & hmk[0];
           else f0 = mr.field(fsh, fmk, 0);
-          const uint32_t aU = o_qx - f0;
-          if (COUNT_ONLY) {
+          aU = o_qx - f0;
+        }
+        if (COUNT_ONLY) {
+          if (live) {
             uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
             for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
             if (U >= 1) h = fnv1a_u32(h, o_A);
             h = fnv1a_u32(h, aU);
             for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
             csum += h;
-          } else if constexpr (kSpec) {
-            constexpr uint32_t kD = uint32_t(NO + 2 + KF);
-            uint32_t* row = ring + ((produced + rho) & ring_mask) * kD;
-#pragma unroll
-            for (int j = 0; j < NO; ++j) row[j] = hpre[j];
-            row[NO] = o_A;
-            row[NO + 1] = aU;
-#pragma unroll
-            for (int c2 = 1; c2 <= KF; ++c2) row[NO + 1 + c2] = uint32_t(mr.w >> hsh[c2]) & hmk[c2];
-          } else {
-            uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
-            for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
-            if (U >= 1) row[U - 1] = o_A;
-            row[U] = aU;
-            for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
-          }
-        }
-        wave_sync();
-        if (!COUNT_ONLY) {
-          const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
-          const uint32_t written = produced + beta + nrows;
-          while (written - flushed >= flush_rows_n) {
-            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                                out_tile + uint64_t(flushed) * d);
-            flushed += flush_rows_n;
           }
           wave_sync();
+        } else {
+          const uint32_t nrows = (tot - beta) < uint32_t(kWave) ? (tot - beta) : uint32_t(kWave);
+          for (uint32_t ph = 0; ph < nphase; ++ph) {
+            const uint32_t plo = ph * phase_rows, phi = plo + phase_rows;
+            if (live && uint32_t(lane) >= plo && uint32_t(lane) < phi) {
+              if constexpr (kSpec) {
+                constexpr uint32_t kD = uint32_t(NO + 2 + KF);
+                uint32_t* row = ring + ((produced + rho) & ring_mask) * kD;
+#pragma unroll
+                for (int j = 0; j < NO; ++j) row[j] = hpre[j];
+                row[NO] = o_A;
+                row[NO + 1] = aU;
+#pragma unroll
+                for (int c2 = 1; c2 <= KF; ++c2)
+                  row[NO + 1 + c2] = uint32_t(mr.w >> hsh[c2]) & hmk[c2];
+              } else {
+                uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
+                for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+                if (U >= 1) row[U - 1] = o_A;
+                row[U] = aU;
+                for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
+              }
+            }
+            wave_sync();
+            const uint32_t written = produced + beta + (nrows < phi ? nrows : phi);
+            while (written - flushed >= flush_rows_n) {
+              flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
+                                  out_tile + uint64_t(flushed) * d);
+              flushed += flush_rows_n;
+            }
+            wave_sync();
+          }
         }
       }
     }

@@ -136,6 +136,34 @@ def test_medium_cases_default_slices():
             assert_same(got, want, f"medium n={n} g={g} k={k}")
 
 
+def wide_queries(seed, count, max_rows=200_000):
+    """Queries with d in [17, 32]: rows wider than 16 words use the 64-row
+    staging ring, which stages each 64-row chunk in two halves."""
+    rng = np.random.default_rng(seed)
+    out = []
+    while len(out) < count:
+        d = int(rng.integers(17, 33))
+        g = [int(x) for x in rng.integers(5, 70, size=d)]
+        n = int(rng.integers(40, 160))
+        c = oracle.count(n, g)
+        if 300 <= c <= max_rows:
+            out.append((n, g))
+    return out
+
+
+def test_wide_rows_every_k():
+    rng = np.random.default_rng(17)
+    for n, g in wide_queries(1700, 8):
+        want = oracle.enumerate_rows(n, g)
+        d = len(g)
+        for k in sorted({0, 1, 2, int(rng.integers(3, d))}):
+            for T in (128, 0):
+                got, r = gpu_rows(n, g, k=k, rows_per_tile=T)
+                assert_same(got, want, f"wide n={n} d={d} k={k} T={T}")
+            c = zset.enumerate_ex(n, g, k=k, count_only=True)
+            assert c.rows == len(want) and c.checksum == oracle.checksum(want)
+
+
 def test_descending_order_is_the_reversal():
     n, g = 2000, [7, 11, 13, 17]
     want = oracle.enumerate_rows(n, g)[::-1]
