@@ -63,6 +63,11 @@ typedef struct {
     int count_only;          /* 1 = no rows are written: only |Z(n)| and the
                                 checksum are produced (`out` may be NULL).      */
     void *stream;            /* hipStream_t to run on; NULL = the null stream.  */
+    int claim_pct;           /* percent of the slices that workgroups claim at
+                                run time (in chunks, from a device counter)
+                                instead of being dealt round-robin; -1 =
+                                automatic (100), 0 = none.  Output is the same
+                                for every value.                               */
 } zset_opts;
 
 /* Per-call timings (device time between HIP events on the call's stream) and
@@ -82,7 +87,7 @@ typedef struct {
 } zset_stats;
 
 /* Fill *opts with the defaults: k = -1, ascending, automatic slices, rows
- * written, null stream. */
+ * written, null stream, automatic claim_pct. */
 void zset_default_opts(zset_opts *opts);
 
 /*

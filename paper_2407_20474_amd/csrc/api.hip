@@ -75,8 +75,9 @@ std::map<int, Ctx*> g_ctx;
 constexpr uint32_t kMinTileStates = 16;
 
 // misc layout (uint64 words): [0] status word (int), [1] checksum, [2..34] row sums
-constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2;
-constexpr size_t kMiscWords = kMiscRowSums + kMaxD + 1;
+constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2, kMiscPool = kMiscRowSums + kMaxD + 1;
+constexpr size_t kMiscWords = kMiscPool + 1;
+constexpr int kDefaultClaimPct = 100;  // percent of slices claimed at run time
 constexpr size_t kPinnedWords = 64;
 
 zset_status get_ctx(Ctx** out) {
@@ -241,6 +242,7 @@ void zset_default_opts(zset_opts* o) {
   if (!o) return;
   std::memset(o, 0, sizeof *o);
   o->k = -1;
+  o->claim_pct = -1;
 }
 
 const char* zset_strerror(zset_status s) {
@@ -390,6 +392,8 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if (opts_in) opts = *opts_in; else zset_default_opts(&opts);
   if (opts.k < -1 || opts.k > d - 1) return fail(ZSET_EINVAL, "k must be -1 or lie in [0, d-1]");
   if (opts.order != 0 && opts.order != 1) return fail(ZSET_EINVAL, "order must be 0 or 1");
+  if (opts.claim_pct < -1 || opts.claim_pct > 100)
+    return fail(ZSET_EINVAL, "claim_pct must be -1 or lie in [0, 100]");
   if (opts.rows_per_tile % 128 != 0 || opts.rows_per_tile > (uint64_t(1) << 30))
     return fail(ZSET_EINVAL, "rows_per_tile must be a multiple of 128 and at most 2^30");
   const bool count_only = opts.count_only != 0;
@@ -606,6 +610,15 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     // 24 slices per wavefront by default, handed out dynamically inside each
     // workgroup.
     const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    // Slices 0..static_tiles-1 are dealt round-robin; the last claim_pct
+    // percent (all, by default) are claimed at run time in chunks of one slice
+    // per wavefront by the workgroups that have capacity: compute units do not
+    // all drain HBM at one rate, so a fixed share per workgroup ends with the
+    // slowest.
+    const int pct = opts.claim_pct < 0 ? kDefaultClaimPct : opts.claim_pct;
+    P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
+    P.chunk = pct > 0 ? uint32_t(write_waves_per_block()) : 0;
+    if (P.chunk && write_lds_bytes(P) > size_t(max_lds_bytes(c))) P.chunk = 0;
     int cus = 0, per_cu = 0;
     ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
     ZSET_HIP(write_occupancy(P, count_only, align16, &per_cu));
@@ -621,13 +634,14 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 30);
     }
     ntiles = (total + T_rows - 1) / T_rows;
-    if (ntiles > 0xffffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+    if (ntiles > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
     {
-      // Give each resident workgroup room for the start states of all of its
-      // slices when the LDS left over at this occupancy allows, so that the
-      // grid stays one resident round.
       const uint64_t resident = uint64_t(cus) * per_cu;
-      const uint64_t need = (ntiles + resident - 1) / resident;
+      P.static_tiles = P.chunk ? ntiles - (ntiles * uint64_t(pct) + 99) / 100 : ntiles;
+      // Give each resident workgroup room for the start states of all of its
+      // dealt slices when the LDS left over at this occupancy allows, so that
+      // the grid stays one resident round.
+      const uint64_t need = (P.static_tiles + resident - 1) / resident;
       const size_t budget = size_t(max_lds_bytes(c)) / size_t(per_cu);
       const size_t base = write_lds_bytes(P);  // with kMinTileStates states
       const uint64_t per_state = uint64_t(U + 2) * sizeof(uint32_t);
@@ -636,7 +650,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       P.max_tiles = uint32_t(std::min<uint64_t>(std::max<uint64_t>(need, kMinTileStates),
                                                 std::min<uint64_t>(fit, 1u << 20)));
       uint64_t blocks = uint64_t(cus) * per_cu;
-      const uint64_t min_blocks = (ntiles + P.max_tiles - 1) / P.max_tiles;
+      const uint64_t min_blocks = (P.static_tiles + P.max_tiles - 1) / P.max_tiles;
       const uint64_t max_blocks = (ntiles + wpb - 1) / wpb;
       blocks = std::max(blocks, min_blocks);
       blocks = std::min(blocks, max_blocks);

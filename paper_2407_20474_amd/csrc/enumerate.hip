@@ -121,6 +121,7 @@ __device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
 
 __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (tile == 0 && P.pool) *P.pool = 0;  // the write pass's chunk counter
   if (tile >= P.ntiles) return;
   plan_tile(P, tile);
 }
@@ -189,12 +190,21 @@ __host__ __device__ inline uint64_t align4(uint64_t words) { return (words + 3) 
 // class ends (LDSCNT), the start states of the workgroup's slices, then per
 // wavefront its staging ring and 64 marks.
 __host__ __device__ inline uint64_t write_wave_words(const EnumParams& P) {
-  return uint64_t(P.ring) * P.d + kWave;
+  return uint64_t(P.ring) * P.d + kWave + (P.chunk ? align4(uint64_t(P.U) + 2) : 0);
+}
+// Claimed chunks pass through a ring of kChunkSlots LDS slots: per slot a
+// flag, the global chunk index and a count of wavefronts done reading it, then
+// the start states of the chunk's slices.
+constexpr uint32_t kChunkSlots = 4;
+__host__ __device__ inline uint64_t claim_words(const EnumParams& P) {
+  if (P.chunk == 0) return 0;
+  return 4 * kChunkSlots + align4(uint64_t(kChunkSlots) * P.chunk * (P.U + 2));
 }
 __host__ __device__ inline uint64_t write_shared_words(const EnumParams& P) {
   uint64_t w = align4(P.memo_words);
   if (P.lds_cnt) w += align4(uint64_t(P.n) + 1) + align4(P.nclass);
   w += align4(uint64_t(P.max_tiles) * (P.U + 2));
+  w += claim_words(P);
   return w;
 }
 
@@ -499,6 +509,18 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
 }
 
+// LDS words of the chunk ring: wait until a word holds v; publish a word after
+// every LDS write of the wavefront before it.
+__device__ inline void wait_word(uint32_t* f, uint32_t v) {
+  while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != v)
+    __builtin_amdgcn_s_sleep(2);
+}
+__device__ inline void publish_flag(uint32_t* f, uint32_t v, int lane) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  wave_sync();
+  if (lane == 0) __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   extern __shared__ __align__(16) uint32_t lds[];
@@ -543,9 +565,10 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   uint32_t* wbase = lds + write_shared_words(P) + size_t(wave) * write_wave_words(P);
   uint32_t* ring = wbase;  // 16-byte aligned: every region above is a multiple of 4 words
   uint32_t* marks = ring + ring_rows * d;
-  __shared__ uint32_t next_slot;
+  __shared__ uint32_t next_slot, first_chunk;
   const uint64_t B = blockIdx.x, NB = gridDim.x;
-  uint32_t my_tiles = B < P.ntiles ? uint32_t((P.ntiles - B + NB - 1) / NB) : 0;
+  const uint64_t nstatic = P.static_tiles;
+  uint32_t my_tiles = B < nstatic ? uint32_t((nstatic - B + NB - 1) / NB) : 0;
   if (my_tiles > P.max_tiles) {  // the host sizes the grid so that this cannot happen
     if (threadIdx.x == 0) set_error(P.err, kErrTileRows);
     my_tiles = 0;
@@ -553,6 +576,43 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   for (uint32_t i = threadIdx.x; i < my_tiles * S; i += blockDim.x) {
     const uint32_t t = i / S, w = i - t * S;
     tstates[i] = P.tiles[(B + uint64_t(t) * NB) * S + w];
+  }
+  // Claimed slices (nstatic.. ntiles-1, in chunks of CH consecutive slices
+  // taken from a global counter, from the end of the order backwards: the last
+  // slices, whose outer prefixes hold few rows each and so cost the most per
+  // row, start first and the pass ends on cheap ones; chunk g holds slices
+  // [hi - cnt, hi) with hi = ntiles - g CH, its e-th taker gets slice
+  // hi - 1 - e).  The workgroup's c-th chunk goes through
+  // ring slot c mod R: cflag = c + 1 once published, cgid = global chunk
+  // index (nchunks when the counter is exhausted), cdone = wavefronts that
+  // have copied their slice start out of the slot (CH when the slot is free).
+  // The first chunk is claimed here, before any store; chunk c + 1 by the
+  // wavefront that takes the first slice of chunk c, so a claim (whose wait
+  // covers that wavefront's pending stores) is paid once per CH slices and
+  // lands about CH slices ahead of use.
+  const uint32_t CH = P.chunk;
+  constexpr uint32_t R = kChunkSlots;
+  const uint32_t nchunks = CH ? uint32_t((P.ntiles - nstatic + CH - 1) / CH) : 0;
+  uint32_t* cflag = tstates + align4(uint64_t(P.max_tiles) * S);
+  uint32_t* cgid = cflag + R;
+  uint32_t* cdone = cgid + R;
+  uint32_t* cstate = cdone + 2 * R;
+  uint32_t* mystate = marks + kWave;
+  if (CH) {
+    if (threadIdx.x == 0) first_chunk = atomicAdd(P.pool, 1u);
+    __syncthreads();
+    const uint32_t gc = min(first_chunk, nchunks);
+    if (gc < nchunks) {
+      const uint64_t hi = P.ntiles - uint64_t(gc) * CH;
+      const uint32_t cnt = uint32_t(min<uint64_t>(CH, hi - nstatic));
+      const uint64_t t0 = hi - cnt;
+      for (uint32_t i = threadIdx.x; i < cnt * S; i += blockDim.x) cstate[i] = P.tiles[t0 * S + i];
+    }
+    if (threadIdx.x < R) {
+      cflag[threadIdx.x] = threadIdx.x == 0 ? 1 : 0;
+      cgid[threadIdx.x] = threadIdx.x == 0 ? gc : 0;
+      cdone[threadIdx.x] = threadIdx.x == 0 ? 0 : CH;
+    }
   }
   if (threadIdx.x == 0) next_slot = 0;
   const uint32_t gj = lane < d ? P.g.g[lane] : 0;
@@ -567,11 +627,59 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     uint32_t slot_l = 0;
     if (lane == 0) slot_l = atomicAdd(&next_slot, 1u);
     const uint32_t ti = __builtin_amdgcn_readfirstlane(slot_l);
-    if (ti >= my_tiles) break;
-    const uint64_t tile = B + uint64_t(ti) * NB;
-    write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(A, tile, tstates + ti * S, ring,
-                                                                marks, lds_memo, lds_cnt, lds_endc,
-                                                                gj, fsh, fmk, csum);
+    if (ti < my_tiles) {
+      const uint64_t tile = B + uint64_t(ti) * NB;
+      write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(A, tile, tstates + ti * S, ring,
+                                                                  marks, lds_memo, lds_cnt,
+                                                                  lds_endc, gj, fsh, fmk, csum);
+      continue;
+    }
+    if (CH == 0) break;
+    const uint32_t dj = ti - my_tiles, c = dj / CH, e = dj - c * CH, r = c % R;
+    // Chunk c is published by the taker of the first slice of chunk c - 1 (or
+    // the prologue), taken earlier; that taker waits only on readers of chunk
+    // c - R, taken earlier still, who wait on nothing after their copy: every
+    // wait ends.
+    wait_word(cflag + r, c + 1);
+    const uint32_t gc = cgid[r];
+    const uint64_t hi = gc < nchunks ? P.ntiles - uint64_t(gc) * CH : nstatic;
+    const uint32_t cnt = uint32_t(min<uint64_t>(CH, hi - nstatic));
+    const bool live = e < cnt;  // the chunk claimed last may be short
+    const uint64_t tile = hi - 1 - e;
+    if (live && lane < int(S)) mystate[lane] = cstate[(r * CH + (cnt - 1 - e)) * S + lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    wave_sync();
+    if (lane == 0) __hip_atomic_fetch_add(cdone + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (e == 0) {
+      // Claim chunk c + 1 into slot c + 1 mod R once the readers of the chunk
+      // it held (c + 1 - R, all of whose slices were taken before this one)
+      // have copied their starts.
+      const uint32_t rn = (c + 1) % R;
+      wait_word(cdone + rn, CH);
+      uint32_t gn = nchunks;  // an exhausted counter passes exhaustion on
+      if (gc < nchunks) {
+        uint32_t g_l = 0;
+        if (lane == 0) g_l = atomicAdd(P.pool, 1u);
+        gn = min(__builtin_amdgcn_readfirstlane(g_l), nchunks);
+      }
+      if (gn < nchunks) {
+        const uint64_t hn = P.ntiles - uint64_t(gn) * CH;
+        const uint32_t cn = uint32_t(min<uint64_t>(CH, hn - nstatic));
+        const uint64_t t0 = hn - cn;
+        uint32_t* dst = cstate + rn * CH * S;
+        for (uint32_t i = lane; i < cn * S; i += kWave) dst[i] = P.tiles[t0 * S + i];
+      }
+      if (lane == 0) {
+        cdone[rn] = 0;
+        cgid[rn] = gn;
+      }
+      publish_flag(cflag + rn, c + 2, lane);
+    }
+    if (gc >= nchunks) break;
+    if (!live) continue;
+    write_tile<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(A, tile, mystate, ring, marks,
+                                                                lds_memo, lds_cnt, lds_endc, gj,
+                                                                fsh, fmk, csum);
   }
 
   if (COUNT_ONLY) {

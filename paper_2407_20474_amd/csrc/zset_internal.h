@@ -39,7 +39,11 @@ struct EnumParams {
   int lds_cnt;              // 1: segment counts C[U][x] and class ends copied to LDS as uint32
   uint32_t nclass;          // residue classes of the leaf layout: min(G, n + 1)
   uint32_t max_tiles;       // slices one workgroup may own (their starts are held in LDS)
-  uint32_t write_blocks;    // workgroups of the write pass; slice t goes to workgroup t mod NB
+  uint32_t write_blocks;    // workgroups of the write pass; slice t < static_tiles goes to
+                            // workgroup t mod NB
+  uint64_t static_tiles;    // slices dealt round-robin; the rest are claimed in chunks
+  uint32_t chunk;           // slices per claimed chunk (0: every slice is dealt)
+  uint32_t* pool;           // chunk counter, zeroed by the slice planner
 };
 
 // One query's share of a batched launch.

@@ -32,7 +32,7 @@ SYMBOLS = (
 class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("order", ctypes.c_int),
                 ("rows_per_tile", ctypes.c_uint64), ("count_only", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("claim_pct", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -231,9 +231,10 @@ class Result:
 
 def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
                  rows_per_tile: int = 0, count_only: bool = False, memo: Memo | None = None,
-                 stream=None, out_rows_cap: int | None = None) -> Result:
+                 stream=None, out_rows_cap: int | None = None, claim_pct: int = -1) -> Result:
     """Z(n; g) through zset_enumerate_ex.  `out` is an int32 CUDA tensor with at least
-    |Z(n)| * d elements (allocated here when None and count_only is False)."""
+    |Z(n)| * d elements (allocated here when None and count_only is False).
+    `claim_pct`: percent of slices claimed at run time (-1 automatic, 0 none)."""
     import torch
     g = _gens(gens)
     d = len(g)
@@ -250,6 +251,7 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     opts.k, opts.order, opts.rows_per_tile = k, order, rows_per_tile
     opts.count_only = 1 if count_only else 0
     opts.stream = _stream_handle(stream)
+    opts.claim_pct = claim_pct
     rows_written, csum, stats = ctypes.c_uint64(), ctypes.c_uint64(), Stats()
     _check(load().zset_enumerate_ex(n, g.ctypes.data_as(_u32p), d, ptr, cap, ctypes.byref(opts),
                                     memo.handle if memo is not None else None,

@@ -164,6 +164,22 @@ def test_wide_rows_every_k():
             assert c.rows == len(want) and c.checksum == oracle.checksum(want)
 
 
+def test_claimed_slices_every_share():
+    """Slices claimed at run time (any share, any chunking) give the dealt rows.
+    3.6e6 rows over 28452 slices of 128 rows: far more than 16 slices per
+    resident workgroup, so claiming is in use; the last slice is ragged."""
+    n, g = 400, [2, 3, 5, 7, 11, 13]
+    want = oracle.enumerate_rows(n, g)
+    want_sum = oracle.checksum(want)
+    cases = [(2, 128, p) for p in (0, 1, 25, 60, 100)] + [(0, 128, 100), (1, 384, 25),
+                                                          (3, 128, 100), (2, 1152, 50)]
+    for k, rpt, pct in cases:
+        got, r = gpu_rows(n, g, k=k, rows_per_tile=rpt, claim_pct=pct)
+        assert_same(got, want, f"claimed k={k} rows_per_tile={rpt} claim_pct={pct}")
+        c = zset.enumerate_ex(n, g, k=k, rows_per_tile=rpt, claim_pct=pct, count_only=True)
+        assert c.rows == len(want) and c.checksum == want_sum, (k, rpt, pct)
+
+
 def test_descending_order_is_the_reversal():
     n, g = 2000, [7, 11, 13, 17]
     want = oracle.enumerate_rows(n, g)[::-1]
@@ -285,9 +301,11 @@ def test_large_config_full_size_bit_exact():
         got = out[s:e].cpu().numpy().view(np.uint32)
         assert_same(got, want[s:e], f"large rows [{s}, {e})")
     say("large: count-only checksum")
-    c = zset.enumerate_ex(n, g, k=k, count_only=True)
-    assert c.rows == rows
-    assert c.checksum == oracle.checksum(want)
+    want_sum = oracle.checksum(want)
+    for pct in (-1, 0, 100):
+        c = zset.enumerate_ex(n, g, k=k, count_only=True, claim_pct=pct)
+        assert c.rows == rows
+        assert c.checksum == want_sum, pct
     del out
     torch.cuda.empty_cache()
 

@@ -84,6 +84,8 @@ def test_enumerate_ex_option_checks():
     assert run(k=-2) == zset.EINVAL
     assert run(order=2) == zset.EINVAL
     assert run(rows_per_tile=100) == zset.EINVAL   # not a multiple of 128
+    assert run(claim_pct=101) == zset.EINVAL
+    assert run(claim_pct=-2) == zset.EINVAL
     assert run() == zset.EINVAL              # out is NULL and rows are wanted
 
 
@@ -103,7 +105,9 @@ def test_default_opts():
     o = zset.Opts()
     o.k, o.order, o.rows_per_tile, o.count_only = 5, 1, 256, 1
     lib.zset_default_opts(ctypes.byref(o))
-    assert (o.k, o.order, o.rows_per_tile, o.count_only) == (-1, 0, 0, 0)
+    o.claim_pct = 7
+    lib.zset_default_opts(ctypes.byref(o))
+    assert (o.k, o.order, o.rows_per_tile, o.count_only, o.claim_pct) == (-1, 0, 0, 0, -1)
     assert o.stream is None
 
 
