@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--rows-per-tile", type=int, default=0)
     ap.add_argument("--count-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-rows", type=float, default=5e7)
+    ap.add_argument("--cpu-sample-rows", type=float, default=2.5e8)
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()

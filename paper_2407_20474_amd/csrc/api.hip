@@ -605,10 +605,10 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     }
     ZSET_HIP(hipEventRecord(c->ev[3], s));
 
-    // 4. Slices: exact rank ranges, starts unranked on the device.  Slice t
-    // goes to workgroup t mod NB of a grid sized to what stays resident; about
-    // 24 slices per wavefront by default, handed out dynamically inside each
-    // workgroup.
+    // 4. Slices: exact rank ranges, starts unranked on the device; about 128
+    // slices per resident wavefront by default (short slices keep the
+    // concurrent write streams of a compute unit close together in memory and
+    // the end of the pass even).
     const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     // Slices 0..static_tiles-1 are dealt round-robin; the last claim_pct
     // percent (all, by default) are claimed at run time in chunks of one slice
@@ -627,7 +627,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     const uint64_t resident_waves = uint64_t(cus) * per_cu * wpb;
     T_rows = opts.rows_per_tile;
     if (T_rows == 0) {
-      const uint64_t want_tiles = resident_waves * 24;
+      const uint64_t want_tiles = resident_waves * 128;
       T_rows = (total + want_tiles - 1) / want_tiles;
       T_rows = (T_rows + 127) / 128 * 128;
       T_rows = std::max<uint64_t>(T_rows, 128);
