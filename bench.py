@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch"])
+    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch", "memo"])
     ap.add_argument("--sweep-d", type=int, default=5, choices=[5, 7, 9],
                     help="dimension of the memo-dimension sweep workload")
     ap.add_argument("--seed", type=int, default=0, help="large workload seed (0, 1 or 2)")
@@ -210,6 +210,105 @@ def run_batch(args):
     b.free()
 
 
+# The paper's Table 1 groups: (d, memo dimension, largest element), generators
+# the first d of (13, 37, 38, 40, ..., 45), memo of the trailing k generators
+# populated up to the largest element of the group; with the paper's own CPU
+# and GPU memo population times (microseconds, Ryzen 3900X / RTX 3080).
+TABLE1_GENS = (13, 37, 38, 40, 41, 42, 43, 44, 45)
+TABLE1_GROUPS = [(3, 1, 300000, 452, 9205), (4, 2, 15000, 3073, 33543),
+                 (5, 2, 10000, 1624, 33645), (5, 3, 5000, 7951, 28841),
+                 (6, 3, 5000, 7341, 26576), (6, 4, 3000, 45837, 26152),
+                 (7, 4, 2000, 55714, 26664), (8, 4, 2000, 46092, 28807),
+                 (9, 4, 1500, 49328, 26591), (9, 5, 1500, 22711, 18628)]
+
+
+def run_memo(args):
+    """Memo population, CPU vs GPU (the paper's Section 4.1 crossover): the
+    serial dynamic recurrence on one host core (the oracle's CPU form of it)
+    against zset_memo_build on the GPU (device time between events on the
+    call's stream, and the call's wall time), for the Table 1 groups and for a
+    sweep of `top` at fixed generators.  The GPU lists are compared with the
+    CPU lists for every case."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2407_20474_amd import zset
+
+    def gpu_time(h, top, reps=5):
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        m = zset.Memo(h, top)  # warm-up (first use of the path)
+        m.free()
+        dev, wall = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ev0.record()
+            m = zset.Memo(h, top)
+            ev1.record()
+            torch.cuda.synchronize()
+            wall.append((time.perf_counter() - t) * 1e6)
+            dev.append(ev0.elapsed_time(ev1) * 1e3)
+            if _ < reps - 1:
+                m.free()
+        return m, float(np.median(dev)), float(np.median(wall))
+
+    def cpu_time(h, top, reps=3):
+        best, res = None, None
+        for _ in range(reps):
+            off, rows, dt = oracle.memo_dynamic(h, top, timed=True)
+            if best is None or dt < best:
+                best, res = dt, (off, rows)
+        return res, best * 1e6
+
+    def case(h, top, paper=None):
+        (off, rows), cpu_us = cpu_time(h, top)
+        m, gpu_dev_us, gpu_wall_us = gpu_time(h, top)
+        goff, grows = m.read()
+        m.free()
+        assert np.array_equal(goff, off) and np.array_equal(grows, rows), (h, top)
+        r = {"h": list(h), "top": top, "memo_rows": int(off[top]),
+             "memo_bytes": int(off[top]) * len(h) * 4, "cpu_us": round(cpu_us, 1),
+             "gpu_us": round(gpu_dev_us, 1), "gpu_wall_us": round(gpu_wall_us, 1),
+             "gpu_faster": gpu_dev_us < cpu_us}
+        if paper:
+            r["paper_cpu_us"], r["paper_gpu_us"] = paper
+        print(f"# memo h={h} top={top}: rows {r['memo_rows']}, cpu {r['cpu_us']} us, "
+              f"gpu {r['gpu_us']} us (wall {r['gpu_wall_us']} us)", file=sys.stderr, flush=True)
+        return r
+
+    groups = []
+    for d, k, elem, pc, pg in TABLE1_GROUPS:
+        h = list(TABLE1_GENS[:d][d - k:])
+        r = case(h, elem + 1, (pc, pg))
+        r["d"], r["k"], r["element"] = d, k, elem
+        groups.append(r)
+    sweep_h = [40, 41, 42, 43]
+    sweep = [case(sweep_h, top) for top in (50, 100, 200, 400, 800, 1600, 3200, 6400)]
+    cross = next((r for r in sweep if r["gpu_faster"]), None)
+    total_rows = sum(r["memo_rows"] for r in groups)
+    gpu_total_us = sum(r["gpu_us"] for r in groups)
+    line = {
+        "metric": "memo rows/s populated by the GPU dynamic recurrence (zset_memo_build)",
+        "value": total_rows / (gpu_total_us * 1e-6),
+        "unit": "memo rows/s",
+        "n_gpus": 1, "steps": 5, "warmup": 1, "ms_per_step": gpu_total_us / 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "memo: the paper's Table 1 memo groups (generators the first d of "
+                               "13, 37, 38, 40..45; memo of the trailing k up to the group's "
+                               "largest element) and a top sweep at h = (40, 41, 42, 43)"},
+        "table1": groups,
+        "top_sweep": sweep,
+        "crossover": ({"h": sweep_h, "top": cross["top"], "memo_rows": cross["memo_rows"]}
+                      if cross else None),
+        "cpu_baseline": {"value": total_rows / (sum(r["cpu_us"] for r in groups) * 1e-6),
+                         "unit": "memo rows/s", "cores": 1, "kind": "oracle",
+                         "sample": "the Table 1 memo groups, serial dynamic recurrence, best of 3"},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -220,6 +319,9 @@ def main():
 
     if args.workload == "batch":
         run_batch(args)
+        return
+    if args.workload == "memo":
+        run_memo(args)
         return
 
     import torch

@@ -56,6 +56,8 @@ def _lib():
                                       ctypes.c_uint64, _u32p]
         lib.oracle_memo.argtypes = [_u32p, ctypes.c_int, ctypes.c_uint64, _u64p, _u32p,
                                     ctypes.c_uint64]
+        lib.oracle_memo_dynamic.argtypes = [_u32p, ctypes.c_int, ctypes.c_uint64, _u64p, _u32p,
+                                            ctypes.c_uint64]
         lib.oracle_fnv1a64.argtypes = [ctypes.c_char_p, ctypes.c_uint64]
         lib.oracle_fnv1a64.restype = ctypes.c_uint64
         lib.oracle_checksum.argtypes = [_u32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64]
@@ -177,6 +179,29 @@ def memo(h, top: int):
     if st != OK:
         raise OracleError(st, "oracle_memo")
     return off, rows[:total]
+
+
+def memo_dynamic(h, top: int, timed: bool = False):
+    """The same (off, rows) built serially by the paper's dynamic recurrence
+    (oracle_memo_dynamic).  With timed=True also returns the seconds of the
+    building call alone (the sizing call and the allocation are not timed)."""
+    import time
+    hh = _gens(h)
+    k = len(hh)
+    off = np.empty(top + 1, dtype=np.uint64)
+    lib = _lib()
+    st = lib.oracle_memo_dynamic(_p32(hh), k, top, _p64(off), None, 0)
+    if st != OK:
+        raise OracleError(st, "oracle_memo_dynamic (sizing)")
+    total = int(off[top])
+    rows = np.empty((max(total, 1), k), dtype=np.uint32)
+    rows.fill(0)
+    t = time.perf_counter()
+    st = lib.oracle_memo_dynamic(_p32(hh), k, top, _p64(off), _p32(rows), total)
+    dt = time.perf_counter() - t
+    if st != OK:
+        raise OracleError(st, "oracle_memo_dynamic")
+    return (off, rows[:total], dt) if timed else (off, rows[:total])
 
 
 def fnv1a64(data: bytes) -> int:

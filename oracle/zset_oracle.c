@@ -219,6 +219,61 @@ int oracle_memo(const uint32_t *h, int k, uint64_t top, uint64_t *off,
     return (rows && total > cap) ? ORACLE_ECAPACITY : ORACLE_OK;
 }
 
+/*
+ * oracle_memo_dynamic: the same lists built serially by the paper's dynamic
+ * recurrence (Lemma 2.3; lists up to an element as in Alg 2.8; saved
+ * cardinalities and block copies as in Section 2.3), read in ascending order.
+ * The rows of Z(p) whose first nonzero coordinate is i are incr_i of the rows
+ * of Z(p - h_i) that are zero left of i; in an ascending list those rows come
+ * first, and there are ge[p - h_i][i] of them, where ge[m][i] = |Z_{>=i}(m)|
+ * counts the rows of Z(m) that are zero left of i.  So Z(p) is the
+ * concatenation over i = k, k-1, .., 1 of incr_i applied to the first
+ * ge[p - h_i][i] rows of Z(p - h_i), and ge[p][i] is the number of rows in
+ * the blocks i' >= i.  Z(0) = [0], ge[0][i] = 1.  One element at a time, on
+ * one CPU thread: this is the CPU memo population the paper times against
+ * its GPU one (Section 4.1, Table 1), used as that baseline.  It is checked
+ * against oracle_memo, which does not use the recurrence.  Call with rows ==
+ * NULL to size the table (off still filled).
+ */
+int oracle_memo_dynamic(const uint32_t *h, int k, uint64_t top, uint64_t *off,
+                        uint32_t *rows, uint64_t cap)
+{
+    if (k < 1 || !h || !off || top < 1) return ORACLE_EINVAL;
+    uint64_t *ge = (uint64_t *)malloc((size_t)top * k * sizeof(uint64_t));
+    if (!ge) return ORACLE_ENOMEM;
+    for (int i = 0; i < k; ++i) ge[i] = 1;
+    off[0] = 0;
+    if (rows && cap >= 1)
+        for (int c = 0; c < k; ++c) rows[c] = 0;
+    uint64_t total = 1;
+    int st = ORACLE_OK;
+    for (uint64_t p = 1; p < top; ++p) {
+        off[p] = total;
+        uint64_t acc = 0;
+        for (int i = k - 1; i >= 0; --i) {
+            uint64_t len = 0;
+            if (p >= h[i]) {
+                const uint64_t src = p - h[i];
+                len = ge[src * k + i];
+                if (rows) {
+                    for (uint64_t t = 0; t < len; ++t) {
+                        const uint64_t from = off[src] + t, to = total + t;
+                        if (to >= cap) { st = ORACLE_ECAPACITY; break; }
+                        for (int c = 0; c < k; ++c)
+                            rows[to * k + c] = rows[from * k + c] + (c == i ? 1u : 0u);
+                    }
+                }
+            }
+            total += len;
+            acc += len;
+            ge[p * k + i] = acc;
+        }
+    }
+    off[top] = total;
+    free(ge);
+    return (rows && total > cap) ? ORACLE_ECAPACITY : st;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Checksum of a row list.                                                   */
 /* ------------------------------------------------------------------------ */

@@ -221,6 +221,24 @@ def test_memo_build_matches_oracle(path, monkeypatch):
         m.free()
 
 
+def test_memo_lists_of_the_table1_groups():
+    """The FactorizationsUpToElement lists of the paper's Table 1 memo groups
+    (generators the first d of 13, 37, 38, 40..45; memo of the trailing k up to
+    the group's largest element), as zset_memo_build returns them, against the
+    oracle's lists (one plain enumeration per element)."""
+    gens = (13, 37, 38, 40, 41, 42, 43, 44, 45)
+    for d, k, elem in [(3, 1, 300000), (4, 2, 15000), (5, 2, 10000), (5, 3, 5000),
+                       (6, 3, 5000), (6, 4, 3000), (7, 4, 2000), (9, 5, 1500)]:
+        h = list(gens[:d][d - k:])
+        say(f"table 1 memo d={d} k={k} h={h} top={elem + 1}")
+        m = zset.Memo(h, elem + 1)
+        off, rows = m.read()
+        m.free()
+        want_off, want_rows = oracle.memo(h, elem + 1)
+        assert np.array_equal(off, want_off), (d, k)
+        assert np.array_equal(rows, want_rows), (d, k)
+
+
 def test_memo_handle_gives_the_same_rows():
     n, g = 2000, [7, 11, 13, 17]
     want = oracle.enumerate_rows(n, g)

@@ -234,6 +234,31 @@ def test_memo_matches_brute_force():
             assert as_tuples(rows[int(off[p]):int(off[p + 1])]) == brute(p, h), (h, p)
 
 
+def test_dynamic_memo_matches_the_definition():
+    """oracle_memo_dynamic (the serial recurrence, the CPU memo population the
+    paper times) equals oracle_memo (one plain enumeration per element), which
+    brute force pins above; cases with repeated, unsorted and unit generators
+    and the first generators of the paper's Table 1."""
+    cases = [([3, 5], 300), ([4, 6, 9], 200), ([7], 90), ([2, 2], 60), ([9, 4, 6], 250),
+             ([1], 12), ([1, 1, 1], 30), ([5, 3, 2, 7], 120), ([37, 38], 2000),
+             ([38, 40, 41], 1500), ([40, 41, 42, 43], 1001), ([41, 42, 43, 44, 45], 501),
+             ([13, 37, 38], 3000), ([6], 1)]
+    for h, top in cases:
+        off, rows = oracle.memo(h, top)
+        doff, drows, dt = oracle.memo_dynamic(h, top, timed=True)
+        assert np.array_equal(off, doff), (h, top)
+        assert np.array_equal(rows, drows), (h, top)
+        assert dt >= 0
+
+
+def test_dynamic_memo_against_alg_2_8_reversed():
+    for n, g in tiny_cases(12, 40, dmax=4, nmax=40):
+        off, rows = oracle.memo_dynamic(g, n + 1)
+        F = method.lex_lists_up_to(n, g)
+        for m in range(n + 1):
+            assert as_tuples(rows[int(off[m]):int(off[m + 1])]) == F[m][::-1], (g, m)
+
+
 def test_threaded_enumeration_matches():
     n, g = 1500, [7, 11, 13, 17]
     full = oracle.enumerate_rows(n, g)
