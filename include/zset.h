@@ -278,6 +278,89 @@ zset_status zset_batch_times(zset_batch batch, double *done_us);
 /* Release a batch (NULL is ignored). */
 void zset_batch_free(zset_batch batch);
 
+/* ------------------------------------------------------------------------
+ * Serving: a request loop over resident generator sets.  A set g is made
+ * resident once up to an element bound n_max (count table C_j[x], x <= n_max,
+ * on the device with a host copy of |Z(n)| for every n <= n_max; for memo
+ * dimension k >= 1 the memo of the trailing k generators for p <= n_max, built
+ * by the recurrence of Lemma 2.3, in its leaf-order layout).  Queries (set, n)
+ * are then submitted at any time; a dispatcher thread admits them in arrival
+ * order as one of `slots` streams and room in the caller's output arena become
+ * free (the rows of a query take |Z(n)| d uint32, rounded up to 16 bytes, known
+ * at submission from the host copy), runs the slice plan and the write pass of
+ * each on its own stream, and stamps submit / admit / done times.  Several
+ * queries are on the device at once; each query's rows are the bytes
+ * zset_enumerate_ex writes for it alone.  Outputs stay in the arena until
+ * zset_server_release.  Entry points are thread-safe.
+ * ------------------------------------------------------------------------ */
+
+typedef struct zset_server_s *zset_server;
+
+typedef struct {
+    int slots;               /* queries on the device at once, 1..64; 0 = 8    */
+    void *arena;             /* device buffer the outputs are carved from, owned
+                                by the caller, 16-byte aligned, kept alive until
+                                zset_server_free                               */
+    uint64_t arena_bytes;    /* its size: the output budget                     */
+} zset_server_opts;
+
+typedef struct {
+    uint64_t rows;           /* |Z(n)|                                          */
+    uint64_t out_offset;     /* uint32 word offset of the rows in the arena      */
+    double submit_us;        /* host steady-clock times, microseconds since the  */
+    double admit_us;         /* server was created: submission, launch on a      */
+    double done_us;          /* slot, and completion seen by the dispatcher      */
+} zset_server_result;
+
+/* Fill *opts with the defaults (8 slots, no arena). */
+void zset_server_default_opts(zset_server_opts *opts);
+
+/* Start a server (its dispatcher thread) on the current device.
+ * Errors: EINVAL (slots out of range, arena NULL / unaligned / not device
+ * memory), ENOMEM, EDEVICE. */
+zset_status zset_server_create(const zset_server_opts *opts, zset_server *server);
+
+/*
+ * zset_server_add_set -- make generator set gens (host, d uint32, each >= 1,
+ * in the caller's order) resident up to n_max (<= 2^31 - 2) with memo
+ * dimension k (-1 = the largest k whose packed memo fits the write pass's LDS,
+ * else 0).  Synchronous.  *set_id receives the set's index (0, 1, ...).
+ * Errors: EINVAL, EOVERFLOW, ENOMEM, EDEVICE.
+ */
+zset_status zset_server_add_set(zset_server server, const uint32_t *gens, int d, uint64_t n_max,
+                                int k, int *set_id);
+
+/* A resident set's memo dimension, n_max, memo rows and device bytes. */
+zset_status zset_server_set_info(zset_server server, int set_id, int *k, uint64_t *n_max,
+                                 uint64_t *memo_rows, uint64_t *resident_bytes);
+
+/* |Z(n)| of a resident set from its host copy (no device work).
+ * Errors: EINVAL (no such set, n > n_max), EOVERFLOW. */
+zset_status zset_server_count(zset_server server, int set_id, uint64_t n, uint64_t *rows);
+
+/* Queue query (set_id, n); never blocks.  *ticket identifies it.
+ * Errors: EINVAL (no such set, n > n_max, server stopping), EOVERFLOW,
+ * ECAPACITY (the rows exceed the whole arena). */
+zset_status zset_server_submit(zset_server server, int set_id, uint64_t n, uint64_t *ticket);
+
+/* Block until the query has finished; fill *result (may be NULL).  Returns the
+ * query's status: OK, or EDEVICE (a HIP error or a kernel check) / EINVAL (the
+ * server stopped before admitting it).  Errors: EINVAL (unknown ticket). */
+zset_status zset_server_wait(zset_server server, uint64_t ticket, zset_server_result *result);
+
+/* Give a finished query's rows back to the arena and forget the ticket.
+ * Errors: EINVAL (unknown ticket, query not finished). */
+zset_status zset_server_release(zset_server server, uint64_t ticket);
+
+/* Queries admitted and completed so far, and the most on the device at once. */
+zset_status zset_server_stats(zset_server server, uint64_t *admitted, uint64_t *completed,
+                              uint64_t *max_inflight);
+
+/* Stop the server: queries on the device finish, queued ones end with EINVAL;
+ * then free every resident set (NULL is ignored).  The arena stays the
+ * caller's. */
+void zset_server_free(zset_server server);
+
 /* Static text for a status code. */
 const char *zset_strerror(zset_status status);
 

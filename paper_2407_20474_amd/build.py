@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libzset.so")
-SOURCES = ["count_table.hip", "scan.hip", "memo.hip", "enumerate.hip", "api.hip", "batch.hip"]
+SOURCES = ["count_table.hip", "scan.hip", "memo.hip", "enumerate.hip", "api.hip", "batch.hip",
+           "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -118,6 +118,78 @@ zset_status get_ctx(Ctx** out) {
 
 }  // namespace
 
+// Slice length, claimed chunks, slice-state capacity and grid of the write
+// pass for P (P.total, P.U, P.d, P.k and the memo fields set; P.pool set by the
+// caller).  Slices 0..static_tiles-1 are dealt round-robin; the last claim_pct
+// percent (all, by default) are claimed at run time in chunks of one slice per
+// wavefront by the workgroups that have capacity: compute units do not all
+// drain HBM at one rate, so a fixed share per workgroup ends with the slowest.
+// About 128 slices per resident wavefront by default (short slices keep the
+// concurrent write streams of a compute unit close together in memory and the
+// end of the pass even).
+zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
+                            bool count_only, bool align16) {
+  const int pct = claim_pct < 0 ? kDefaultClaimPct : claim_pct;
+  const size_t lds_max = size_t(device_max_lds_bytes(device));
+  P.max_tiles = kMinTileStates;
+  P.chunk = pct > 0 ? uint32_t(write_waves_per_block()) : 0;
+  if (P.chunk && write_lds_bytes(P) > lds_max) P.chunk = 0;
+  int cus = 0, per_cu = 0;
+  ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  ZSET_HIP(write_occupancy(P, count_only, align16, &per_cu));
+  if (per_cu < 1) return fail(ZSET_EDEVICE, "the write pass does not fit on a compute unit");
+  const uint64_t wpb = uint64_t(write_waves_per_block());
+  const uint64_t resident_waves = uint64_t(cus) * per_cu * wpb;
+  uint64_t T_rows = rows_per_tile;
+  if (T_rows == 0) {
+    const uint64_t want_tiles = resident_waves * 128;
+    T_rows = (P.total + want_tiles - 1) / want_tiles;
+    T_rows = (T_rows + 127) / 128 * 128;
+    T_rows = std::max<uint64_t>(T_rows, 128);
+    T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 30);
+  }
+  const uint64_t ntiles = (P.total + T_rows - 1) / T_rows;
+  if (ntiles > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+  const uint64_t resident = uint64_t(cus) * per_cu;
+  P.static_tiles = P.chunk ? ntiles - (ntiles * uint64_t(pct) + 99) / 100 : ntiles;
+  // Give each resident workgroup room for the start states of all of its
+  // dealt slices when the LDS left over at this occupancy allows, so that the
+  // grid stays one resident round.
+  const uint64_t need = (P.static_tiles + resident - 1) / resident;
+  const size_t budget = lds_max / size_t(per_cu);
+  const size_t base = write_lds_bytes(P);  // with kMinTileStates states
+  const uint64_t per_state = uint64_t(P.U + 2) * sizeof(uint32_t);
+  uint64_t fit = P.max_tiles;
+  if (budget > base + 16) fit += (budget - base - 16) / per_state;
+  P.max_tiles = uint32_t(std::min<uint64_t>(std::max<uint64_t>(need, kMinTileStates),
+                                            std::min<uint64_t>(fit, 1u << 20)));
+  uint64_t blocks = resident;
+  const uint64_t min_blocks = (P.static_tiles + P.max_tiles - 1) / P.max_tiles;
+  const uint64_t max_blocks = (ntiles + wpb - 1) / wpb;
+  blocks = std::max(blocks, min_blocks);
+  blocks = std::min(blocks, max_blocks);
+  if (blocks > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+  P.write_blocks = uint32_t(std::max<uint64_t>(blocks, 1));
+  P.rows_per_tile = T_rows;
+  P.ntiles = ntiles;
+  return ZSET_OK;
+}
+
+// Leaf-order row format for elements p <= n: fields floor(p / G) <= n / G and
+// m_c <= n / h_c, packed into one 32- or 64-bit word when they fit.
+void leaf_format(EnumParams& P, uint64_t n, const uint32_t* gens, int U, int k) {
+  uint32_t shift = 0;
+  for (int c2 = 0; c2 <= k; ++c2) {
+    const uint32_t vmax = uint32_t(n / gens[U + c2]);
+    uint32_t bits = 0;
+    while (bits < 32 && (uint64_t(vmax) >> bits) != 0) ++bits;
+    P.fshift[c2] = shift;
+    P.fmask[c2] = bits >= 32 ? ~0u : ((1u << bits) - 1u);
+    shift += bits;
+  }
+  P.pack = shift <= 32 ? 1 : (shift <= 64 ? 2 : 0);
+}
+
 bool is_device_pointer(const void* p) {
   hipPointerAttribute_t attr;
   std::memset(&attr, 0, sizeof attr);
@@ -224,15 +296,6 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint
 }  // namespace
 }  // namespace zset
 
-struct zset_memo_s {
-  int device;
-  int k;
-  uint64_t top;
-  uint64_t rows;
-  uint32_t h[zset::kMaxD];
-  uint64_t* off;  // device, top + 1
-  uint32_t* nat;  // device, rows * k
-};
 
 using namespace zset;
 
@@ -525,13 +588,14 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     P.k = k;
     P.total = total;
     P.table = T;
+    P.table_stride = N;
     P.err = err;
     P.checksum = misc + kMiscSum;
     P.out = out;
     P.dG = DivMod32::make(G);
     P.ring = d <= 16 ? 128 : 64;
     P.flush = P.ring / 2;
-    P.max_tiles = kMinTileStates;  // grown below to what LDS leaves at this occupancy
+    P.max_tiles = kMinTileStates;  // grown by size_write_pass to what LDS leaves
 
     // 3. Memo (k >= 1): natural-order rows, then the leaf-order layout.
     ZSET_HIP(hipEventRecord(c->ev[2], s));
@@ -559,19 +623,8 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         off = o;
         nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       }
-      // Leaf-order row format: fields floor(p / G) <= n / G and m_c <= n / h_c,
-      // packed into one 32- or 64-bit word when they fit, and then copied to
-      // LDS by the write pass when that fits too.
-      uint32_t shift = 0;
-      for (int c2 = 0; c2 <= k; ++c2) {
-        const uint32_t vmax = uint32_t(n / gens[U + c2]);
-        uint32_t bits = 0;
-        while (bits < 32 && (uint64_t(vmax) >> bits) != 0) ++bits;
-        P.fshift[c2] = shift;
-        P.fmask[c2] = bits >= 32 ? ~0u : ((1u << bits) - 1u);
-        shift += bits;
-      }
-      P.pack = shift <= 32 ? 1 : (shift <= 64 ? 2 : 0);
+      // Leaf-order row format, copied to LDS by the write pass when it fits.
+      leaf_format(P, n, gens, U, k);
       P.nclass = uint32_t(std::min<uint64_t>(G, N));
       const char* lds_env = std::getenv("ZSET_MEMO_LDS");
       const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
@@ -610,55 +663,12 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     // concurrent write streams of a compute unit close together in memory and
     // the end of the pass even).
     const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-    // Slices 0..static_tiles-1 are dealt round-robin; the last claim_pct
-    // percent (all, by default) are claimed at run time in chunks of one slice
-    // per wavefront by the workgroups that have capacity: compute units do not
-    // all drain HBM at one rate, so a fixed share per workgroup ends with the
-    // slowest.
-    const int pct = opts.claim_pct < 0 ? kDefaultClaimPct : opts.claim_pct;
     P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
-    P.chunk = pct > 0 ? uint32_t(write_waves_per_block()) : 0;
-    if (P.chunk && write_lds_bytes(P) > size_t(max_lds_bytes(c))) P.chunk = 0;
-    int cus = 0, per_cu = 0;
-    ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    ZSET_HIP(write_occupancy(P, count_only, align16, &per_cu));
-    if (per_cu < 1) return fail(ZSET_EDEVICE, "the write pass does not fit on a compute unit");
-    const uint64_t wpb = uint64_t(write_waves_per_block());
-    const uint64_t resident_waves = uint64_t(cus) * per_cu * wpb;
-    T_rows = opts.rows_per_tile;
-    if (T_rows == 0) {
-      const uint64_t want_tiles = resident_waves * 128;
-      T_rows = (total + want_tiles - 1) / want_tiles;
-      T_rows = (T_rows + 127) / 128 * 128;
-      T_rows = std::max<uint64_t>(T_rows, 128);
-      T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 30);
-    }
-    ntiles = (total + T_rows - 1) / T_rows;
-    if (ntiles > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
-    {
-      const uint64_t resident = uint64_t(cus) * per_cu;
-      P.static_tiles = P.chunk ? ntiles - (ntiles * uint64_t(pct) + 99) / 100 : ntiles;
-      // Give each resident workgroup room for the start states of all of its
-      // dealt slices when the LDS left over at this occupancy allows, so that
-      // the grid stays one resident round.
-      const uint64_t need = (P.static_tiles + resident - 1) / resident;
-      const size_t budget = size_t(max_lds_bytes(c)) / size_t(per_cu);
-      const size_t base = write_lds_bytes(P);  // with kMinTileStates states
-      const uint64_t per_state = uint64_t(U + 2) * sizeof(uint32_t);
-      uint64_t fit = P.max_tiles;
-      if (budget > base + 16) fit += (budget - base - 16) / per_state;
-      P.max_tiles = uint32_t(std::min<uint64_t>(std::max<uint64_t>(need, kMinTileStates),
-                                                std::min<uint64_t>(fit, 1u << 20)));
-      uint64_t blocks = uint64_t(cus) * per_cu;
-      const uint64_t min_blocks = (P.static_tiles + P.max_tiles - 1) / P.max_tiles;
-      const uint64_t max_blocks = (ntiles + wpb - 1) / wpb;
-      blocks = std::max(blocks, min_blocks);
-      blocks = std::min(blocks, max_blocks);
-      if (blocks > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
-      P.write_blocks = uint32_t(std::max<uint64_t>(blocks, 1));
-    }
-    P.rows_per_tile = T_rows;
-    P.ntiles = ntiles;
+    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, c->device, count_only, align16)) !=
+        ZSET_OK)
+      return st;
+    T_rows = P.rows_per_tile;
+    ntiles = P.ntiles;
     if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
     P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
     ZSET_HIP(launch_plan(P, s));

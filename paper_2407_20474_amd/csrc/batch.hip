@@ -442,6 +442,7 @@ zset_status plan_queries(zset_batch b, const int* kreq, const uint64_t* treq, in
     const uint64_t N = q.n + 1;
     EnumParams& P = q.P;
     P.table = table0 + q.table_off;
+    P.table_stride = q.n + 1;
     P.err = err;
     P.checksum = at<uint64_t>(b->checksums, uint64_t(i));
     P.out = nullptr;

@@ -96,7 +96,7 @@ __device__ inline uint32_t wave_incl_sum_sat(uint32_t v, uint32_t cap) {
 
 // Slice start: first U coordinates and the offset t0 inside their block.
 __device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
-  const uint64_t N = uint64_t(P.n) + 1;
+  const uint64_t N = P.table_stride;
   uint64_t r = tile * P.rows_per_tile;
   uint32_t x = P.n;
   uint32_t* st = P.tiles + tile * uint64_t(P.U + 2);
@@ -237,7 +237,7 @@ __device__ inline TileArgs tile_args(const EnumParams& P) {
   A.flush = P.flush;
   A.total = P.total;
   A.rows_per_tile = P.rows_per_tile;
-  A.cnt_row = P.table + uint64_t(P.U) * (uint64_t(P.n) + 1);
+  A.cnt_row = P.table + uint64_t(P.U) * P.table_stride;
   A.endc = P.endc;
   A.leaf = P.leaf;
   A.leaf_rows = P.leaf_rows;
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   }
   if (MODE == 1 && LDSCNT) {
     // Values fit 32 bits (checked by the host).
-    const uint64_t* cu = P.table + uint64_t(U) * N;
+    const uint64_t* cu = P.table + uint64_t(U) * P.table_stride;
     for (uint64_t x = threadIdx.x; x < N; x += blockDim.x) lds_cnt[x] = uint32_t(cu[x]);
     for (uint32_t r = threadIdx.x; r < P.nclass; r += blockDim.x) lds_endc[r] = uint32_t(P.endc[r]);
   }
@@ -782,7 +782,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write_batch(
     }
     if (k >= 1 && ldscnt) {
       const uint64_t N = uint64_t(rfl(P.n)) + 1;
-      const uint64_t* cu = rflp(P.table) + uint64_t(U) * N;
+      const uint64_t* cu = rflp(P.table) + uint64_t(U) * rfl64(P.table_stride);
       const uint64_t* endc = rflp(P.endc);
       const uint32_t nclass = rfl(P.nclass);
       for (uint64_t x = threadIdx.x; x < N; x += blockDim.x) lds_cnt[x] = uint32_t(cu[x]);

@@ -1,0 +1,593 @@
+// serve.hip -- a request loop over resident generator sets (zset_server_*).
+//
+// A generator set g is made resident once, up to an element bound n_max:
+//   * its count table C[j][x] = |Z(x; g_j..g_d)| for x <= n_max, on the device,
+//     with a host copy of row 0 (|Z(n)| for every n <= n_max), which prices a
+//     query's output bytes (|Z(n)| d 4) without touching the device;
+//   * for memo dimension k >= 1, the memo Z(p; h) of the trailing k generators
+//     for p <= n_max, built by the dynamic recurrence (zset_memo_build), and its
+//     leaf-order layout with the residue-class ends.  A segment Z(x; G, h)
+//     starts at end[x mod G] - C_U[x] whatever the query's n, as long as
+//     x <= n_max, so one layout serves every n <= n_max.
+// A query (set, n) then needs only the slice plan and the write pass, with no
+// host synchronisation.  Queries run on `slots` streams at once (continuous
+// batching): a dispatcher thread admits waiting queries in arrival order as a
+// slot and room in the output arena become free, launches them, watches their
+// completion events and stamps submit / admit / done times on the host's
+// steady clock.  The rows of a query are the bytes zset_enumerate_ex writes
+// for it alone: the kernels and their arguments are the same, only the memo
+// covers more elements.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "zset.h"
+#include "zset_host.h"
+#include "zset_internal.h"
+
+namespace zset {
+namespace {
+
+constexpr int kMaxSlots = 64;
+constexpr int kDefaultSlots = 8;
+// Slices of one query at most: size_write_pass picks about 128 per resident
+// wavefront (and rows_per_tile >= 128 rows below that), so this bounds every
+// query's slice table once the device's resident wavefronts are known.
+constexpr uint64_t kSlicesPerWave = 128;
+
+double now_us(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
+}
+
+struct ResidentSet {
+  int d = 0, k = 0, L = 0, U = 0;
+  uint32_t g[kMaxD] = {};
+  uint64_t n_max = 0;
+  std::vector<uint64_t> c0;  // |Z(n)| for n <= n_max
+  DevBuf table, endc, leaf;
+  uint64_t memo_rows = 0;
+  uint64_t sum_u = 0;        // sum over x <= n_max of C_U[x]
+  EnumParams tmpl;           // per-set fields of the write pass
+};
+
+enum ReqState { kQueued = 0, kRunning = 1, kDone = 2, kFailed = 3 };
+
+struct Request {
+  int set = 0;
+  uint64_t n = 0, rows = 0, words = 0, out_off = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int state = kQueued;
+  int slot = -1;
+  zset_status status = ZSET_OK;
+  std::string msg;
+};
+
+struct Slot {
+  hipStream_t s = nullptr;
+  hipEvent_t done = nullptr;
+  DevBuf tiles, misc;  // misc: [0] status word, [1] checksum, [2] chunk counter
+  int* pinned = nullptr;
+  uint64_t ticket = 0;
+  bool busy = false;
+};
+
+}  // namespace
+}  // namespace zset
+
+struct zset_server_s {
+  int device = 0;
+  std::chrono::steady_clock::time_point t0;
+  std::vector<zset::ResidentSet*> sets;
+  std::vector<zset::Slot> slots;
+  uint32_t* arena = nullptr;
+  uint64_t arena_words = 0;
+  std::map<uint64_t, uint64_t> free_list;  // word offset -> words, coalesced
+  uint64_t slice_cap = 0;                  // slices one slot's table holds
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, zset::Request> reqs;
+  uint64_t next_ticket = 1;
+  std::thread worker;
+  bool stop = false;
+  uint64_t admitted = 0, completed = 0, max_inflight = 0;
+};
+
+namespace zset {
+namespace {
+
+uint64_t words_of(uint64_t rows, int d) { return (rows * uint64_t(d) + 3) / 4 * 4; }
+
+// First fit in the arena (16-byte granules); false when no hole is large enough.
+bool arena_alloc(zset_server_s* S, uint64_t words, uint64_t* off) {
+  for (auto it = S->free_list.begin(); it != S->free_list.end(); ++it) {
+    if (it->second >= words) {
+      *off = it->first;
+      const uint64_t rest = it->second - words, at = it->first + words;
+      S->free_list.erase(it);
+      if (rest) S->free_list[at] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void arena_free(zset_server_s* S, uint64_t off, uint64_t words) {
+  if (words == 0) return;
+  auto it = S->free_list.emplace(off, words).first;
+  auto next = std::next(it);
+  if (next != S->free_list.end() && it->first + it->second == next->first) {
+    it->second += next->second;
+    S->free_list.erase(next);
+  }
+  if (it != S->free_list.begin()) {
+    auto prev = std::prev(it);
+    if (prev->first + prev->second == it->first) {
+      prev->second += it->second;
+      S->free_list.erase(it);
+    }
+  }
+}
+
+// Enqueues one admitted query on its slot's stream.  Called by the dispatcher
+// with the server lock held; every call is asynchronous.
+zset_status launch_query(zset_server_s* S, Request& r, Slot& sl) {
+  const ResidentSet& R = *S->sets[r.set];
+  int* err = reinterpret_cast<int*>(sl.misc.p);
+  uint64_t* misc = reinterpret_cast<uint64_t*>(sl.misc.p);
+  uint32_t* out = S->arena + r.out_off;
+  ZSET_HIP(hipMemsetAsync(sl.misc.p, 0, 3 * sizeof(uint64_t), sl.s));
+  if (r.rows > 0 && R.d == 1) {
+    ZSET_HIP(launch_single(r.n, R.g[0], out, false, misc + 1, sl.s));
+  } else if (r.rows > 0) {
+    EnumParams P = R.tmpl;
+    P.n = uint32_t(r.n);
+    P.total = r.rows;
+    P.out = out;
+    P.err = err;
+    P.checksum = misc + 1;
+    P.pool = reinterpret_cast<uint32_t*>(misc + 2);
+    P.lds_cnt = 0;
+    const size_t lds_max = size_t(device_max_lds_bytes(S->device));
+    if (R.k >= 1 && R.sum_u < (uint64_t(1) << 32) && R.memo_rows < (uint64_t(1) << 32)) {
+      P.lds_cnt = 1;
+      if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
+    }
+    zset_status st = size_write_pass(P, 0, -1, S->device, false, true);
+    if (st != ZSET_OK) return st;
+    if (P.ntiles > S->slice_cap) return fail(ZSET_EDEVICE, "internal: slice table too small");
+    P.tiles = reinterpret_cast<uint32_t*>(sl.tiles.p);
+    ZSET_HIP(launch_plan(P, sl.s));
+    ZSET_HIP(launch_write(P, false, true, sl.s));
+  }
+  ZSET_HIP(hipMemcpyAsync(sl.pinned, err, sizeof(int), hipMemcpyDeviceToHost, sl.s));
+  ZSET_HIP(hipEventRecord(sl.done, sl.s));
+  return ZSET_OK;
+}
+
+void dispatcher(zset_server_s* S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lock(S->mu);
+  for (;;) {
+    bool busy = false;
+    // Completions.
+    for (Slot& sl : S->slots) {
+      if (!sl.busy) continue;
+      const hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) {
+        busy = true;
+        continue;
+      }
+      Request& r = S->reqs[sl.ticket];
+      r.t_done = now_us(S->t0);
+      if (q != hipSuccess) {
+        (void)hipGetLastError();
+        r.state = kFailed;
+        r.status = ZSET_EDEVICE;
+        r.msg = std::string("query on the device: ") + hipGetErrorString(q);
+      } else if (*sl.pinned != 0) {
+        r.state = kFailed;
+        r.status = ZSET_EDEVICE;
+        r.msg = device_error_text(*sl.pinned);
+      } else {
+        r.state = kDone;
+      }
+      sl.busy = false;
+      ++S->completed;
+      S->cv.notify_all();
+    }
+    // Admissions, in arrival order: the head waits for a slot and for room in
+    // the arena.
+    while (!S->queue.empty()) {
+      Slot* free_slot = nullptr;
+      for (Slot& sl : S->slots)
+        if (!sl.busy) {
+          free_slot = &sl;
+          break;
+        }
+      if (!free_slot) break;
+      const uint64_t t = S->queue.front();
+      Request& r = S->reqs[t];
+      if (r.words > 0 && !arena_alloc(S, r.words, &r.out_off)) break;
+      S->queue.pop_front();
+      r.t_admit = now_us(S->t0);
+      const zset_status st = launch_query(S, r, *free_slot);
+      if (st != ZSET_OK) {
+        r.state = kFailed;
+        r.status = st;
+        r.msg = g_last_error;
+        r.t_done = now_us(S->t0);
+        S->cv.notify_all();
+        continue;
+      }
+      r.state = kRunning;
+      r.slot = int(free_slot - S->slots.data());
+      free_slot->ticket = t;
+      free_slot->busy = true;
+      busy = true;
+      ++S->admitted;
+    }
+    if (S->stop) {  // queries never admitted end here, with an error
+      for (const uint64_t t : S->queue) {
+        Request& r = S->reqs[t];
+        r.state = kFailed;
+        r.status = ZSET_EINVAL;
+        r.msg = "the server stopped before the query was admitted";
+      }
+      S->queue.clear();
+      S->cv.notify_all();
+    }
+    uint64_t inflight = 0;
+    for (Slot& sl : S->slots) inflight += sl.busy ? 1 : 0;
+    S->max_inflight = std::max(S->max_inflight, inflight);
+    if (S->stop && !busy && S->queue.empty()) break;
+    if (!busy) {
+      // Nothing on the device: sleep until a submission, a release (room in
+      // the arena) or the end.
+      S->cv.wait(lock);
+    } else {
+      lock.unlock();
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      lock.lock();
+    }
+  }
+}
+
+}  // namespace
+}  // namespace zset
+
+using namespace zset;
+
+void zset_server_default_opts(zset_server_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->slots = kDefaultSlots;
+}
+
+zset_status zset_server_create(const zset_server_opts* opts, zset_server* out) {
+  g_last_error.clear();
+  if (!opts || !out) return fail(ZSET_EINVAL, "opts or server is NULL");
+  *out = nullptr;
+  const int slots = opts->slots ? opts->slots : kDefaultSlots;
+  if (slots < 1 || slots > kMaxSlots) return fail(ZSET_EINVAL, "slots must lie in [1, 64]");
+  if (!opts->arena || opts->arena_bytes < 16)
+    return fail(ZSET_EINVAL, "the output arena is missing or smaller than 16 bytes");
+  if ((reinterpret_cast<uintptr_t>(opts->arena) & 15) != 0)
+    return fail(ZSET_EINVAL, "the output arena must be 16-byte aligned");
+  if (!is_device_pointer(opts->arena)) return fail(ZSET_EINVAL, "the arena is not device memory");
+  zset_server_s* S = new zset_server_s();
+  S->t0 = std::chrono::steady_clock::now();
+  auto bail = [&](zset_status st) {
+    zset_server_free(S);
+    return st;
+  };
+  int cus = 0;
+  if (hipGetDevice(&S->device) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, S->device) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(ZSET_EDEVICE, "device query failed"));
+  }
+  S->arena = reinterpret_cast<uint32_t*>(opts->arena);
+  S->arena_words = opts->arena_bytes / 16 * 4;
+  S->free_list[0] = S->arena_words;
+  // At most 2 write workgroups per compute unit fit beside the smallest memo.
+  S->slice_cap = uint64_t(cus) * 2 * write_waves_per_block() * kSlicesPerWave + 1;
+  S->slots.resize(slots);
+  for (Slot& sl : S->slots) {
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(ZSET_EDEVICE, "stream or event creation failed"));
+    }
+    if (hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), 16, hipHostMallocDefault) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(ZSET_ENOMEM, "hipHostMalloc failed"));
+    }
+    zset_status st = ensure(sl.misc, 4 * sizeof(uint64_t));
+    if (st == ZSET_OK)
+      st = ensure(sl.tiles, size_t(S->slice_cap) * (kMaxD + 2) * sizeof(uint32_t));
+    if (st != ZSET_OK) return bail(st);
+  }
+  S->worker = std::thread(dispatcher, S);
+  *out = S;
+  return ZSET_OK;
+}
+
+zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint64_t n_max, int k,
+                                int* set_id) {
+  g_last_error.clear();
+  if (!S || !set_id) return fail(ZSET_EINVAL, "server or set_id is NULL");
+  zset_status st = check_query(n_max, gens, d);
+  if (st != ZSET_OK) return st;
+  if (k < -1 || k > d - 1) return fail(ZSET_EINVAL, "k must be -1 or lie in [0, d-1]");
+  ResidentSet* R = new ResidentSet();
+  auto bail = [&](zset_status e) {
+    for (DevBuf* b : {&R->table, &R->endc, &R->leaf})
+      if (b->p) (void)hipFree(b->p);
+    delete R;
+    return e;
+  };
+  R->d = d;
+  R->n_max = n_max;
+  for (int i = 0; i < d; ++i) R->g[i] = gens[i];
+  const uint64_t N = n_max + 1;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(ZSET_EDEVICE, "hipStreamCreate failed"));
+  }
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } guard{s};
+  DevBuf scratch;  // row sums, status word
+  struct ScratchGuard {
+    DevBuf& b;
+    ~ScratchGuard() {
+      if (b.p) (void)hipFree(b.p);
+    }
+  } sguard{scratch};
+  if ((st = ensure(R->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return bail(st);
+  if ((st = ensure(scratch, (kMaxD + 2) * sizeof(uint64_t))) != ZSET_OK) return bail(st);
+  uint64_t* T = reinterpret_cast<uint64_t*>(R->table.p);
+  uint64_t* sums_dev = reinterpret_cast<uint64_t*>(scratch.p);
+  int* err = reinterpret_cast<int*>(sums_dev + kMaxD + 1);
+  if (hipMemsetAsync(scratch.p, 0, (kMaxD + 2) * sizeof(uint64_t), s) != hipSuccess ||
+      launch_count_table(T, n_max, gens, d, sums_dev, s) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(ZSET_EDEVICE, "count table launch failed"));
+  }
+  uint64_t sums[kMaxD + 1];
+  R->c0.resize(N);
+  if (hipMemcpyAsync(sums, sums_dev, (d + 1) * sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(R->c0.data(), T, N * sizeof(uint64_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipGetLastError();
+    return bail(fail(ZSET_EDEVICE, "count table readback failed"));
+  }
+  const size_t lds_max = size_t(device_max_lds_bytes(S->device));
+
+  // Memo dimension: the requested one, else the largest k whose packed memo
+  // over p <= n_max fits in the write pass's LDS; else k = 0 (the last
+  // coordinate by division).
+  auto tmpl_for = [&](int kk, EnumParams& P) {
+    std::memset(&P, 0, sizeof P);
+    const int L = d - std::max(kk, 1);
+    const int U = (kk == 0) ? d - 1 : L - 1;
+    for (int i = 0; i < d; ++i) P.g.g[i] = gens[i];
+    P.n = uint32_t(n_max);
+    P.d = d;
+    P.U = U;
+    P.k = kk;
+    P.table = T;
+    P.table_stride = N;
+    P.dG = DivMod32::make(gens[U]);
+    P.ring = d <= 16 ? 128 : 64;
+    P.flush = P.ring / 2;
+    P.max_tiles = 16;
+    P.chunk = uint32_t(write_waves_per_block());
+    if (kk >= 1) {
+      leaf_format(P, n_max, gens, U, kk);
+      const uint64_t Rn = sums[L];
+      if (Rn >= (uint64_t(1) << 32)) P.pack = 0;
+      P.memo_words = P.pack ? Rn * uint64_t(P.pack) : 0;
+      P.nclass = uint32_t(std::min<uint64_t>(gens[U], N));
+      P.leaf_rows = Rn;
+    }
+  };
+  int kk = k;
+  if (d == 1) {
+    kk = 0;
+  } else if (kk < 0) {
+    kk = 0;
+    for (int c = d - 1; c >= 1; --c) {
+      EnumParams P;
+      tmpl_for(c, P);
+      if (P.pack != 0 && write_lds_bytes(P) <= lds_max) {
+        kk = c;
+        break;
+      }
+    }
+  }
+  R->k = kk;
+  R->L = d - std::max(kk, 1);
+  R->U = (kk == 0) ? d - 1 : R->L - 1;
+  tmpl_for(kk, R->tmpl);
+  R->sum_u = sums[R->U];
+  if (kk >= 1 && d >= 2) {
+    EnumParams& P = R->tmpl;
+    const uint64_t Rn = sums[R->L];
+    R->memo_rows = Rn;
+    if (P.pack != 0 && write_lds_bytes(P) > lds_max) {
+      P.pack = 0;
+      P.memo_words = 0;
+    }
+    zset_memo m = nullptr;
+    if ((st = zset_memo_build(gens + R->L, kk, N, s, &m)) != ZSET_OK) return bail(st);
+    struct MemoGuard {
+      zset_memo m;
+      ~MemoGuard() { zset_memo_free(m); }
+    } mguard{m};
+    if (m->rows != Rn) return bail(fail(ZSET_EDEVICE, "internal: resident memo size"));
+    const uint32_t G = gens[R->U];
+    const uint64_t leaf_words = P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(kk + 1);
+    if ((st = ensure(R->endc, size_t(P.nclass) * sizeof(uint64_t))) != ZSET_OK) return bail(st);
+    if ((st = ensure(R->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return bail(st);
+    uint64_t* endc = reinterpret_cast<uint64_t*>(R->endc.p);
+    uint32_t* leaf = reinterpret_cast<uint32_t*>(R->leaf.p);
+    uint32_t nclass = 0;
+    const uint64_t* cu = T + uint64_t(R->U) * N;
+    if (launch_class_ends(cu, n_max, G, endc, &nclass, s) != hipSuccess ||
+        launch_memo_leaf(make_leaf_job(kk, n_max, G, m->off, m->nat, cu, endc, leaf, Rn, P), err,
+                         s) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(ZSET_EDEVICE, "leaf layout launch failed"));
+    }
+    int code = 0;
+    if (hipMemcpyAsync(&code, err, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      (void)hipGetLastError();
+      return bail(fail(ZSET_EDEVICE, "leaf layout failed"));
+    }
+    if (code != 0) return bail(fail(ZSET_EDEVICE, device_error_text(code)));
+    P.endc = endc;
+    P.leaf = leaf;
+    P.nclass = nclass;
+  }
+  std::lock_guard<std::mutex> lock(S->mu);
+  S->sets.push_back(R);
+  *set_id = int(S->sets.size() - 1);
+  return ZSET_OK;
+}
+
+zset_status zset_server_set_info(zset_server S, int set_id, int* k, uint64_t* n_max,
+                                 uint64_t* memo_rows, uint64_t* resident_bytes) {
+  g_last_error.clear();
+  if (!S) return fail(ZSET_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lock(S->mu);
+  if (set_id < 0 || set_id >= int(S->sets.size())) return fail(ZSET_EINVAL, "no such set");
+  const ResidentSet& R = *S->sets[set_id];
+  if (k) *k = R.k;
+  if (n_max) *n_max = R.n_max;
+  if (memo_rows) *memo_rows = R.memo_rows;
+  if (resident_bytes) *resident_bytes = R.table.bytes + R.endc.bytes + R.leaf.bytes;
+  return ZSET_OK;
+}
+
+zset_status zset_server_count(zset_server S, int set_id, uint64_t n, uint64_t* rows) {
+  g_last_error.clear();
+  if (!S || !rows) return fail(ZSET_EINVAL, "server or rows is NULL");
+  std::lock_guard<std::mutex> lock(S->mu);
+  if (set_id < 0 || set_id >= int(S->sets.size())) return fail(ZSET_EINVAL, "no such set");
+  const ResidentSet& R = *S->sets[set_id];
+  if (n > R.n_max) return fail(ZSET_EINVAL, "n exceeds the set's n_max");
+  *rows = R.c0[n];
+  if (*rows == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
+  return ZSET_OK;
+}
+
+zset_status zset_server_submit(zset_server S, int set_id, uint64_t n, uint64_t* ticket) {
+  g_last_error.clear();
+  if (!S || !ticket) return fail(ZSET_EINVAL, "server or ticket is NULL");
+  std::lock_guard<std::mutex> lock(S->mu);
+  if (S->stop) return fail(ZSET_EINVAL, "the server is stopping");
+  if (set_id < 0 || set_id >= int(S->sets.size())) return fail(ZSET_EINVAL, "no such set");
+  const ResidentSet& R = *S->sets[set_id];
+  if (n > R.n_max) return fail(ZSET_EINVAL, "n exceeds the set's n_max");
+  const uint64_t rows = R.c0[n];
+  if (rows == ~uint64_t(0) || rows > (~uint64_t(0)) / (4 * uint64_t(R.d)))
+    return fail(ZSET_EOVERFLOW, "|Z(n)| * d * 4 bytes overflows 64 bits");
+  const uint64_t words = words_of(rows, R.d);
+  if (words > S->arena_words)
+    return fail(ZSET_ECAPACITY, "the query's rows exceed the whole output arena");
+  const uint64_t t = S->next_ticket++;
+  Request& r = S->reqs[t];
+  r.set = set_id;
+  r.n = n;
+  r.rows = rows;
+  r.words = words;
+  r.t_submit = now_us(S->t0);
+  S->queue.push_back(t);
+  *ticket = t;
+  S->cv.notify_all();
+  return ZSET_OK;
+}
+
+zset_status zset_server_wait(zset_server S, uint64_t ticket, zset_server_result* res) {
+  g_last_error.clear();
+  if (!S) return fail(ZSET_EINVAL, "server is NULL");
+  std::unique_lock<std::mutex> lock(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(ZSET_EINVAL, "unknown ticket");
+  S->cv.wait(lock, [&] { return it->second.state >= kDone; });
+  const Request& r = it->second;
+  if (res) {
+    res->rows = r.rows;
+    res->out_offset = r.out_off;
+    res->submit_us = r.t_submit;
+    res->admit_us = r.t_admit;
+    res->done_us = r.t_done;
+  }
+  if (r.state == kFailed) return fail(r.status, r.msg);
+  return ZSET_OK;
+}
+
+zset_status zset_server_release(zset_server S, uint64_t ticket) {
+  g_last_error.clear();
+  if (!S) return fail(ZSET_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lock(S->mu);
+  auto it = S->reqs.find(ticket);
+  if (it == S->reqs.end()) return fail(ZSET_EINVAL, "unknown ticket");
+  if (it->second.state < kDone) return fail(ZSET_EINVAL, "the query has not finished");
+  if (it->second.t_admit > 0 && it->second.words > 0)
+    arena_free(S, it->second.out_off, it->second.words);
+  S->reqs.erase(it);
+  S->cv.notify_all();
+  return ZSET_OK;
+}
+
+zset_status zset_server_stats(zset_server S, uint64_t* admitted, uint64_t* completed,
+                              uint64_t* max_inflight) {
+  g_last_error.clear();
+  if (!S) return fail(ZSET_EINVAL, "server is NULL");
+  std::lock_guard<std::mutex> lock(S->mu);
+  if (admitted) *admitted = S->admitted;
+  if (completed) *completed = S->completed;
+  if (max_inflight) *max_inflight = S->max_inflight;
+  return ZSET_OK;
+}
+
+void zset_server_free(zset_server S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lock(S->mu);
+    S->stop = true;
+    S->cv.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  for (Slot& sl : S->slots) {
+    if (sl.s) (void)hipStreamSynchronize(sl.s);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (sl.s) (void)hipStreamDestroy(sl.s);
+    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    for (DevBuf* b : {&sl.tiles, &sl.misc})
+      if (b->p) (void)hipFree(b->p);
+  }
+  for (ResidentSet* R : S->sets) {
+    for (DevBuf* b : {&R->table, &R->endc, &R->leaf})
+      if (b->p) (void)hipFree(b->p);
+    delete R;
+  }
+  delete S;
+}

@@ -35,6 +35,13 @@ zset_status check_query(uint64_t n, const uint32_t* gens, int d);
 bool is_device_pointer(const void* p);
 const char* device_error_text(int code);
 int device_max_lds_bytes(int device);
+
+struct EnumParams;
+// Write-pass sizing (slice length, claimed chunks, slice-state capacity, grid)
+// and the leaf-order row format; shared by the single-query path and the server.
+zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
+                            bool count_only, bool align16);
+void leaf_format(EnumParams& P, uint64_t n, const uint32_t* gens, int U, int k);
 uint32_t next_pow2(uint32_t v);
 float elapsed_us(hipEvent_t a, hipEvent_t b);
 
@@ -45,3 +52,15 @@ float elapsed_us(hipEvent_t a, hipEvent_t b);
     hipError_t e_ = (call);                                \
     if (e_ != hipSuccess) return ::zset::hip_fail(e_, #call); \
   } while (0)
+
+// Memo handle (zset_memo): natural-order lists on the device.
+struct zset_memo_s {
+  int device;
+  int k;
+  uint64_t top;
+  uint64_t rows;
+  uint32_t h[ZSET_MAX_D];
+  uint64_t* off;  // device, top + 1
+  uint32_t* nat;  // device, rows * k
+};
+

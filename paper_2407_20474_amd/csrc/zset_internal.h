@@ -20,7 +20,8 @@ struct EnumParams {
   uint64_t total;           // |Z(n)|
   uint64_t rows_per_tile;   // rows per slice (multiple of 128)
   uint64_t ntiles;          // slices
-  const uint64_t* table;    // count table, (d+1) x (n+1)
+  const uint64_t* table;    // count table, (d+1) rows of table_stride entries (x = 0..n used)
+  uint64_t table_stride;    // entries per count-table row: n + 1, or more for a resident table
   const uint64_t* endc;     // residue-class ends of the leaf-order memo (k >= 1)
   const uint32_t* leaf;     // leaf-order memo rows, k+1 uint32 each (k >= 1)
   uint64_t leaf_rows;       // rows in `leaf`

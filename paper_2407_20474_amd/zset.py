@@ -25,6 +25,9 @@ SYMBOLS = (
     "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
     "zset_batch_default_opts", "zset_batch_create", "zset_batch_info", "zset_batch_run",
     "zset_batch_times", "zset_batch_free",
+    "zset_server_default_opts", "zset_server_create", "zset_server_add_set",
+    "zset_server_set_info", "zset_server_count", "zset_server_submit", "zset_server_wait",
+    "zset_server_release", "zset_server_stats", "zset_server_free",
     "zset_strerror", "zset_selftest_host", "zset_last_error",
 )
 
@@ -33,6 +36,20 @@ class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("order", ctypes.c_int),
                 ("rows_per_tile", ctypes.c_uint64), ("count_only", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("claim_pct", ctypes.c_int)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int), ("arena", ctypes.c_void_p),
+                ("arena_bytes", ctypes.c_uint64)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("rows", ctypes.c_uint64), ("out_offset", ctypes.c_uint64),
+                ("submit_us", ctypes.c_double), ("admit_us", ctypes.c_double),
+                ("done_us", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Stats(ctypes.Structure):
@@ -114,6 +131,21 @@ def load():
     lib.zset_batch_times.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.zset_batch_free.argtypes = [ctypes.c_void_p]
     lib.zset_batch_free.restype = None
+    lib.zset_server_default_opts.argtypes = [ctypes.POINTER(ServerOpts)]
+    lib.zset_server_default_opts.restype = None
+    lib.zset_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]
+    lib.zset_server_add_set.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_int, _i32p]
+    lib.zset_server_set_info.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p, _u64p, _u64p,
+                                         _u64p]
+    lib.zset_server_count.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, _u64p]
+    lib.zset_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, _u64p]
+    lib.zset_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.POINTER(ServerResult)]
+    lib.zset_server_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
+    lib.zset_server_stats.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p]
+    lib.zset_server_free.argtypes = [ctypes.c_void_p]
+    lib.zset_server_free.restype = None
     lib.zset_strerror.argtypes = [ctypes.c_int]
     lib.zset_strerror.restype = ctypes.c_char_p
     lib.zset_selftest_host.argtypes = []
@@ -121,7 +153,10 @@ def load():
     lib.zset_last_error.restype = ctypes.c_char_p
     for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
                  "zset_enumerate", "zset_enumerate_ex", "zset_batch_create", "zset_batch_info",
-                 "zset_batch_run", "zset_batch_times", "zset_selftest_host"):
+                 "zset_batch_run", "zset_batch_times", "zset_selftest_host",
+                 "zset_server_create", "zset_server_add_set", "zset_server_set_info",
+                 "zset_server_count", "zset_server_submit", "zset_server_wait",
+                 "zset_server_release", "zset_server_stats"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -364,6 +399,89 @@ class Batch:
     def free(self):
         if self._handle is not None and self._handle.value:
             load().zset_batch_free(self._handle)
+        self._handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop over resident generator sets (zset_server_*).
+
+    `arena` is a contiguous int32 CUDA tensor that the outputs are carved from;
+    the caller keeps it alive while the server runs.  Submission never blocks;
+    wait() blocks until a query is done (the GIL is released meanwhile)."""
+
+    def __init__(self, arena, slots: int = 8):
+        if arena.dtype.itemsize != 4 or not arena.is_contiguous():
+            raise ValueError("arena must be a contiguous 4-byte CUDA tensor")
+        self.arena = arena.reshape(-1)
+        self.d = []
+        opts = ServerOpts()
+        load().zset_server_default_opts(ctypes.byref(opts))
+        opts.slots = slots
+        opts.arena = self.arena.data_ptr()
+        opts.arena_bytes = self.arena.numel() * 4
+        handle = ctypes.c_void_p(None)
+        _check(load().zset_server_create(ctypes.byref(opts), ctypes.byref(handle)),
+               "zset_server_create")
+        self._handle = handle
+
+    def add_set(self, gens, n_max: int, k: int = -1) -> int:
+        g = _gens(gens)
+        sid = ctypes.c_int()
+        _check(load().zset_server_add_set(self._handle, g.ctypes.data_as(_u32p), len(g), n_max, k,
+                                          ctypes.byref(sid)), "zset_server_add_set")
+        self.d.append(len(g))
+        return int(sid.value)
+
+    def set_info(self, set_id: int) -> dict:
+        k, n_max, rows, nbytes = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().zset_server_set_info(self._handle, set_id, ctypes.byref(k),
+                                           ctypes.byref(n_max), ctypes.byref(rows),
+                                           ctypes.byref(nbytes)), "zset_server_set_info")
+        return {"k": int(k.value), "n_max": int(n_max.value), "memo_rows": int(rows.value),
+                "resident_bytes": int(nbytes.value)}
+
+    def count(self, set_id: int, n: int) -> int:
+        v = ctypes.c_uint64()
+        _check(load().zset_server_count(self._handle, set_id, n, ctypes.byref(v)),
+               "zset_server_count")
+        return int(v.value)
+
+    def submit(self, set_id: int, n: int) -> int:
+        t = ctypes.c_uint64()
+        _check(load().zset_server_submit(self._handle, set_id, n, ctypes.byref(t)),
+               "zset_server_submit")
+        return int(t.value)
+
+    def wait(self, ticket: int) -> dict:
+        r = ServerResult()
+        _check(load().zset_server_wait(self._handle, ticket, ctypes.byref(r)), "zset_server_wait")
+        return r.as_dict()
+
+    def rows_of(self, set_id: int, result: dict):
+        """The query's rows: an int32 view (rows, d) into the arena."""
+        d = self.d[set_id]
+        off, rows = int(result["out_offset"]), int(result["rows"])
+        return self.arena[off:off + rows * d].view(rows, d)
+
+    def release(self, ticket: int) -> None:
+        _check(load().zset_server_release(self._handle, ticket), "zset_server_release")
+
+    def stats(self) -> dict:
+        a, c, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().zset_server_stats(self._handle, ctypes.byref(a), ctypes.byref(c),
+                                        ctypes.byref(m)), "zset_server_stats")
+        return {"admitted": int(a.value), "completed": int(c.value),
+                "max_inflight": int(m.value)}
+
+    def free(self) -> None:
+        if self._handle is not None and self._handle.value:
+            load().zset_server_free(self._handle)
         self._handle = ctypes.c_void_p(None)
 
     def __del__(self):

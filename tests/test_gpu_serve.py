@@ -1,0 +1,110 @@
+"""The request loop (zset_server_*, through the C ABI): every query served in
+a mix of concurrent queries gives exactly the bytes zset_enumerate_ex writes
+for it alone, and the oracle's rows on a sample.  Integer work: bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_20474_amd import zset
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# (generators, n_max, requested k): memo dimensions auto, 0, 1, 2 and d = 1, 2.
+SETS = [([7, 11, 13, 17], 3000, -1), ([13, 34, 37, 54, 65, 83], 1500, -1),
+        ([5, 9], 5000, -1), ([11], 400, -1), ([6, 10, 15], 900, 0),
+        ([9, 4, 6, 7], 700, 1), ([3, 5, 7, 11, 13], 300, 2), ([12, 18, 30], 500, -1)]
+
+
+def alone(n, g, k):
+    r = zset.enumerate_ex(n, g, k=k)
+    if r.rows == 0:
+        return np.zeros((0, len(g)), np.uint32)
+    return r.out[: r.rows].cpu().numpy().view(np.uint32).reshape(r.rows, len(g))
+
+
+def test_served_mix_matches_each_query_alone():
+    rng = np.random.default_rng(77)
+    arena = torch.empty(6_000_000, dtype=torch.int32, device="cuda")  # 24 MB: admission waits
+    srv = zset.Server(arena, slots=8)
+    ids = []
+    for g, n_max, k in SETS:
+        sid = srv.add_set(g, n_max, k)
+        info = srv.set_info(sid)
+        say(f"set {sid}: g={g} n_max={n_max} k={info['k']} memo_rows={info['memo_rows']}")
+        if k >= 0:
+            assert info["k"] == k
+        ids.append(sid)
+    queries = []
+    for _ in range(400):
+        s = int(rng.integers(0, len(SETS)))
+        n = int(rng.integers(0, SETS[s][1] + 1))
+        queries.append((s, n))
+    queries += [(0, 0), (0, 3000), (3, 0), (3, 11), (3, 12), (4, 1), (2, 5000)]
+    say(f"submitting {len(queries)} queries at once")
+    tickets = [srv.submit(ids[s], n) for s, n in queries]
+    checked = 0
+    for (s, n), t in zip(queries, tickets):
+        res = srv.wait(t)
+        g, _, _ = SETS[s]
+        k = srv.set_info(ids[s])["k"]
+        assert res["rows"] == srv.count(ids[s], n) == oracle.count(n, g)
+        got = srv.rows_of(ids[s], res).cpu().numpy().view(np.uint32) if res["rows"] else \
+            np.zeros((0, len(g)), np.uint32)
+        want = alone(n, g, k)
+        assert got.shape == want.shape and np.array_equal(got, want), (s, n, k)
+        if checked < 60:
+            assert np.array_equal(got, oracle.enumerate_rows(n, g)), (s, n)
+            checked += 1
+        assert res["submit_us"] <= res["admit_us"] <= res["done_us"]
+        srv.release(t)
+    st = srv.stats()
+    say(f"stats {st}")
+    assert st["completed"] == len(queries)
+    assert st["max_inflight"] > 1  # queries overlapped on the device
+    srv.free()
+
+
+def test_server_errors():
+    arena = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
+    srv = zset.Server(arena, slots=2)
+    sid = srv.add_set([7, 11, 13, 17], 2000)
+    with pytest.raises(zset.ZsetError) as e:
+        srv.submit(sid, 2001)  # beyond n_max
+    assert e.value.status == zset.EINVAL
+    with pytest.raises(zset.ZsetError) as e:
+        srv.submit(sid + 1, 10)  # no such set
+    assert e.value.status == zset.EINVAL
+    with pytest.raises(zset.ZsetError) as e:
+        srv.submit(sid, 2000)  # 81205 rows x 4 words exceed the 65536-word arena
+    assert e.value.status == zset.ECAPACITY
+    with pytest.raises(zset.ZsetError) as e:
+        srv.wait(12345)
+    assert e.value.status == zset.EINVAL
+    t = srv.submit(sid, 500)
+    srv.wait(t)
+    srv.release(t)
+    with pytest.raises(zset.ZsetError) as e:
+        srv.release(t)
+    assert e.value.status == zset.EINVAL
+    with pytest.raises(zset.ZsetError) as e:
+        srv.add_set([3, 0], 10)
+    assert e.value.status == zset.EINVAL
+    # Queued queries that can never be admitted end with EINVAL when the server stops.
+    t1 = srv.submit(sid, 900)
+    srv.wait(t1)  # holds its rows: the next queries wait for room
+    pending = [srv.submit(sid, 1000) for _ in range(3)]
+    srv.release(t1)
+    for t in pending:
+        srv.wait(t)
+        srv.release(t)
+    srv.free()

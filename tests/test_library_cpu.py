@@ -138,3 +138,24 @@ def test_stored_workloads_match_the_oracle():
         assert g == inputs.draw_gens(item["seed"], len(g), 10, 200)
         assert oracle.count(n, g) == item["rows"]
         assert 1e8 <= item["rows"] <= 1e9
+
+
+def test_server_argument_checks():
+    lib = zset.load()
+    handle = ctypes.c_void_p()
+    assert lib.zset_server_create(None, ctypes.byref(handle)) == zset.EINVAL
+    o = zset.ServerOpts()
+    lib.zset_server_default_opts(ctypes.byref(o))
+    assert o.slots == 8 and not o.arena and o.arena_bytes == 0
+    assert lib.zset_server_create(ctypes.byref(o), ctypes.byref(handle)) == zset.EINVAL  # no arena
+    o.slots = 65
+    assert lib.zset_server_create(ctypes.byref(o), ctypes.byref(handle)) == zset.EINVAL
+    t = ctypes.c_uint64()
+    assert lib.zset_server_submit(None, 0, 10, ctypes.byref(t)) == zset.EINVAL
+    assert lib.zset_server_wait(None, 1, None) == zset.EINVAL
+    assert lib.zset_server_release(None, 1) == zset.EINVAL
+    g = np.array([3, 5], dtype=np.uint32)
+    sid = ctypes.c_int()
+    assert lib.zset_server_add_set(None, g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 2, 10,
+                                   -1, ctypes.byref(sid)) == zset.EINVAL
+    lib.zset_server_free(None)
