@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch", "memo"])
+    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch", "memo", "serve"])
     ap.add_argument("--sweep-d", type=int, default=5, choices=[5, 7, 9],
                     help="dimension of the memo-dimension sweep workload")
     ap.add_argument("--seed", type=int, default=0, help="large workload seed (0, 1 or 2)")
@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--count-only", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=float, default=2.5e8)
+    ap.add_argument("--serve-queries", type=int, default=10000,
+                    help="queries per arrival rate of the served workload")
+    ap.add_argument("--slots", type=int, default=8, help="server slots (served workload)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -309,6 +312,147 @@ def run_memo(args):
     print(json.dumps(line), flush=True)
 
 
+def run_serve(args):
+    """Served queries: 64 resident generator sets (drawn as the batched queries'
+    are, seed 5), a stream of queries (set uniform, |Z(n)| target log-uniform in
+    [1e1, 1e8], n the smallest element reaching it), Poisson arrivals at 0.5, 1
+    and 2 times the plain path's saturation rate, into a 64 GiB output arena.
+    The plain path is one zset_enumerate_ex call per query, one at a time: its
+    service times are measured on the same stream, and its latencies at each
+    rate follow from them (first come, first served, one query at a time)."""
+    import math
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2407_20474_amd import inputs, zset
+
+    nq = args.serve_queries
+    sets = inputs.draw_generator_sets(5, 64)
+    stream = inputs.draw_served_stream(5, nq, len(sets))
+    top = 10 ** 8
+    # n for each target: the smallest n whose |Z(n)| reaches it, from the
+    # running maximum of the count table's first row.
+    ns = [None] * nq
+    n_need = [0] * len(sets)
+    by_set = {}
+    for i, (s, t) in enumerate(stream):
+        by_set.setdefault(s, []).append((i, t))
+    t_setup = time.perf_counter()
+    for s, g in enumerate(sets):
+        d = len(g)
+        n_hi = int(1.3 * (top * math.factorial(d - 1) * math.prod(g)) ** (1.0 / (d - 1))) + max(g)
+        while True:
+            c0 = zset.count_table(n_hi, g)[0]
+            run = torch.cummax(c0, dim=0).values
+            if int(run[-1]) >= top:
+                break
+            n_hi = int(n_hi * 1.5)
+        targets = torch.tensor([t for _, t in by_set.get(s, [])], dtype=torch.int64, device="cuda")
+        if targets.numel():
+            idx = torch.searchsorted(run, targets).tolist()
+            for (i, _), n in zip(by_set[s], idx):
+                ns[i] = int(n)
+                n_need[s] = max(n_need[s], int(n))
+        del c0, run
+    arena = torch.empty((64 << 30) // 4, dtype=torch.int32, device="cuda")
+    srv = zset.Server(arena, slots=args.slots)
+    ks = []
+    for s, g in enumerate(sets):
+        srv.add_set(g, max(n_need[s], 1))
+        ks.append(srv.set_info(s)["k"])
+    queries = [(s, ns[i]) for i, (s, _) in enumerate(stream)]
+    rows = [srv.count(s, n) for s, n in queries]
+    total_rows = sum(rows)
+    setup_s = time.perf_counter() - t_setup
+    print(f"# serve: {len(sets)} sets resident in {setup_s:.1f} s, {nq} queries, "
+          f"{total_rows} rows", file=sys.stderr, flush=True)
+
+    # Plain path: service times, one query at a time.
+    service = np.zeros(nq)
+    for i, (s, n) in enumerate(queries):
+        t = time.perf_counter()
+        zset.enumerate_ex(n, sets[s], out=arena)
+        service[i] = time.perf_counter() - t
+        if (i + 1) % 2000 == 0:
+            print(f"# plain {i + 1}/{nq}", file=sys.stderr, flush=True)
+    mu_plain = nq / service.sum()
+    plain_rows_s = total_rows / service.sum()
+
+    def plain_latency(arrive):
+        end, lat = 0.0, np.zeros(nq)
+        for i in range(nq):
+            start = max(arrive[i], end)
+            end = start + service[i]
+            lat[i] = end - arrive[i]
+        return lat
+
+    results = {}
+    for mult in (0.5, 1.0, 2.0, None):
+        # None: every query arrives at time 0 (the server's saturation throughput).
+        lam = mult * mu_plain if mult else float("inf")
+        arrive = (inputs.poisson_arrivals(50 + int(mult * 10), nq, lam) if mult
+                  else np.zeros(nq))
+        tickets = [None] * nq
+        got = [None] * nq
+        ready = threading.Semaphore(0)
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i, (s, n) in enumerate(queries):
+                dt = arrive[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit(s, n)
+                ready.release()
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        for i in range(nq):
+            ready.acquire()
+            got[i] = srv.wait(tickets[i])
+            srv.release(tickets[i])
+            if (i + 1) % 2000 == 0:
+                print(f"# served x{mult or 'sat'} {i + 1}/{nq}", file=sys.stderr, flush=True)
+        th.join()
+        lat = np.array([r["done_us"] - r["submit_us"] for r in got])
+        span = (max(r["done_us"] for r in got) - min(r["submit_us"] for r in got)) * 1e-6
+        pl = plain_latency(arrive) * 1e6
+        key = f"x{mult}" if mult else "saturation"
+        results[key] = {
+            "rate_qps": round(lam, 1) if mult else None,
+            "p50_us": round(float(np.percentile(lat, 50)), 1),
+            "p99_us": round(float(np.percentile(lat, 99)), 1),
+            "rows_per_s": total_rows / span, "span_s": round(span, 3),
+            "plain_p50_us": round(float(np.percentile(pl, 50)), 1),
+            "plain_p99_us": round(float(np.percentile(pl, 99)), 1)}
+        print(f"# served {key}: {results[key]}", file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.free()
+    best = results["saturation"]
+    line = {
+        "metric": "served Z(n) factorizations/s (bit-exact) with p50/p99 latency",
+        "value": best["rows_per_s"],
+        "unit": "factorizations/s",
+        "n_gpus": 1, "steps": nq, "warmup": 0,
+        "ms_per_step": best["span_s"] * 1e3 / nq,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": (f"serve: {len(sets)} resident generator sets (d in 3..8, g in "
+                                f"[5, 150]), {nq} queries with |Z| log-uniform in [1e1, 1e8] "
+                                f"({total_rows} rows), Poisson arrivals at 0.5/1/2 x the plain "
+                                f"path's saturation rate and all at once (value: the last), "
+                                f"64 GiB output arena, {args.slots} slots"),
+                   "k_histogram": {int(k): ks.count(k) for k in sorted(set(ks))}},
+        "serve": {"plain_qps": mu_plain, "plain_rows_per_s": plain_rows_s,
+                  "speedup_vs_plain": best["rows_per_s"] / plain_rows_s,
+                  "rates": results, "max_inflight": st["max_inflight"],
+                  "setup_s": round(setup_s, 2)},
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -322,6 +466,9 @@ def main():
         return
     if args.workload == "memo":
         run_memo(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
 
     import torch

@@ -130,7 +130,7 @@ zset_status get_ctx(Ctx** out) {
 zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
                             bool count_only, bool align16) {
   const int pct = claim_pct < 0 ? kDefaultClaimPct : claim_pct;
-  const size_t lds_max = size_t(device_max_lds_bytes(device));
+  const size_t lds_max = size_t(write_lds_budget(device));
   P.max_tiles = kMinTileStates;
   P.chunk = pct > 0 ? uint32_t(write_waves_per_block()) : 0;
   if (P.chunk && write_lds_bytes(P) > lds_max) P.chunk = 0;
@@ -216,6 +216,8 @@ zset_status check_query(uint64_t n, const uint32_t* gens, int d) {
   return ZSET_OK;
 }
 
+
+int write_lds_budget(int device) { return device_max_lds_bytes(device) - 256; }
 
 int device_max_lds_bytes(int device) {
   int v = 0;
@@ -628,7 +630,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       P.nclass = uint32_t(std::min<uint64_t>(G, N));
       const char* lds_env = std::getenv("ZSET_MEMO_LDS");
       const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
-      const size_t lds_max = size_t(max_lds_bytes(c));
+      const size_t lds_max = size_t(write_lds_budget(c->device));
       if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
       if (P.pack != 0) {
         P.memo_words = Rn * uint64_t(P.pack);

@@ -198,7 +198,7 @@ zset_status launch_stages(zset_batch b, uint32_t* out, hipStream_t s, bool timed
 zset_status plan_queries(zset_batch b, const int* kreq, const uint64_t* treq, int cus) {
   const uint32_t max_steps = b->opts.max_chain_steps ? b->opts.max_chain_steps : kDefaultChainSteps;
   const uint32_t unit_tiles = b->opts.unit_tiles ? b->opts.unit_tiles : kDefaultUnitTiles;
-  const uint32_t lds_words = uint32_t(device_max_lds_bytes(b->device) / 4);
+  const uint32_t lds_words = uint32_t(write_lds_budget(b->device) / 4);
   const bool co = b->opts.count_only != 0;
 
   int dmax = 1;

@@ -155,7 +155,7 @@ zset_status launch_query(zset_server_s* S, Request& r, Slot& sl) {
     P.checksum = misc + 1;
     P.pool = reinterpret_cast<uint32_t*>(misc + 2);
     P.lds_cnt = 0;
-    const size_t lds_max = size_t(device_max_lds_bytes(S->device));
+    const size_t lds_max = size_t(write_lds_budget(S->device));
     if (R.k >= 1 && R.sum_u < (uint64_t(1) << 32) && R.memo_rows < (uint64_t(1) << 32)) {
       P.lds_cnt = 1;
       if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
@@ -376,11 +376,12 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
     (void)hipGetLastError();
     return bail(fail(ZSET_EDEVICE, "count table readback failed"));
   }
-  const size_t lds_max = size_t(device_max_lds_bytes(S->device));
+  const size_t lds_max = size_t(write_lds_budget(S->device));
 
   // Memo dimension: the requested one, else the largest k whose packed memo
-  // over p <= n_max fits in the write pass's LDS; else k = 0 (the last
-  // coordinate by division).
+  // over p <= n_max fits in the write pass's LDS; else the single-query
+  // rule (the largest k whose memo stays small beside the output, read from
+  // global memory).
   auto tmpl_for = [&](int kk, EnumParams& P) {
     std::memset(&P, 0, sizeof P);
     const int L = d - std::max(kk, 1);
@@ -410,13 +411,21 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
   if (d == 1) {
     kk = 0;
   } else if (kk < 0) {
-    kk = 0;
-    for (int c = d - 1; c >= 1; --c) {
+    for (int c = d - 1; c >= 1 && kk < 0; --c) {
       EnumParams P;
       tmpl_for(c, P);
-      if (P.pack != 0 && write_lds_bytes(P) <= lds_max) {
-        kk = c;
-        break;
+      if (P.pack != 0 && write_lds_bytes(P) <= lds_max) kk = c;
+    }
+    if (kk < 0) {
+      kk = 1;
+      const uint64_t total = R->c0[n_max];
+      for (int c = d - 1; c >= 1; --c) {
+        const uint64_t Rc = sums[d - c];
+        if (Rc != ~uint64_t(0) && Rc <= std::max<uint64_t>(uint64_t(1) << 16, total / 16) &&
+            Rc * (c + 1) * 4 <= (uint64_t(512) << 20)) {
+          kk = c;
+          break;
+        }
       }
     }
   }

@@ -35,6 +35,10 @@ zset_status check_query(uint64_t n, const uint32_t* gens, int d);
 bool is_device_pointer(const void* p);
 const char* device_error_text(int code);
 int device_max_lds_bytes(int device);
+// Dynamic LDS the write-pass kernels may request: the device's LDS per
+// workgroup less a reserve for their static shared variables (a request that
+// fills the device's LDS exactly would not leave room for them).
+int write_lds_budget(int device);
 
 struct EnumParams;
 // Write-pass sizing (slice length, claimed chunks, slice-state capacity, grid)

@@ -66,6 +66,42 @@ def draw_query_specs(seed: int, count: int, dlo: int = 3, dhi: int = 8, glo: int
     return specs
 
 
+def draw_generator_sets(seed: int, count: int, dlo: int = 3, dhi: int = 8, glo: int = 5,
+                        ghi: int = 150):
+    """Generator sets of the served workload, drawn as the batched queries' are:
+    d uniform in [dlo, dhi], distinct generators uniform in [glo, ghi] with gcd 1
+    (redrawn on the same stream), sorted ascending."""
+    rng = np.random.default_rng(seed)
+    pool = np.arange(glo, ghi + 1)
+    sets = []
+    for _ in range(count):
+        d = int(rng.integers(dlo, dhi + 1))
+        while True:
+            g = rng.choice(pool, size=d, replace=False)
+            if reduce(math.gcd, (int(x) for x in g)) == 1:
+                break
+        sets.append(sorted(int(x) for x in g))
+    return sets
+
+
+def draw_served_stream(seed: int, count: int, nsets: int, log_lo: float = 1.0,
+                       log_hi: float = 8.0):
+    """(set index, row target) pairs of a served query stream: the set uniform
+    over nsets, the target ceil(10^u) with u uniform in [log_lo, log_hi]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        s = int(rng.integers(0, nsets))
+        out.append((s, int(math.ceil(10.0 ** rng.uniform(log_lo, log_hi)))))
+    return out
+
+
+def poisson_arrivals(seed: int, count: int, rate: float):
+    """Arrival times (seconds from 0) of a Poisson stream of the given rate."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=count))
+
+
 def load_query_file(path: str):
     """Rows 'n rows g_1 ... g_d' of a stored query list -> [(n, gens, rows)]."""
     out = []

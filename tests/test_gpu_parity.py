@@ -180,6 +180,18 @@ def test_claimed_slices_every_share():
         assert c.rows == len(want) and c.checksum == want_sum, (k, rpt, pct)
 
 
+def test_write_pass_at_the_device_lds_limit():
+    """Queries whose write pass, as first sized, asked for exactly the device's
+    160 KiB of dynamic LDS (which the kernel's static shared variables do not
+    leave): the sizing keeps a reserve for them, and the rows match."""
+    for n, g, k in [(33722, [34, 65, 137], 2), (5937, [99, 101, 104, 141], 3),
+                    (1688, [51, 64, 70, 88, 89, 90, 116, 118], 5)]:
+        want = oracle.enumerate_rows(n, g)
+        for kk in (-1, k):
+            got, r = gpu_rows(n, g, k=kk)
+            assert_same(got, want, f"lds limit n={n} g={g} k={kk}")
+
+
 def test_descending_order_is_the_reversal():
     n, g = 2000, [7, 11, 13, 17]
     want = oracle.enumerate_rows(n, g)[::-1]
