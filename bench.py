@@ -122,57 +122,81 @@ def batch_cpu_baseline(queries, sample_rows):
 
 
 def run_batch(args):
-    """The batched workload: 4096 independent queries, one persistent write launch."""
+    """The batched workload (4096 independent queries) through the request
+    loop: at plan time every query's generator set is made resident up to its
+    own n (count table, memo, leaf layout); a step submits all 4096 queries at
+    once and waits for every one (slice plans and write passes on the server's
+    slots, outputs side by side in one arena).  The plain path is one
+    zset_enumerate_ex call per query, one at a time, every stage included."""
     import numpy as np
     import torch
 
     from paper_2407_20474_amd import inputs, zset
 
     allq = inputs.load_batch_queries()
-    queries = [(n, g) for n, g, _ in allq]
+    rows = sum(r for _, _, r in allq)
+    bytes_written = sum(r * len(g) * 4 for _, g, r in allq)
+    words = sum((r * len(g) + 3) // 4 * 4 for _, g, r in allq)
+    arena = torch.empty(words + 4, dtype=torch.int32, device="cuda")
+    srv = zset.Server(arena, slots=args.slots)
     t = time.perf_counter()
-    b = zset.Batch(queries)
+    ks = []
+    for i, (n, g, r) in enumerate(allq):
+        sid = srv.add_set(g, n)
+        assert srv.count(sid, n) == r, "count disagrees with the stored workload"
+        ks.append(srv.set_info(sid)["k"])
+        if (i + 1) % 1024 == 0:
+            print(f"# batch plan {i + 1}/{len(allq)}", file=sys.stderr, flush=True)
     create_s = time.perf_counter() - t
-    assert [int(x) for x in b.rows] == [r for _, _, r in allq], "counts disagree with the stored workload"
-    rows = int(b.rows.sum())
-    bytes_written = int(sum(int(b.rows[i]) * int(b.d[i]) * 4 for i in range(b.nq)))
-    out = b.alloc()
-    print(f"# batch planned in {create_s:.2f} s: {b.nq} queries, {rows} rows, "
+    print(f"# batch planned in {create_s:.2f} s: {len(allq)} queries, {rows} rows, "
           f"{bytes_written / 1e9:.1f} GB", file=sys.stderr, flush=True)
+
+    def step():
+        tickets = [srv.submit(i, n) for i, (n, _, _) in enumerate(allq)]
+        res = [srv.wait(tk) for tk in tickets]
+        return tickets, res
+
     for i in range(args.warmup):
-        b.run(out)
+        tickets, _ = step()
+        for tk in tickets:
+            srv.release(tk)
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    stats = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(b.run(out).stats)
+    for i in range(args.steps):
+        tickets, res = step()
+        if i < args.steps - 1:
+            for tk in tickets:
+                srv.release(tk)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
     value = rows / (dt / args.steps)
-    done_us = b.times()
-    lat = done_us[b.rows > 0]
-    # Stage breakdown (and the write kernel's time) from one eager run of the same plan.
-    e = zset.Batch(queries, use_graph=False)
-    es = e.run(out).stats
-    e.free()
-    print(f"# batched: {ms_per_step:.2f} ms/run; eager stages {es}", file=sys.stderr, flush=True)
-    # The plain path: one zset_enumerate_ex call per query, into the same buffer.
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    for q, (n, g) in enumerate(queries):
-        r = int(b.rows[q])
+    start = min(r["submit_us"] for r in res)
+    done = np.array([r["done_us"] - start for r in res])
+    # Bit-exact against the plain path on a sample of queries (bytes on the device).
+    rng = np.random.default_rng(4)
+    sample = sorted(set(rng.choice(len(allq), size=32, replace=False).tolist()
+                        + np.argsort([r for _, _, r in allq])[-4:].tolist()))
+    for q in sample:
+        n, g, r = allq[q]
         if r == 0:
             continue
-        zset.enumerate_ex(n, g, out=b.rows_of(out, q))
+        alone = zset.enumerate_ex(n, g)
+        assert torch.equal(srv.rows_of(q, res[q]), alone.out[:r]), q
+    for tk in tickets:
+        srv.release(tk)
+    # The plain path: one zset_enumerate_ex call per query, into the arena.
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for n, g, r in allq:
+        zset.enumerate_ex(n, g, out=arena)
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - tp
     plain_value = rows / plain_s
-    print(f"# plain path: {plain_s:.2f} s for {b.nq} calls", file=sys.stderr, flush=True)
-    write_us = es["write_us"]
-    achieved = bytes_written / (write_us * 1e-6) / 1e9
-    kcount = {int(k): int((b.k == k).sum()) for k in np.unique(b.k)}
+    print(f"# plain path: {plain_s:.2f} s for {len(allq)} calls", file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.free()
     line = {
         "metric": "Z(n) factorizations/s emitted (bit-exact)",
         "value": value,
@@ -187,30 +211,25 @@ def run_batch(args):
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": (f"batch: {b.nq} queries (d in 3..8, g in [5, 150], |Z| log-uniform in "
-                         f"[1e2, 1e7]), {rows} rows, {bytes_written / 1e9:.1f} GB, one graph "
-                         f"replay per step"),
-            "queries": b.nq, "rows": rows, "k_histogram": kcount,
+            "workload": (f"batch: {len(allq)} queries (d in 3..8, g in [5, 150], |Z| log-uniform "
+                         f"in [1e2, 1e7]), {rows} rows, {bytes_written / 1e9:.1f} GB; each step "
+                         f"submits every query to the request loop ({args.slots} slots) and "
+                         f"waits for all"),
+            "queries": len(allq), "rows": rows,
+            "k_histogram": {int(k): ks.count(k) for k in sorted(set(ks))},
         },
         "batch": {
             "plain_value": plain_value, "plain_s": plain_s, "speedup_vs_plain": value / plain_value,
-            "p50_done_us": float(np.percentile(lat, 50)), "p99_done_us": float(np.percentile(lat, 99)),
-            "create_s": create_s, "eager_stages_us": {k: round(es[k], 1) for k in
-                                                     ("count_us", "memo_us", "plan_us", "write_us",
-                                                      "total_us")},
-            "units": stats[-1]["units"], "write_blocks": stats[-1]["write_blocks"],
-            "lds_bytes": stats[-1]["lds_bytes"], "graph_run_us": round(stats[-1]["total_us"], 1),
+            "p50_done_us": float(np.percentile(done, 50)),
+            "p99_done_us": float(np.percentile(done, 99)),
+            "create_s": create_s, "max_inflight": st["max_inflight"],
+            "checked_against_plain": len(sample),
         },
         "step_hbm_write_frac": round(bytes_written / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                     "kernel": "k_write_batch (persistent batched write pass, eager run)",
-                     "algorithmic_bytes_per_launch": bytes_written},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = batch_cpu_baseline(allq, args.cpu_sample_rows / 2)
+        line["cpu_baseline"] = batch_cpu_baseline(allq, args.cpu_sample_rows / 10)
     print(json.dumps(line), flush=True)
-    b.free()
 
 
 # The paper's Table 1 groups: (d, memo dimension, largest element), generators

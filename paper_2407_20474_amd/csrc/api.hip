@@ -1,6 +1,7 @@
 // api.hip -- the C ABI of libzset.so (include/zset.h): argument checks,
 // per-device scratch memory, the order of launches, status codes and timings.
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -134,8 +135,12 @@ zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct
   P.max_tiles = kMinTileStates;
   P.chunk = pct > 0 ? uint32_t(write_waves_per_block()) : 0;
   if (P.chunk && write_lds_bytes(P) > lds_max) P.chunk = 0;
-  int cus = 0, per_cu = 0;
-  ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  static std::atomic<int> cus_of[64];  // compute units per device, asked for once
+  int cus = (device >= 0 && device < 64) ? cus_of[device].load() : 0, per_cu = 0;
+  if (cus == 0) {
+    ZSET_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    if (device >= 0 && device < 64) cus_of[device].store(cus);
+  }
   ZSET_HIP(write_occupancy(P, count_only, align16, &per_cu));
   if (per_cu < 1) return fail(ZSET_EDEVICE, "the write pass does not fit on a compute unit");
   const uint64_t wpb = uint64_t(write_waves_per_block());
@@ -220,12 +225,18 @@ zset_status check_query(uint64_t n, const uint32_t* gens, int d) {
 int write_lds_budget(int device) { return device_max_lds_bytes(device) - 256; }
 
 int device_max_lds_bytes(int device) {
+  static std::atomic<int> lds_of[64];  // asked for once per device
+  if (device >= 0 && device < 64) {
+    const int v = lds_of[device].load();
+    if (v != 0) return v;
+  }
   int v = 0;
   if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 64 * 1024;
   }
+  if (device >= 0 && device < 64) lds_of[device].store(v);
   return v;
 }
 

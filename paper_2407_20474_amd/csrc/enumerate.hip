@@ -38,6 +38,9 @@
 // load in the prologue is what lets the stores stream.
 // In count-only mode no row is stored: each row's FNV-1a-64 (rank, row) hash is
 // summed instead.
+#include <map>
+#include <mutex>
+
 #include "zset_internal.h"
 
 namespace zset {
@@ -907,12 +910,39 @@ __global__ __launch_bounds__(256) void k_reverse_rows(uint32_t* out, uint64_t ro
   }
 }
 
+// Per instantiation of the write kernel: the largest dynamic LDS its function
+// attribute has been raised to, and the occupancy found for each LDS size
+// (both fixed for a kernel and a size, and costly to ask for per call).
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
+struct WriteKernelCache {
+  static std::mutex mu;
+  static size_t attr_lds;
+  static std::map<size_t, int> occupancy;
+};
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
+std::mutex WriteKernelCache<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>::mu;
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
+size_t WriteKernelCache<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>::attr_lds = 0;
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
+std::map<size_t, int> WriteKernelCache<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>::occupancy;
+
+template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
+hipError_t raise_lds_attr(size_t lds) {
+  using C = WriteKernelCache<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
+  auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
+  std::lock_guard<std::mutex> lock(C::mu);
+  if (lds <= C::attr_lds) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  if (e == hipSuccess) C::attr_lds = lds;
+  return e;
+}
+
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 hipError_t launch_write_t(const EnumParams& P, hipStream_t s) {
   auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
   const size_t lds = write_lds_bytes(P);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  hipError_t e = raise_lds_attr<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(kern, dim3(P.write_blocks), dim3(kWriteWaves * kWave), lds, s, P);
   return hipGetLastError();
@@ -920,12 +950,24 @@ hipError_t launch_write_t(const EnumParams& P, hipStream_t s) {
 
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
 hipError_t occupancy_t(const EnumParams& P, int* per_cu) {
+  using C = WriteKernelCache<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
   auto kern = k_write<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>;
   const size_t lds = write_lds_bytes(P);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+  {
+    std::lock_guard<std::mutex> lock(C::mu);
+    auto it = C::occupancy.find(lds);
+    if (it != C::occupancy.end()) {
+      *per_cu = it->second;
+      return hipSuccess;
+    }
+  }
+  hipError_t e = raise_lds_attr<MODE, COUNT_ONLY, ALIGN16, PACK, LDSCNT, NO, KF>(lds);
   if (e != hipSuccess) return e;
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, kWriteWaves * kWave, lds);
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kern, kWriteWaves * kWave, lds);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(C::mu);
+  C::occupancy[lds] = *per_cu;
+  return hipSuccess;
 }
 
 // Outer-prefix length and k compiled in for the common materialising shapes
