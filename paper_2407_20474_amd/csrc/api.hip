@@ -63,7 +63,7 @@ struct Ctx {
   int device = -1;
   DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount;
   uint64_t* pinned = nullptr;  // host readback area
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[7] = {};
   // Side stream for a memo recurrence that runs beside the count table, with
   // its fork event and start / end events.
   hipStream_t side = nullptr;
@@ -75,8 +75,9 @@ std::map<int, Ctx*> g_ctx;
 // Slice start states each write workgroup keeps in LDS, at least.
 constexpr uint32_t kMinTileStates = 16;
 
-// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..34] row sums
-constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2, kMiscPool = kMiscRowSums + kMaxD + 1;
+// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..2+d] row
+// sums and [3+d] |Z(n)| (kMaxD + 2 words), then the write pass's chunk counter.
+constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2, kMiscPool = kMiscRowSums + kMaxD + 2;
 constexpr size_t kMiscWords = kMiscPool + 1;
 constexpr int kDefaultClaimPct = 100;  // percent of slices claimed at run time
 constexpr size_t kPinnedWords = 64;
@@ -513,6 +514,10 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   } side_join;
   bool early = false;
   uint64_t early_cap = 0;
+  // The recurrence is enqueued first: it is the longer of the two and the
+  // rest of the call waits for it.  The fork event orders it after the status
+  // reset.
+  ZSET_HIP(hipEventRecord(c->fork, s));
   {
     const char* path = std::getenv("ZSET_MEMO_PATH");
     const bool force_global = path && std::strcmp(path, "global") == 0;
@@ -533,7 +538,6 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
           if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
           if ((st = ensure(c->nat, size_t(early_cap) * kk * sizeof(uint32_t))) != ZSET_OK)
             return st;
-          ZSET_HIP(hipEventRecord(c->fork, s));
           ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
           side_join.c = c;
           ZSET_HIP(hipEventRecord(c->memo0, c->side));
@@ -546,11 +550,11 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
       }
     }
   }
+  // Count table, then one readback of the row sums and |Z(n)|.
   ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
   ZSET_HIP(hipEventRecord(c->ev[1], s));
-  ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 1) * sizeof(uint64_t),
+  ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 2) * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
-  ZSET_HIP(hipMemcpyAsync(c->pinned + (d + 1), T + n, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   ZSET_HIP(hipStreamSynchronize(s));
   uint64_t sums[kMaxD + 1];
   for (int j = 0; j <= d; ++j) sums[j] = c->pinned[j];
@@ -586,6 +590,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if (total > 0 && d == 1) {
     ZSET_HIP(hipEventRecord(c->ev[2], s));
     ZSET_HIP(hipEventRecord(c->ev[3], s));
+    ZSET_HIP(hipEventRecord(c->ev[6], s));
     ZSET_HIP(launch_single(n, gens[0], out, count_only, misc + kMiscSum, s));
     ZSET_HIP(hipEventRecord(c->ev[4], s));
   } else if (total > 0) {
@@ -610,11 +615,65 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     P.flush = P.ring / 2;
     P.max_tiles = kMinTileStates;  // grown by size_write_pass to what LDS leaves
 
-    // 3. Memo (k >= 1): natural-order rows, then the leaf-order layout.
+    // 3. Leaf-order row format and what the write pass keeps in LDS (from the
+    // row sums alone), slices, class ends and the slice plan.  None of these
+    // needs the memo's rows, so while the recurrence runs on the side stream
+    // they run beside it.
+    const uint64_t Rn = k >= 1 ? sums[L] : 0;  // rows of Memo[p] over p <= n
+    uint64_t leaf_words = 0;
+    if (k >= 1) {
+      memo_rows = Rn;
+      leaf_format(P, n, gens, U, k);
+      P.nclass = uint32_t(std::min<uint64_t>(G, N));
+      const char* lds_env = std::getenv("ZSET_MEMO_LDS");
+      const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
+      const size_t lds_max = size_t(write_lds_budget(c->device));
+      if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
+      if (P.pack != 0) {
+        P.memo_words = Rn * uint64_t(P.pack);
+        if (write_lds_bytes(P) > lds_max) P.pack = 0;
+      }
+      if (P.pack == 0) P.memo_words = 0;
+      // Segment counts and class ends in LDS too when every value fits 32 bits
+      // (their sum over x <= n bounds each) and the space is there.
+      if (!lds_off && sums[U] < (uint64_t(1) << 32) && Rn < (uint64_t(1) << 32)) {
+        P.lds_cnt = 1;
+        if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
+      }
+      leaf_words = P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
+      const uint64_t nclass_max = std::min<uint64_t>(G, N);
+      if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
+      if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
+      P.endc = reinterpret_cast<uint64_t*>(c->endc.p);
+      P.leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
+      P.leaf_rows = Rn;
+      memo_bytes = leaf_words * 4;
+    }
+    // Slices: exact rank ranges, starts unranked on the device; about 128
+    // slices per resident wavefront by default (short slices keep the
+    // concurrent write streams of a compute unit close together in memory and
+    // the end of the pass even).
+    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
+    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, c->device, count_only, align16)) !=
+        ZSET_OK)
+      return st;
+    T_rows = P.rows_per_tile;
+    ntiles = P.ntiles;
+    if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
+    P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
     ZSET_HIP(hipEventRecord(c->ev[2], s));
     if (k >= 1) {
-      const uint64_t Rn = sums[L];  // rows of Memo[p] over p <= n
-      memo_rows = Rn;
+      uint32_t nclass = 0;
+      ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc),
+                                 &nclass, s));
+    }
+    ZSET_HIP(launch_plan(P, s));
+    ZSET_HIP(hipEventRecord(c->ev[3], s));
+
+    // 4. Memo rows (k >= 1) -- a memo handle's, the side-stream recurrence's,
+    // or built here -- then the leaf-order layout.
+    if (k >= 1) {
       const uint64_t* off = nullptr;
       const uint32_t* nat = nullptr;
       if (memo) {
@@ -636,55 +695,13 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         off = o;
         nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       }
-      // Leaf-order row format, copied to LDS by the write pass when it fits.
-      leaf_format(P, n, gens, U, k);
-      P.nclass = uint32_t(std::min<uint64_t>(G, N));
-      const char* lds_env = std::getenv("ZSET_MEMO_LDS");
-      const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
-      const size_t lds_max = size_t(write_lds_budget(c->device));
-      if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
-      if (P.pack != 0) {
-        P.memo_words = Rn * uint64_t(P.pack);
-        if (write_lds_bytes(P) > lds_max) P.pack = 0;
-      }
-      if (P.pack == 0) P.memo_words = 0;
-      // Segment counts and class ends in LDS too when every value fits 32 bits
-      // (their sum over x <= n bounds each) and the space is there.
-      if (!lds_off && sums[U] < (uint64_t(1) << 32) && Rn < (uint64_t(1) << 32)) {
-        P.lds_cnt = 1;
-        if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
-      }
-      const uint64_t leaf_words = P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
-      const uint64_t nclass_max = std::min<uint64_t>(G, N);
-      if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
-      if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
-      uint32_t nclass = 0;
-      uint64_t* endc = reinterpret_cast<uint64_t*>(c->endc.p);
-      ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, endc, &nclass, s));
-      uint32_t* leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
-      ZSET_HIP(launch_memo_leaf(
-          make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, endc, leaf, Rn, P), err, s));
-      P.endc = endc;
-      P.leaf = leaf;
-      P.leaf_rows = Rn;
-      memo_bytes = leaf_words * 4;
+      ZSET_HIP(hipEventRecord(c->ev[6], s));
+      ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                              const_cast<uint32_t*>(P.leaf), Rn, P),
+                                err, s));
+    } else {
+      ZSET_HIP(hipEventRecord(c->ev[6], s));
     }
-    ZSET_HIP(hipEventRecord(c->ev[3], s));
-
-    // 4. Slices: exact rank ranges, starts unranked on the device; about 128
-    // slices per resident wavefront by default (short slices keep the
-    // concurrent write streams of a compute unit close together in memory and
-    // the end of the pass even).
-    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-    P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
-    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, c->device, count_only, align16)) !=
-        ZSET_OK)
-      return st;
-    T_rows = P.rows_per_tile;
-    ntiles = P.ntiles;
-    if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
-    P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
-    ZSET_HIP(launch_plan(P, s));
     ZSET_HIP(hipEventRecord(c->ev[4], s));
 
     // 5. Write (or count-only) pass.
@@ -692,6 +709,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   } else {
     ZSET_HIP(hipEventRecord(c->ev[2], s));
     ZSET_HIP(hipEventRecord(c->ev[3], s));
+    ZSET_HIP(hipEventRecord(c->ev[6], s));
     ZSET_HIP(hipEventRecord(c->ev[4], s));
   }
   ZSET_HIP(hipEventRecord(c->ev[5], s));
@@ -706,10 +724,16 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if (stats) {
     std::memset(stats, 0, sizeof *stats);
     stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
-    memo_us = elapsed_us(c->ev[2], c->ev[3]);
-    plan_us = elapsed_us(c->ev[3], c->ev[4]);
+    // plan: class ends + slice plan; memo: the recurrence (on the side stream
+    // when it ran there, else on the call's stream up to ev[6]) and the leaf
+    // layout; write: the write pass.
+    plan_us = elapsed_us(c->ev[2], c->ev[3]);
+    memo_us = elapsed_us(c->ev[6], c->ev[4]);
+    if (early && k >= 1 && total > 0 && d > 1 && memo_rows <= early_cap)
+      memo_us += elapsed_us(c->memo0, c->memo1);
+    else
+      memo_us += elapsed_us(c->ev[3], c->ev[6]);
     write_us = elapsed_us(c->ev[4], c->ev[5]);
-    if (early && k >= 1 && total > 0 && d > 1) memo_us += elapsed_us(c->memo0, c->memo1);
     stats->memo_us = memo ? 0.0 : memo_us;
     stats->plan_us = plan_us;
     stats->write_us = write_us;

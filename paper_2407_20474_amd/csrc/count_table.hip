@@ -221,6 +221,8 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table(uint64_t* __restrict
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
   count_table_global(T, N, g, d, sums);
+  __syncthreads();
+  if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
 }
 
 __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
@@ -231,6 +233,8 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
   count_table_lds(T, N, g, d, sums, buf);
+  __syncthreads();
+  if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
 }
 
 // Batched forms: workgroup b computes the table of jobs[first + b], and

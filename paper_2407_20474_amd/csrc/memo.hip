@@ -33,6 +33,9 @@
 // memo row carries floor(p / G) so that a = floor(x / G) - floor(p / G).
 #include <cstring>
 
+#include <map>
+#include <mutex>
+
 #include "zset_internal.h"
 
 namespace zset {
@@ -337,10 +340,21 @@ hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32
   Gens hg{};
   for (int i = 0; i < k; ++i) hg.g[i] = h[i];
   const size_t lds = memo_wave_lds_bytes(k, Rcap, W);
+  // The LDS attribute of each instantiation is raised once to the largest size
+  // asked for so far (setting it costs as much as a launch).
+  static std::mutex attr_mu;
+  static std::map<const void*, size_t> attr_lds;
   auto go = [&](auto kern) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
+    const void* f = reinterpret_cast<const void*>(kern);
+    {
+      std::lock_guard<std::mutex> lock(attr_mu);
+      size_t& have = attr_lds[f];
+      if (lds > have) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        have = lds;
+      }
+    }
     hipLaunchKernelGGL(kern, dim3(1), dim3(kWave), lds, s, hg, k, uint32_t(top), step, W,
                        uint32_t(Rcap), uint32_t(Rexp), nat, off_out, err);
     return hipGetLastError();

@@ -103,7 +103,8 @@ struct BatchLds {
 };
 
 // count_table.hip
-// Count table (d+1) x (n+1); when sums is non-NULL also sums[j] = sum_x C[j][x].
+// Count table (d+1) x (n+1); when sums is non-NULL (d+2 entries) also
+// sums[j] = sum_x C[j][x] for j = 0..d and sums[d+1] = C[0][n] = |Z(n)|.
 hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens, int d,
                               uint64_t* sums, hipStream_t s);
 uint32_t count_table_lds_max();
