@@ -472,6 +472,65 @@ def run_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def run_sweep(args):
+    """The memo-dimension sweep: d = 5, 7, 9 (the stored workloads, |Z| ~ 3.16e8
+    each) and k = 0..3, each materialised and in count-only mode: memo build
+    time, memo bytes, rows/s of the whole call (median of the timed calls) and
+    of the write pass, and the count-only checksum."""
+    import numpy as np
+    import torch
+
+    from paper_2407_20474_amd import inputs, zset
+
+    table = []
+    for item in inputs.load_workloads()["sweep"]:
+        n, g, rows = item["n"], item["gens"], item["rows"]
+        d = len(g)
+        out = torch.empty((rows, d), dtype=torch.int32, device="cuda")
+        for k in item["ks"]:
+            rec = {"d": d, "k": k, "n": n, "rows": rows}
+            for co in (False, True):
+                stats, wall = [], []
+                for i in range(args.warmup + args.steps):
+                    torch.cuda.synchronize()
+                    t = time.perf_counter()
+                    r = zset.enumerate_ex(n, g, out=None if co else out, k=k, count_only=co)
+                    dt = time.perf_counter() - t
+                    if i >= args.warmup:
+                        stats.append(r.stats)
+                        wall.append(dt)
+                med = float(np.median(wall))
+                wus = float(np.median([x["write_us"] for x in stats]))
+                key = "count_only" if co else "materialise"
+                rec[key] = {"rows_per_s": rows / med, "ms": round(med * 1e3, 3),
+                            "write_us": round(wus, 1),
+                            "memo_us": round(float(np.median([x["memo_us"] for x in stats])), 1),
+                            "count_us": round(float(np.median([x["count_us"] for x in stats])), 1)}
+                if co:
+                    rec[key]["checksum"] = f"{r.checksum:016x}"
+                else:
+                    rec[key]["write_gbs"] = round(rows * d * 4 / (wus * 1e-6) / 1e9, 1)
+                    rec["memo_rows"] = stats[-1]["memo_rows"]
+                    rec["memo_bytes"] = stats[-1]["memo_bytes"]
+                    rec["rows_per_tile"] = stats[-1]["rows_per_tile"]
+            print(f"# sweep d={d} k={k}: {rec}", file=sys.stderr, flush=True)
+            table.append(rec)
+        del out
+        torch.cuda.empty_cache()
+    best = max(table, key=lambda r: r["materialise"]["rows_per_s"])
+    line = {
+        "metric": "Z(n) factorizations/s emitted (bit-exact), memo-dimension sweep",
+        "value": best["materialise"]["rows_per_s"], "unit": "factorizations/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": best["materialise"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "sweep: d = 5, 7, 9 (generators in [10, 200], |Z| ~ 3.16e8 each), "
+                               "k = 0..3, materialised and count-only (value: the best)"},
+        "sweep": table,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -488,6 +547,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "sweep" and args.k is None:
+        run_sweep(args)
         return
 
     import torch

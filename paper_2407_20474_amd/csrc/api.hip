@@ -75,12 +75,14 @@ std::map<int, Ctx*> g_ctx;
 // Slice start states each write workgroup keeps in LDS, at least.
 constexpr uint32_t kMinTileStates = 16;
 
-// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..2+d] row
-// sums and [3+d] |Z(n)| (kMaxD + 2 words), then the write pass's chunk counter.
-constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2, kMiscPool = kMiscRowSums + kMaxD + 2;
+// misc layout (uint64 words): [0] status word (int), [1] checksum, [2..] the
+// count table's row sums, |Z(n)| and row maxima (2 kMaxD + 3 words), then the
+// write pass's chunk counter.
+constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2,
+              kMiscPool = kMiscRowSums + 2 * kMaxD + 3;
 constexpr size_t kMiscWords = kMiscPool + 1;
 constexpr int kDefaultClaimPct = 100;  // percent of slices claimed at run time
-constexpr size_t kPinnedWords = 64;
+constexpr size_t kPinnedWords = 128;
 
 zset_status get_ctx(Ctx** out) {
   int dev = 0;
@@ -272,12 +274,15 @@ int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
 
 // Builds Memo[p] = Z(p; h) for p < top into nat (natural order) and the
 // natural offsets off[0..top].  `ge` holds |Z(m; h_i..h_k)| for i = 0..k-1
-// (row stride ge_stride) and `sizes` = ge row 0; R = the total row count.
-// Memos that fit in LDS are built by one wavefront (k_memo_chain_wave), which
-// also writes the offsets; larger ones by the global schedule after a scan.
+// (row stride ge_stride) and `sizes` = ge row 0; R = the total row count and
+// rowmax the longest list.  Memos that fit in LDS are built by one wavefront
+// (k_memo_chain_wave), which also writes the offsets; larger ones by one
+// wavefront with a ring of the last lists in LDS (k_memo_chain_window) when
+// that ring fits, else by the global schedule after a scan.
+// ZSET_MEMO_PATH=global / window forces those paths (tests).
 zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
-                            const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint32_t* nat,
-                            hipStream_t s) {
+                            const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint64_t rowmax,
+                            uint32_t* nat, hipStream_t s) {
   if (k == 1) {
     if (R != (top - 1) / h[0] + 1) return fail(ZSET_EDEVICE, "memo row count disagrees (k = 1)");
     ZSET_HIP(launch_memo_k1(h[0], top, R, nat, off, s));
@@ -290,14 +295,26 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint
   }
   const char* path = std::getenv("ZSET_MEMO_PATH");
   const bool force_global = path && std::strcmp(path, "global") == 0;
+  const bool force_window = path && std::strcmp(path, "window") == 0;
   const uint32_t step = std::min<uint32_t>(b, kWave);
   const uint64_t Wl = uint64_t(hmax) + step;
   const uint32_t W = Wl < (uint64_t(1) << 30) ? next_pow2(uint32_t(Wl)) : 0;
   int* err = reinterpret_cast<int*>(c->misc.p);
-  if (!force_global && W != 0 && R < (uint64_t(1) << 30) &&
-      memo_wave_lds_bytes(k, R, W) <= size_t(max_lds_bytes(c))) {
+  const size_t lds = size_t(max_lds_bytes(c));
+  if (!force_global && !force_window && W != 0 && R < (uint64_t(1) << 30) &&
+      memo_wave_lds_bytes(k, R, W) <= lds) {
     ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, R, nat, off, err, s));
     return ZSET_OK;
+  }
+  if (!force_global && W != 0 && R < (uint64_t(1) << 32) && rowmax < (uint64_t(1) << 24)) {
+    const uint64_t need = (uint64_t(hmax) + step) * std::max<uint64_t>(rowmax, 1);
+    if (need < (uint64_t(1) << 30)) {
+      const uint32_t cap = next_pow2(uint32_t(need));
+      if (memo_wave_lds_bytes(k, cap, W) <= lds) {
+        ZSET_HIP(launch_memo_chain_window(h, k, top, step, W, hmax, cap, R, nat, off, err, s));
+        return ZSET_OK;
+      }
+    }
   }
   ZSET_HIP(launch_exclusive_scan(ge, top, off, s));
   zset_status st = ensure(c->srcw, size_t(R) * sizeof(uint64_t));
@@ -386,7 +403,8 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   const uint64_t nm = top - 1;
   if ((st = ensure(c->hcount, size_t(k + 1) * top * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* CT = reinterpret_cast<uint64_t*>(c->hcount.p);
-  ZSET_HIP(launch_count_table(CT, nm, gens_trailing, k, nullptr, s));
+  uint64_t* msums = reinterpret_cast<uint64_t*>(c->misc.p) + kMiscRowSums;
+  ZSET_HIP(launch_count_table(CT, nm, gens_trailing, k, msums, s));
   zset_memo m = new zset_memo_s();
   std::memset(m, 0, sizeof *m);
   m->k = k;
@@ -408,9 +426,12 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   hipError_t e = launch_exclusive_scan(CT, top, m->off, s);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->pinned, m->off + top, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)  // the longest list: the count table's row-0 maximum
+    e = hipMemcpyAsync(c->pinned + 1, msums + k + 2, sizeof(uint64_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return cleanup(hip_fail(e, "memo offsets"));
   const uint64_t R = c->pinned[0];
+  const uint64_t rowmax = c->pinned[1];
   if (R == ~uint64_t(0)) return cleanup(fail(ZSET_EOVERFLOW, "memo rows overflow 64 bits"));
   m->rows = R;
   if (hipMalloc(&m->nat, std::max<size_t>(16, size_t(R) * k * sizeof(uint32_t))) != hipSuccess) {
@@ -421,7 +442,7 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   int* err = reinterpret_cast<int*>(c->misc.p);
   e = hipMemsetAsync(err, 0, sizeof(int), s);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync"));
-  st = build_memo_rows(c, m->h, k, top, m->off, CT, top, R, m->nat, s);
+  st = build_memo_rows(c, m->h, k, top, m->off, CT, top, R, rowmax, m->nat, s);
   if (st != ZSET_OK) return cleanup(st);
   e = hipMemcpyAsync(c->pinned, err, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -553,11 +574,14 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   // Count table, then one readback of the row sums and |Z(n)|.
   ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
   ZSET_HIP(hipEventRecord(c->ev[1], s));
-  ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (d + 2) * sizeof(uint64_t),
+  ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (2 * d + 3) * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
   ZSET_HIP(hipStreamSynchronize(s));
-  uint64_t sums[kMaxD + 1];
-  for (int j = 0; j <= d; ++j) sums[j] = c->pinned[j];
+  uint64_t sums[kMaxD + 1], rowmax[kMaxD + 1];
+  for (int j = 0; j <= d; ++j) {
+    sums[j] = c->pinned[j];
+    rowmax[j] = c->pinned[d + 2 + j];
+  }
   const uint64_t total = c->pinned[d + 1];
   if (total == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
   if (total > (~uint64_t(0)) / (4 * uint64_t(d)))
@@ -689,7 +713,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
         if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
         uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
-        st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn,
+        st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
                              reinterpret_cast<uint32_t*>(c->nat.p), s);
         if (st != ZSET_OK) return st;
         off = o;

@@ -24,6 +24,22 @@ namespace {
 constexpr int kCtThreads = 1024;
 constexpr int kCtPart = 2048;  // chunk partial sums held in LDS
 
+__device__ inline uint64_t block_max_u64(uint64_t v, uint64_t* red) {
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    const uint64_t y = __shfl_xor(v, off, kWave);
+    v = y > v ? y : v;
+  }
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x & (kWave - 1);
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  uint64_t t = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kCtThreads / kWave; ++w) t = red[w] > t ? red[w] : t;
+  __syncthreads();
+  return t;
+}
+
 __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
 #pragma unroll
   for (int off = kWave / 2; off >= 1; off >>= 1) v = sat_add_u64(v, __shfl_xor(v, off, kWave));
@@ -41,25 +57,28 @@ __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
 // sums sums[j] = sum_x C[j][x] (saturating) when sums is non-NULL.  `gs` is
 // a copy of the generators in LDS.
 __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs,
-                                   int d, uint64_t* __restrict__ sums) {
+                                   int d, uint64_t* __restrict__ sums,
+                                   uint64_t* __restrict__ maxes) {
   __shared__ uint64_t part[kCtPart];
   __shared__ uint64_t red[kCtThreads / kWave];
   const int tid = threadIdx.x;
   uint64_t* last = T + size_t(d) * N;
   for (uint64_t x = tid; x < N; x += kCtThreads) last[x] = (x == 0) ? 1 : 0;
   if (tid == 0 && sums) sums[d] = 1;
+  if (tid == 0 && maxes) maxes[d] = 1;
   __syncthreads();
 
   for (int j = d - 1; j >= 0; --j) {
     const uint64_t* __restrict__ U = T + size_t(j + 1) * N;
     uint64_t* __restrict__ V = T + size_t(j) * N;
     const uint32_t G = gs[j];
-    uint64_t acc = 0;
+    uint64_t acc = 0, mx = 0;
     if (G >= N) {  // no x - g_j >= 0: the row is a copy
       for (uint64_t x = tid; x < N; x += kCtThreads) {
         const uint64_t v = U[x];
         V[x] = v;
         acc = sat_add_u64(acc, v);
+        mx = v > mx ? v : mx;
       }
     } else {
       const uint32_t rows = uint32_t((uint64_t(N) + G - 1) / G);
@@ -105,6 +124,7 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
               run = sat_add_u64(run, U[x]);
               V[x] = run;
               acc = sat_add_u64(acc, run);
+              mx = run > mx ? run : mx;
             }
           }
         }
@@ -113,6 +133,8 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
     }
     const uint64_t total = block_sum_u64(acc, red);
     if (tid == 0 && sums) sums[j] = total;
+    const uint64_t top = block_max_u64(mx, red);
+    if (tid == 0 && maxes) maxes[j] = top;
     __syncthreads();
   }
 }
@@ -123,7 +145,8 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
 constexpr uint32_t kCtLdsMax = 16384;
 
 __device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs, int d,
-                                uint64_t* __restrict__ sums, uint64_t* buf) {
+                                uint64_t* __restrict__ sums, uint64_t* __restrict__ maxes,
+                                uint64_t* buf) {
   __shared__ uint64_t part[kCtPart];
   __shared__ uint64_t red[kCtThreads / kWave];
   const int tid = threadIdx.x;
@@ -132,6 +155,7 @@ __device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint
     T[size_t(d) * N + x] = (x == 0) ? 1 : 0;
   }
   if (tid == 0 && sums) sums[d] = 1;
+  if (tid == 0 && maxes) maxes[d] = 1;
   __syncthreads();
 
   for (int j = d - 1; j >= 0; --j) {
@@ -203,14 +227,17 @@ __device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint
         __syncthreads();
       }
     }
-    uint64_t acc = 0;
+    uint64_t acc = 0, mx = 0;
     for (uint32_t x = tid; x < N; x += kCtThreads) {
       const uint64_t v = buf[x];
       T[size_t(j) * N + x] = v;
       acc = sat_add_u64(acc, v);
+      mx = v > mx ? v : mx;
     }
     const uint64_t total = block_sum_u64(acc, red);
     if (tid == 0 && sums) sums[j] = total;
+    const uint64_t top = block_max_u64(mx, red);
+    if (tid == 0 && maxes) maxes[j] = top;
   }
 }
 
@@ -220,7 +247,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table(uint64_t* __restrict
   __shared__ uint32_t g[kMaxD];
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
-  count_table_global(T, N, g, d, sums);
+  count_table_global(T, N, g, d, sums, sums ? sums + d + 2 : nullptr);
   __syncthreads();
   if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
 }
@@ -232,7 +259,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   __shared__ uint32_t g[kMaxD];
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
-  count_table_lds(T, N, g, d, sums, buf);
+  count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf);
   __syncthreads();
   if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
 }
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_batch_lds(
   uint32_t N;
   int d;
   load_job(jobs, g, &T, &N, &d, &sums, &total);
-  count_table_lds(T, N, g, d, sums, dyn_buf);
+  count_table_lds(T, N, g, d, sums, nullptr, dyn_buf);
   __syncthreads();
   if (threadIdx.x == 0) *total = T[N - 1];
 }
@@ -271,7 +298,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_batch_global(
   uint32_t N;
   int d;
   load_job(jobs, g, &T, &N, &d, &sums, &total);
-  count_table_global(T, N, g, d, sums);
+  count_table_global(T, N, g, d, sums, nullptr);
   __syncthreads();
   if (threadIdx.x == 0) *total = T[N - 1];
 }

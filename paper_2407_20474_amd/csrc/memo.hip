@@ -176,6 +176,125 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32
   memo_chain_wave<KMAX>(hg, k, top, step, W, Rcap, Rexp, nat, off_out, err, lds);
 }
 
+// The same recurrence for memos larger than LDS: the sources of a batch are
+// lists of the last max(h) elements only, so LDS keeps a ring of Mmask + 1
+// rows (a power of two) holding those lists, and every row is also stored to
+// `nat` as it is made.  Before each batch the rows still needed (those of the
+// elements x0 - max(h) and later) plus the batch's own must fit the ring; the
+// caller sizes it from the largest list (max(h) + step lists at most), and a
+// batch that would not fit stops the build with an error.
+template <int KMAX>
+__device__ inline void memo_chain_window(const uint32_t (&hg)[KMAX], int k, uint32_t top,
+                                         uint32_t step, uint32_t W, uint32_t hmax,
+                                         uint32_t Mmask, uint32_t Rexp,
+                                         uint32_t* __restrict__ nat,
+                                         uint64_t* __restrict__ off_out, int* __restrict__ err,
+                                         uint32_t* lds) {
+  uint32_t* GE = lds;
+  uint32_t* OFF = GE + size_t(W) * k;
+  uint32_t* M = lds + memo_ring_words(k, W);
+  const uint32_t lane = threadIdx.x;
+  const uint32_t Wm = W - 1;
+
+  if (lane < uint32_t(k)) {
+    M[lane] = 0;
+    GE[lane] = 1;
+    nat[lane] = 0;
+  }
+  if (lane == 0) {
+    OFF[0] = 0;
+    off_out[0] = 0;
+  }
+  uint32_t running = 1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+  for (uint32_t x0 = 1; x0 < top; x0 += step) {
+    const uint32_t p = x0 + lane;
+    const bool valid = lane < step && p < top;
+    uint32_t s[KMAX], so[KMAX];
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) {
+      s[i] = 0;
+      so[i] = 0;
+      if (i < k && valid && p >= hg[i]) {
+        const uint32_t slot = (p - hg[i]) & Wm;
+        s[i] = GE[slot * k + i];
+        so[i] = OFF[slot];
+      }
+    }
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; --i) {
+      if (i < k) {
+        acc += s[i];
+        if (valid) GE[(p & Wm) * k + i] = acc;
+      }
+    }
+    const uint32_t size = valid ? acc : 0;
+    const uint32_t incl = wave_incl_sum_u32(size);
+    const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
+    const uint32_t oldest = x0 > hmax ? OFF[(x0 - hmax) & Wm] : 0;
+    if (uint64_t(running) + tot - oldest > uint64_t(Mmask) + 1) {
+      if (lane == 0) {
+        off_out[top] = ~uint64_t(0);
+        set_error(err, kErrMemoTotal);
+      }
+      return;
+    }
+    const uint32_t off_p = running + incl - size;
+    if (valid) {
+      OFF[p & Wm] = off_p;
+      off_out[p] = off_p;
+    }
+    uint32_t dst = off_p;
+#pragma unroll
+    for (int i = KMAX - 1; i >= 0; --i) {
+      if (i < k) {
+        for (uint32_t r = 0; r < s[i]; ++r) {
+          uint32_t v[KMAX];
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c)
+            if (c < k) v[c] = M[((so[i] + r) & Mmask) * k + c];
+#pragma unroll
+          for (int c = 0; c < KMAX; ++c) {
+            if (c < k) {
+              const uint32_t w = v[c] + (c == i ? 1u : 0u);
+              M[((dst + r) & Mmask) * k + c] = w;
+              nat[uint64_t(dst + r) * k + c] = w;
+            }
+          }
+        }
+        dst += s[i];
+      }
+    }
+    running += tot;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  if (lane == 0) {
+    off_out[top] = running;
+    if (Rexp != 0 && running != Rexp) set_error(err, kErrMemoTotal);
+  }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(kWave) void k_memo_chain_window(Gens h, int k, uint32_t top,
+                                                              uint32_t step, uint32_t W,
+                                                              uint32_t hmax, uint32_t Mmask,
+                                                              uint32_t Rexp,
+                                                              uint32_t* __restrict__ nat,
+                                                              uint64_t* __restrict__ off_out,
+                                                              int* __restrict__ err) {
+  extern __shared__ __align__(16) uint32_t lds[];
+  uint32_t hg[KMAX];
+#pragma unroll
+  for (int i = 0; i < KMAX; ++i) hg[i] = h.g[i];
+  memo_chain_window<KMAX>(hg, k, top, step, W, hmax, Mmask, Rexp, nat, off_out, err, lds);
+}
+
 // Batched: workgroup b (one wavefront) builds the memo of jobs[b].
 template <int KMAX>
 __global__ __launch_bounds__(kWave) void k_memo_chain_batch(const MemoJob* __restrict__ jobs,
@@ -363,6 +482,35 @@ hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32
   if (k <= 4) return go(k_memo_chain_wave<4>);
   if (k <= 8) return go(k_memo_chain_wave<8>);
   return go(k_memo_chain_wave<kMaxD>);
+}
+
+hipError_t launch_memo_chain_window(const uint32_t* h, int k, uint64_t top, uint32_t step,
+                                    uint32_t W, uint32_t hmax, uint32_t cap_rows, uint64_t Rexp,
+                                    uint32_t* nat, uint64_t* off_out, int* err, hipStream_t s) {
+  Gens hg{};
+  for (int i = 0; i < k; ++i) hg.g[i] = h[i];
+  const size_t lds = memo_wave_lds_bytes(k, cap_rows, W);
+  static std::mutex attr_mu;
+  static std::map<const void*, size_t> attr_lds;
+  auto go = [&](auto kern) {
+    const void* f = reinterpret_cast<const void*>(kern);
+    {
+      std::lock_guard<std::mutex> lock(attr_mu);
+      size_t& have = attr_lds[f];
+      if (lds > have) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        have = lds;
+      }
+    }
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kWave), lds, s, hg, k, uint32_t(top), step, W, hmax,
+                       cap_rows - 1, uint32_t(Rexp), nat, off_out, err);
+    return hipGetLastError();
+  };
+  if (k <= 2) return go(k_memo_chain_window<2>);
+  if (k <= 4) return go(k_memo_chain_window<4>);
+  if (k <= 8) return go(k_memo_chain_window<8>);
+  return go(k_memo_chain_window<kMaxD>);
 }
 
 uint32_t memo_k1_blocks(uint64_t top) { return uint32_t((top + 1 + 255) / 256); }

@@ -357,11 +357,11 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
     }
   } sguard{scratch};
   if ((st = ensure(R->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return bail(st);
-  if ((st = ensure(scratch, (kMaxD + 3) * sizeof(uint64_t))) != ZSET_OK) return bail(st);
+  if ((st = ensure(scratch, (2 * kMaxD + 4) * sizeof(uint64_t))) != ZSET_OK) return bail(st);
   uint64_t* T = reinterpret_cast<uint64_t*>(R->table.p);
   uint64_t* sums_dev = reinterpret_cast<uint64_t*>(scratch.p);
-  int* err = reinterpret_cast<int*>(sums_dev + kMaxD + 2);  // after the d+2 sums
-  if (hipMemsetAsync(scratch.p, 0, (kMaxD + 3) * sizeof(uint64_t), s) != hipSuccess ||
+  int* err = reinterpret_cast<int*>(sums_dev + 2 * kMaxD + 3);  // after sums, |Z|, maxima
+  if (hipMemsetAsync(scratch.p, 0, (2 * kMaxD + 4) * sizeof(uint64_t), s) != hipSuccess ||
       launch_count_table(T, n_max, gens, d, sums_dev, s) != hipSuccess) {
     (void)hipGetLastError();
     return bail(fail(ZSET_EDEVICE, "count table launch failed"));

@@ -103,8 +103,9 @@ struct BatchLds {
 };
 
 // count_table.hip
-// Count table (d+1) x (n+1); when sums is non-NULL (d+2 entries) also
-// sums[j] = sum_x C[j][x] for j = 0..d and sums[d+1] = C[0][n] = |Z(n)|.
+// Count table (d+1) x (n+1); when sums is non-NULL (2d+3 entries) also
+// sums[j] = sum_x C[j][x] for j = 0..d, sums[d+1] = C[0][n] = |Z(n)| and
+// sums[d+2+j] = max_x C[j][x] (all saturating).
 hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens, int d,
                               uint64_t* sums, hipStream_t s);
 uint32_t count_table_lds_max();
@@ -132,6 +133,11 @@ uint64_t memo_wave_capacity(int k, uint32_t W, size_t lds_bytes);
 hipError_t launch_memo_chain_wave(const uint32_t* h, int k, uint64_t top, uint32_t step,
                                   uint32_t W, uint64_t Rcap, uint64_t Rexp, uint32_t* nat,
                                   uint64_t* off_out, int* err, hipStream_t s);
+// The recurrence for memos larger than LDS: a ring of cap_rows rows (a power
+// of two, >= (max(h) + step) x the longest list) and rows streamed to nat.
+hipError_t launch_memo_chain_window(const uint32_t* h, int k, uint64_t top, uint32_t step,
+                                    uint32_t W, uint32_t hmax, uint32_t cap_rows, uint64_t Rexp,
+                                    uint32_t* nat, uint64_t* off_out, int* err, hipStream_t s);
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
                               uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);

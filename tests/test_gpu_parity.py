@@ -218,7 +218,7 @@ def test_count_only_checksum():
 # Memo build (the dynamic recurrence) and memo handles
 # --------------------------------------------------------------------------
 
-@pytest.mark.parametrize("path", ["lds", "global"])
+@pytest.mark.parametrize("path", ["lds", "global", "window"])
 def test_memo_build_matches_oracle(path, monkeypatch):
     monkeypatch.setenv("ZSET_MEMO_PATH", path)
     for h, top in [([3, 5], 200), ([72, 75], 3000), ([4, 6, 9], 300), ([7], 100),
@@ -231,6 +231,17 @@ def test_memo_build_matches_oracle(path, monkeypatch):
         assert np.array_equal(off, want_off), (h, top)
         assert np.array_equal(rows, want_rows), (h, top)
         m.free()
+
+
+def test_windowed_memo_in_the_single_path(monkeypatch):
+    """Memos built with a ring of recent lists in LDS, rows streamed to global
+    memory, inside full enumerations (every k) against the oracle."""
+    monkeypatch.setenv("ZSET_MEMO_PATH", "window")
+    for n, g in [(2000, [7, 11, 13, 17]), (400, [2, 3, 5, 7, 11, 13]), (3000, [38, 40, 5, 9])]:
+        want = oracle.enumerate_rows(n, g)
+        for k in range(1, len(g)):
+            got, r = gpu_rows(n, g, k=k, rows_per_tile=256)
+            assert_same(got, want, f"window memo n={n} g={g} k={k}")
 
 
 def test_memo_lists_of_the_table1_groups():
