@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--serve-queries", type=int, default=10000,
                     help="queries per arrival rate of the served workload")
     ap.add_argument("--slots", type=int, default=8, help="server slots (served workload)")
+    ap.add_argument("--kmode", default="tuned", choices=["tuned", "auto"],
+                    help="memo dimension of the batched and served queries (both paths): the "
+                         "autotuner's table or the library's rule")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
@@ -121,6 +124,13 @@ def batch_cpu_baseline(queries, sample_rows):
                       f"oracle per query, {dt:.2f} s"}
 
 
+def k_chooser(args):
+    from paper_2407_20474_amd import zset
+    if args.kmode == "tuned":
+        return lambda n, g: zset.tuned(n, g)[0]
+    return lambda n, g: -1
+
+
 def run_batch(args):
     """The batched workload (4096 independent queries) through the request
     loop: at plan time every query's generator set is made resident up to its
@@ -139,10 +149,11 @@ def run_batch(args):
     words = sum((r * len(g) + 3) // 4 * 4 for _, g, r in allq)
     arena = torch.empty(words + 4, dtype=torch.int32, device="cuda")
     srv = zset.Server(arena, slots=args.slots)
+    kq = k_chooser(args)
     t = time.perf_counter()
     ks = []
     for i, (n, g, r) in enumerate(allq):
-        sid = srv.add_set(g, n)
+        sid = srv.add_set(g, n, k=kq(n, g))
         assert srv.count(sid, n) == r, "count disagrees with the stored workload"
         ks.append(srv.set_info(sid)["k"])
         if (i + 1) % 1024 == 0:
@@ -182,15 +193,15 @@ def run_batch(args):
         n, g, r = allq[q]
         if r == 0:
             continue
-        alone = zset.enumerate_ex(n, g)
+        alone = zset.enumerate_ex(n, g, k=ks[q])
         assert torch.equal(srv.rows_of(q, res[q]), alone.out[:r]), q
     for tk in tickets:
         srv.release(tk)
     # The plain path: one zset_enumerate_ex call per query, into the arena.
     torch.cuda.synchronize()
     tp = time.perf_counter()
-    for n, g, r in allq:
-        zset.enumerate_ex(n, g, out=arena)
+    for q, (n, g, r) in enumerate(allq):
+        zset.enumerate_ex(n, g, out=arena, k=ks[q])
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - tp
     plain_value = rows / plain_s
@@ -377,9 +388,10 @@ def run_serve(args):
         del c0, run
     arena = torch.empty((64 << 30) // 4, dtype=torch.int32, device="cuda")
     srv = zset.Server(arena, slots=args.slots)
+    kq = k_chooser(args)
     ks = []
     for s, g in enumerate(sets):
-        srv.add_set(g, max(n_need[s], 1))
+        srv.add_set(g, max(n_need[s], 1), k=kq(max(n_need[s], 1), g))
         ks.append(srv.set_info(s)["k"])
     queries = [(s, ns[i]) for i, (s, _) in enumerate(stream)]
     rows = [srv.count(s, n) for s, n in queries]
@@ -392,7 +404,7 @@ def run_serve(args):
     service = np.zeros(nq)
     for i, (s, n) in enumerate(queries):
         t = time.perf_counter()
-        zset.enumerate_ex(n, sets[s], out=arena)
+        zset.enumerate_ex(n, sets[s], out=arena, k=ks[s])
         service[i] = time.perf_counter() - t
         if (i + 1) % 2000 == 0:
             print(f"# plain {i + 1}/{nq}", file=sys.stderr, flush=True)

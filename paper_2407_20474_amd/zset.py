@@ -264,6 +264,16 @@ class Result:
     out: object = None   # torch.int32 CUDA tensor (rows, d): the uint32 rows
 
 
+def tuned(n: int, gens):
+    """(k, rows_per_tile) from the autotuner's table for this query's bucket
+    (d, decade of |Z(n)|), or (-1, 0) -- the library's own choice -- when the
+    table has no entry."""
+    from . import autotune
+    g = _gens(gens)
+    c = autotune.choose(len(g), count(n, g))
+    return c if c is not None else (-1, 0)
+
+
 def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
                  rows_per_tile: int = 0, count_only: bool = False, memo: Memo | None = None,
                  stream=None, out_rows_cap: int | None = None, claim_pct: int = -1) -> Result:
@@ -273,6 +283,9 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     import torch
     g = _gens(gens)
     d = len(g)
+    if k == "tuned":
+        k, t = tuned(n, g)
+        rows_per_tile = rows_per_tile or t
     if out is None and not count_only:
         rows = count(n, g)
         out = torch.empty((max(rows, 1), d), dtype=torch.int32, device="cuda")
@@ -430,8 +443,12 @@ class Server:
                "zset_server_create")
         self._handle = handle
 
-    def add_set(self, gens, n_max: int, k: int = -1) -> int:
+    def add_set(self, gens, n_max: int, k=-1) -> int:
+        """k: -1 (the library's rule), "tuned" (the autotuner's choice for the
+        bucket of |Z(n_max)|), or a memo dimension."""
         g = _gens(gens)
+        if k == "tuned":
+            k = tuned(n_max, g)[0]
         sid = ctypes.c_int()
         _check(load().zset_server_add_set(self._handle, g.ctypes.data_as(_u32p), len(g), n_max, k,
                                           ctypes.byref(sid)), "zset_server_add_set")

@@ -159,3 +159,18 @@ def test_server_argument_checks():
     assert lib.zset_server_add_set(None, g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), 2, 10,
                                    -1, ctypes.byref(sid)) == zset.EINVAL
     lib.zset_server_free(None)
+
+
+def test_autotune_table_is_well_formed():
+    from paper_2407_20474_amd import autotune
+    import json
+    t = json.load(open(autotune.TUNING_JSON))["buckets"]
+    for d in range(3, 10):
+        for dec in autotune.DECADES:
+            e = t[f"d={d},dec={dec}"]
+            assert 0 <= e["k"] <= d - 1 and e["rows_per_tile"] % 128 == 0 and e["rows_per_s"] > 0
+    assert autotune.bucket_key(5, 3e8) == "d=5,dec=8"
+    assert autotune.bucket_key(4, 7) == "d=4,dec=3"       # below the first decade
+    assert autotune.bucket_key(4, 5e12) == "d=4,dec=8"    # above the last
+    assert autotune.choose(6, 2e8) == (t["d=6,dec=8"]["k"], t["d=6,dec=8"]["rows_per_tile"])
+    assert autotune.choose(12, 1000) is None              # no bucket
