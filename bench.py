@@ -62,7 +62,8 @@ def parse():
     ap.add_argument("--cpu-sample-rows", type=float, default=2.5e8)
     ap.add_argument("--serve-queries", type=int, default=10000,
                     help="queries per arrival rate of the served workload")
-    ap.add_argument("--slots", type=int, default=8, help="server slots (served workload)")
+    ap.add_argument("--slots", type=int, default=16, help="server slots (batched and served)")
+    ap.add_argument("--dispatchers", type=int, default=1, help="server dispatcher threads")
     ap.add_argument("--kmode", default="tuned", choices=["tuned", "auto"],
                     help="memo dimension of the batched and served queries (both paths): the "
                          "autotuner's table or the library's rule")
@@ -148,7 +149,7 @@ def run_batch(args):
     bytes_written = sum(r * len(g) * 4 for _, g, r in allq)
     words = sum((r * len(g) + 3) // 4 * 4 for _, g, r in allq)
     arena = torch.empty(words + 4, dtype=torch.int32, device="cuda")
-    srv = zset.Server(arena, slots=args.slots)
+    srv = zset.Server(arena, slots=args.slots, dispatchers=args.dispatchers)
     kq = k_chooser(args)
     t = time.perf_counter()
     ks = []
@@ -234,6 +235,7 @@ def run_batch(args):
             "p50_done_us": float(np.percentile(done, 50)),
             "p99_done_us": float(np.percentile(done, 99)),
             "create_s": create_s, "max_inflight": st["max_inflight"],
+            "dispatcher_launch_us_per_query": round(st["launch_us"] / max(st["admitted"], 1), 2),
             "checked_against_plain": len(sample),
         },
         "step_hbm_write_frac": round(bytes_written / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
@@ -387,7 +389,7 @@ def run_serve(args):
                 n_need[s] = max(n_need[s], int(n))
         del c0, run
     arena = torch.empty((64 << 30) // 4, dtype=torch.int32, device="cuda")
-    srv = zset.Server(arena, slots=args.slots)
+    srv = zset.Server(arena, slots=args.slots, dispatchers=args.dispatchers)
     kq = k_chooser(args)
     ks = []
     for s, g in enumerate(sets):

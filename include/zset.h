@@ -302,6 +302,10 @@ typedef struct {
                                 by the caller, 16-byte aligned, kept alive until
                                 zset_server_free                               */
     uint64_t arena_bytes;    /* its size: the output budget                     */
+    int dispatchers;         /* host threads that launch and retire queries, each
+                                owning an equal share of the slots; 0 = 1 (more
+                                threads measured slower: launches serialise in
+                                the runtime)                                   */
 } zset_server_opts;
 
 typedef struct {
@@ -312,7 +316,7 @@ typedef struct {
     double done_us;          /* slot, and completion seen by the dispatcher      */
 } zset_server_result;
 
-/* Fill *opts with the defaults (8 slots, no arena). */
+/* Fill *opts with the defaults (8 slots, no arena, 1 dispatcher). */
 void zset_server_default_opts(zset_server_opts *opts);
 
 /* Start a server (its dispatcher thread) on the current device.
@@ -352,9 +356,11 @@ zset_status zset_server_wait(zset_server server, uint64_t ticket, zset_server_re
  * Errors: EINVAL (unknown ticket, query not finished). */
 zset_status zset_server_release(zset_server server, uint64_t ticket);
 
-/* Queries admitted and completed so far, and the most on the device at once. */
+/* Queries admitted and completed so far, the most on the device at once, and
+ * the dispatcher's host time spent enqueueing queries (microseconds).  Any
+ * output pointer may be NULL. */
 zset_status zset_server_stats(zset_server server, uint64_t *admitted, uint64_t *completed,
-                              uint64_t *max_inflight);
+                              uint64_t *max_inflight, double *launch_us);
 
 /* Stop the server: queries on the device finish, queued ones end with EINVAL;
  * then free every resident set (NULL is ignored).  The arena stays the

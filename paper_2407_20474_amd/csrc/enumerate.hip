@@ -124,7 +124,13 @@ __device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
 
 __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (tile == 0 && P.pool) *P.pool = 0;  // the write pass's chunk counter
+  if (tile == 0) {
+    if (P.pool) *P.pool = 0;  // the write pass's chunk counter
+    if (P.reset_status) {     // a query of its own: status words start clear
+      *P.err = 0;
+      *P.checksum = 0;
+    }
+  }
   if (tile >= P.ntiles) return;
   plan_tile(P, tile);
 }

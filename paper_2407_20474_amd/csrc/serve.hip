@@ -71,12 +71,26 @@ struct Request {
 
 struct Slot {
   hipStream_t s = nullptr;
-  hipEvent_t done = nullptr;
   DevBuf tiles, misc;  // misc: [0] status word, [1] checksum, [2] chunk counter
-  int* pinned = nullptr;
+  // Pinned host words written by the device when a query ends: [0] the
+  // query's sequence number, [1] its status word.
+  uint64_t* flag = nullptr;      // host address
+  uint64_t* flag_dev = nullptr;  // device address of the same words
+  uint64_t seq = 0;
+  double t_launch = 0;
   uint64_t ticket = 0;
   bool busy = false;
 };
+
+// End of one served query on its slot's stream: the status word, then the
+// sequence number (released at system scope) to pinned host memory, which the
+// dispatcher reads with plain loads.
+__global__ void k_query_done(const int* __restrict__ err, uint64_t* flag, uint64_t seq) {
+  if (threadIdx.x == 0) {
+    reinterpret_cast<volatile int*>(flag + 1)[0] = *err;
+    __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+}
 
 }  // namespace
 }  // namespace zset
@@ -95,9 +109,10 @@ struct zset_server_s {
   std::deque<uint64_t> queue;
   std::map<uint64_t, zset::Request> reqs;
   uint64_t next_ticket = 1;
-  std::thread worker;
+  std::vector<std::thread> workers;
   bool stop = false;
   uint64_t admitted = 0, completed = 0, max_inflight = 0;
+  double launch_us = 0;  // dispatcher host time spent enqueueing queries
 };
 
 namespace zset {
@@ -136,24 +151,26 @@ void arena_free(zset_server_s* S, uint64_t off, uint64_t words) {
   }
 }
 
-// Enqueues one admitted query on its slot's stream.  Called by the dispatcher
-// with the server lock held; every call is asynchronous.
-zset_status launch_query(zset_server_s* S, Request& r, Slot& sl) {
-  const ResidentSet& R = *S->sets[r.set];
+// Enqueues one admitted query on its slot's stream.  Called by a dispatcher
+// without the server lock (the resident set is immutable once added; the
+// slot belongs to this dispatcher); every call is asynchronous.
+zset_status launch_query(zset_server_s* S, const ResidentSet& R, uint64_t n, uint64_t rows,
+                         uint64_t out_off, Slot& sl) {
   int* err = reinterpret_cast<int*>(sl.misc.p);
   uint64_t* misc = reinterpret_cast<uint64_t*>(sl.misc.p);
-  uint32_t* out = S->arena + r.out_off;
-  ZSET_HIP(hipMemsetAsync(sl.misc.p, 0, 3 * sizeof(uint64_t), sl.s));
-  if (r.rows > 0 && R.d == 1) {
-    ZSET_HIP(launch_single(r.n, R.g[0], out, false, misc + 1, sl.s));
-  } else if (r.rows > 0) {
+  uint32_t* out = S->arena + out_off;
+  if (R.d == 1) {
+    ZSET_HIP(hipMemsetAsync(sl.misc.p, 0, 3 * sizeof(uint64_t), sl.s));
+    ZSET_HIP(launch_single(n, R.g[0], out, false, misc + 1, sl.s));
+  } else {
     EnumParams P = R.tmpl;
-    P.n = uint32_t(r.n);
-    P.total = r.rows;
+    P.n = uint32_t(n);
+    P.total = rows;
     P.out = out;
     P.err = err;
     P.checksum = misc + 1;
     P.pool = reinterpret_cast<uint32_t*>(misc + 2);
+    P.reset_status = 1;  // the slice planner clears err and checksum
     P.lds_cnt = 0;
     const size_t lds_max = size_t(write_lds_budget(S->device));
     if (R.k >= 1 && R.sum_u < (uint64_t(1) << 32) && R.memo_rows < (uint64_t(1) << 32)) {
@@ -167,35 +184,52 @@ zset_status launch_query(zset_server_s* S, Request& r, Slot& sl) {
     ZSET_HIP(launch_plan(P, sl.s));
     ZSET_HIP(launch_write(P, false, true, sl.s));
   }
-  ZSET_HIP(hipMemcpyAsync(sl.pinned, err, sizeof(int), hipMemcpyDeviceToHost, sl.s));
-  ZSET_HIP(hipEventRecord(sl.done, sl.s));
+  ++sl.seq;
+  hipLaunchKernelGGL(k_query_done, dim3(1), dim3(64), 0, sl.s, err, sl.flag_dev, sl.seq);
+  ZSET_HIP(hipGetLastError());
   return ZSET_OK;
 }
 
-void dispatcher(zset_server_s* S) {
+// Dispatcher `id` of `nth` serves the slots id, id + nth, ...: it notes their
+// completions and admits queued queries into them.
+void dispatcher(zset_server_s* S, int id, int nth) {
   (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lock(S->mu);
+  const int nslots = int(S->slots.size());
   for (;;) {
     bool busy = false;
-    // Completions.
-    for (Slot& sl : S->slots) {
+    // Completions: the slot's flag words in pinned host memory.  A slot
+    // whose flag has not come after 2 s asks the runtime whether its stream
+    // failed (a query that ends normally always sets the flag).
+    for (int si = id; si < nslots; si += nth) {
+      Slot& sl = S->slots[si];
       if (!sl.busy) continue;
-      const hipError_t q = hipEventQuery(sl.done);
-      if (q == hipErrorNotReady) {
-        busy = true;
-        continue;
+      const uint64_t got = __atomic_load_n(sl.flag, __ATOMIC_ACQUIRE);
+      hipError_t q = hipSuccess;
+      if (got != sl.seq) {
+        if (now_us(S->t0) - sl.t_launch < 2e6) {
+          busy = true;
+          continue;
+        }
+        q = hipStreamQuery(sl.s);
+        if (q == hipErrorNotReady) {
+          busy = true;
+          continue;
+        }
+        if (q == hipSuccess) q = hipErrorUnknown;  // stream done, flag never written
       }
       Request& r = S->reqs[sl.ticket];
       r.t_done = now_us(S->t0);
+      const int code = reinterpret_cast<volatile int*>(sl.flag + 1)[0];
       if (q != hipSuccess) {
         (void)hipGetLastError();
         r.state = kFailed;
         r.status = ZSET_EDEVICE;
         r.msg = std::string("query on the device: ") + hipGetErrorString(q);
-      } else if (*sl.pinned != 0) {
+      } else if (code != 0) {
         r.state = kFailed;
         r.status = ZSET_EDEVICE;
-        r.msg = device_error_text(*sl.pinned);
+        r.msg = device_error_text(code);
       } else {
         r.state = kDone;
       }
@@ -207,30 +241,47 @@ void dispatcher(zset_server_s* S) {
     // the arena.
     while (!S->queue.empty()) {
       Slot* free_slot = nullptr;
-      for (Slot& sl : S->slots)
-        if (!sl.busy) {
-          free_slot = &sl;
+      for (int si = id; si < nslots; si += nth)
+        if (!S->slots[si].busy) {
+          free_slot = &S->slots[si];
           break;
         }
       if (!free_slot) break;
       const uint64_t t = S->queue.front();
       Request& r = S->reqs[t];
+      if (r.rows == 0) {  // nothing to write: done without the device
+        S->queue.pop_front();
+        r.t_admit = r.t_done = now_us(S->t0);
+        r.state = kDone;
+        ++S->admitted;
+        ++S->completed;
+        S->cv.notify_all();
+        continue;
+      }
       if (r.words > 0 && !arena_alloc(S, r.words, &r.out_off)) break;
       S->queue.pop_front();
       r.t_admit = now_us(S->t0);
-      const zset_status st = launch_query(S, r, *free_slot);
+      r.state = kRunning;
+      free_slot->busy = true;  // this dispatcher's slot: no other thread touches it
+      const ResidentSet* R = S->sets[r.set];
+      const uint64_t qn = r.n, qrows = r.rows, qoff = r.out_off;
+      lock.unlock();
+      zset_status st = launch_query(S, *R, qn, qrows, qoff, *free_slot);
+      std::string msg = st != ZSET_OK ? g_last_error : std::string();
+      lock.lock();
+      S->launch_us += now_us(S->t0) - r.t_admit;
       if (st != ZSET_OK) {
+        free_slot->busy = false;
         r.state = kFailed;
         r.status = st;
-        r.msg = g_last_error;
+        r.msg = msg;
         r.t_done = now_us(S->t0);
         S->cv.notify_all();
         continue;
       }
-      r.state = kRunning;
+      free_slot->t_launch = r.t_admit;
       r.slot = int(free_slot - S->slots.data());
       free_slot->ticket = t;
-      free_slot->busy = true;
       busy = true;
       ++S->admitted;
     }
@@ -245,7 +296,7 @@ void dispatcher(zset_server_s* S) {
       S->cv.notify_all();
     }
     uint64_t inflight = 0;
-    for (Slot& sl : S->slots) inflight += sl.busy ? 1 : 0;
+    for (const Slot& sl : S->slots) inflight += sl.busy ? 1 : 0;
     S->max_inflight = std::max(S->max_inflight, inflight);
     if (S->stop && !busy && S->queue.empty()) break;
     if (!busy) {
@@ -253,8 +304,10 @@ void dispatcher(zset_server_s* S) {
       // the arena) or the end.
       S->cv.wait(lock);
     } else {
+      // Queries on the device: poll again at once (a timed sleep lasts tens
+      // of microseconds, longer than many queries).
       lock.unlock();
-      std::this_thread::sleep_for(std::chrono::microseconds(5));
+      std::this_thread::yield();
       lock.lock();
     }
   }
@@ -302,22 +355,26 @@ zset_status zset_server_create(const zset_server_opts* opts, zset_server* out) {
   S->slice_cap = uint64_t(cus) * 2 * write_waves_per_block() * kSlicesPerWave + 1;
   S->slots.resize(slots);
   for (Slot& sl : S->slots) {
-    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess) {
       (void)hipGetLastError();
-      return bail(fail(ZSET_EDEVICE, "stream or event creation failed"));
+      return bail(fail(ZSET_EDEVICE, "stream creation failed"));
     }
-    if (hipHostMalloc(reinterpret_cast<void**>(&sl.pinned), 16, hipHostMallocDefault) !=
-        hipSuccess) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&sl.flag), 16, hipHostMallocDefault) !=
+            hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&sl.flag_dev), sl.flag, 0) !=
+            hipSuccess) {
       (void)hipGetLastError();
-      return bail(fail(ZSET_ENOMEM, "hipHostMalloc failed"));
+      return bail(fail(ZSET_ENOMEM, "pinned completion words"));
     }
+    sl.flag[0] = 0;
+    sl.flag[1] = 0;
     zset_status st = ensure(sl.misc, 4 * sizeof(uint64_t));
     if (st == ZSET_OK)
       st = ensure(sl.tiles, size_t(S->slice_cap) * (kMaxD + 2) * sizeof(uint32_t));
     if (st != ZSET_OK) return bail(st);
   }
-  S->worker = std::thread(dispatcher, S);
+  const int nth = std::max(1, std::min(opts->dispatchers ? opts->dispatchers : 1, slots));
+  for (int i = 0; i < nth; ++i) S->workers.emplace_back(dispatcher, S, i, nth);
   *out = S;
   return ZSET_OK;
 }
@@ -567,13 +624,14 @@ zset_status zset_server_release(zset_server S, uint64_t ticket) {
 }
 
 zset_status zset_server_stats(zset_server S, uint64_t* admitted, uint64_t* completed,
-                              uint64_t* max_inflight) {
+                              uint64_t* max_inflight, double* launch_us) {
   g_last_error.clear();
   if (!S) return fail(ZSET_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> lock(S->mu);
   if (admitted) *admitted = S->admitted;
   if (completed) *completed = S->completed;
   if (max_inflight) *max_inflight = S->max_inflight;
+  if (launch_us) *launch_us = S->launch_us;
   return ZSET_OK;
 }
 
@@ -584,12 +642,12 @@ void zset_server_free(zset_server S) {
     S->stop = true;
     S->cv.notify_all();
   }
-  if (S->worker.joinable()) S->worker.join();
+  for (std::thread& w : S->workers)
+    if (w.joinable()) w.join();
   for (Slot& sl : S->slots) {
     if (sl.s) (void)hipStreamSynchronize(sl.s);
-    if (sl.done) (void)hipEventDestroy(sl.done);
     if (sl.s) (void)hipStreamDestroy(sl.s);
-    if (sl.pinned) (void)hipHostFree(sl.pinned);
+    if (sl.flag) (void)hipHostFree(sl.flag);
     for (DevBuf* b : {&sl.tiles, &sl.misc})
       if (b->p) (void)hipFree(b->p);
   }

@@ -45,6 +45,7 @@ struct EnumParams {
   uint64_t static_tiles;    // slices dealt round-robin; the rest are claimed in chunks
   uint32_t chunk;           // slices per claimed chunk (0: every slice is dealt)
   uint32_t* pool;           // chunk counter, zeroed by the slice planner
+  int reset_status;         // 1: the slice planner also clears *err and *checksum
 };
 
 // One query's share of a batched launch.

@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("arena", ctypes.c_void_p),
-                ("arena_bytes", ctypes.c_uint64)]
+                ("arena_bytes", ctypes.c_uint64), ("dispatchers", ctypes.c_int)]
 
 
 class ServerResult(ctypes.Structure):
@@ -143,7 +143,8 @@ def load():
     lib.zset_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
                                      ctypes.POINTER(ServerResult)]
     lib.zset_server_release.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
-    lib.zset_server_stats.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p]
+    lib.zset_server_stats.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p,
+                                      ctypes.POINTER(ctypes.c_double)]
     lib.zset_server_free.argtypes = [ctypes.c_void_p]
     lib.zset_server_free.restype = None
     lib.zset_strerror.argtypes = [ctypes.c_int]
@@ -428,7 +429,7 @@ class Server:
     the caller keeps it alive while the server runs.  Submission never blocks;
     wait() blocks until a query is done (the GIL is released meanwhile)."""
 
-    def __init__(self, arena, slots: int = 8):
+    def __init__(self, arena, slots: int = 8, dispatchers: int = 1):
         if arena.dtype.itemsize != 4 or not arena.is_contiguous():
             raise ValueError("arena must be a contiguous 4-byte CUDA tensor")
         self.arena = arena.reshape(-1)
@@ -436,6 +437,7 @@ class Server:
         opts = ServerOpts()
         load().zset_server_default_opts(ctypes.byref(opts))
         opts.slots = slots
+        opts.dispatchers = dispatchers
         opts.arena = self.arena.data_ptr()
         opts.arena_bytes = self.arena.numel() * 4
         handle = ctypes.c_void_p(None)
@@ -490,11 +492,11 @@ class Server:
         _check(load().zset_server_release(self._handle, ticket), "zset_server_release")
 
     def stats(self) -> dict:
-        a, c, m = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        a, c, m, t = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_double()
         _check(load().zset_server_stats(self._handle, ctypes.byref(a), ctypes.byref(c),
-                                        ctypes.byref(m)), "zset_server_stats")
+                                        ctypes.byref(m), ctypes.byref(t)), "zset_server_stats")
         return {"admitted": int(a.value), "completed": int(c.value),
-                "max_inflight": int(m.value)}
+                "max_inflight": int(m.value), "launch_us": float(t.value)}
 
     def free(self) -> None:
         if self._handle is not None and self._handle.value:

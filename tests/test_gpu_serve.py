@@ -32,10 +32,11 @@ def alone(n, g, k):
     return r.out[: r.rows].cpu().numpy().view(np.uint32).reshape(r.rows, len(g))
 
 
-def test_served_mix_matches_each_query_alone():
-    rng = np.random.default_rng(77)
+@pytest.mark.parametrize("slots,dispatchers", [(8, 2), (5, 3), (4, 1)])
+def test_served_mix_matches_each_query_alone(slots, dispatchers):
+    rng = np.random.default_rng(77 + slots)
     arena = torch.empty(6_000_000, dtype=torch.int32, device="cuda")  # 24 MB: admission waits
-    srv = zset.Server(arena, slots=8)
+    srv = zset.Server(arena, slots=slots, dispatchers=dispatchers)
     ids = []
     for g, n_max, k in SETS:
         sid = srv.add_set(g, n_max, k)
