@@ -547,6 +547,11 @@ def run_sweep(args):
 
 def main():
     args = parse()
+    if args.workload in ("batch", "serve"):
+        # One hardware queue per server slot (HIP maps streams onto
+        # GPU_MAX_HW_QUEUES queues, 4 by default, which caps how many queries
+        # run at once); it must be set before the runtime starts.
+        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.slots))))
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the enumeration shards by rank ranges with no "
               "communication, and this build runs on a single MI355X (use --gpus 1).",

@@ -129,6 +129,7 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
     if (P.reset_status) {     // a query of its own: status words start clear
       *P.err = 0;
       *P.checksum = 0;
+      if (P.blocks_done) *P.blocks_done = 0;
     }
   }
   if (tile >= P.ntiles) return;
@@ -700,6 +701,23 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     if (lane == 0 && csum != 0)
       atomicAdd(reinterpret_cast<unsigned long long*>(P.checksum),
                 static_cast<unsigned long long>(csum));
+  }
+  if (P.done_flag) {
+    // Completion for a host that polls pinned memory: every workgroup counts
+    // itself after its stores and error word (device-scope release); the
+    // last one copies the status word out and then publishes the sequence
+    // number at system scope.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const uint32_t prev = atomicAdd(P.blocks_done, 1u);
+      if (prev == gridDim.x - 1) {
+        __threadfence();
+        reinterpret_cast<volatile int*>(P.done_flag + 1)[0] =
+            __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(P.done_flag, P.done_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
   }
 }
 

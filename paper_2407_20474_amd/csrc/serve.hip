@@ -181,8 +181,14 @@ zset_status launch_query(zset_server_s* S, const ResidentSet& R, uint64_t n, uin
     if (st != ZSET_OK) return st;
     if (P.ntiles > S->slice_cap) return fail(ZSET_EDEVICE, "internal: slice table too small");
     P.tiles = reinterpret_cast<uint32_t*>(sl.tiles.p);
+    // The write pass's last workgroup posts the completion.
+    P.blocks_done = reinterpret_cast<uint32_t*>(misc + 3);
+    P.done_flag = sl.flag_dev;
+    P.done_seq = sl.seq + 1;
     ZSET_HIP(launch_plan(P, sl.s));
     ZSET_HIP(launch_write(P, false, true, sl.s));
+    ++sl.seq;
+    return ZSET_OK;
   }
   ++sl.seq;
   hipLaunchKernelGGL(k_query_done, dim3(1), dim3(64), 0, sl.s, err, sl.flag_dev, sl.seq);

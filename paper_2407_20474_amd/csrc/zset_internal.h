@@ -45,7 +45,10 @@ struct EnumParams {
   uint64_t static_tiles;    // slices dealt round-robin; the rest are claimed in chunks
   uint32_t chunk;           // slices per claimed chunk (0: every slice is dealt)
   uint32_t* pool;           // chunk counter, zeroed by the slice planner
-  int reset_status;         // 1: the slice planner also clears *err and *checksum
+  int reset_status;         // 1: the slice planner also clears *err, *checksum, *blocks_done
+  uint32_t* blocks_done;    // write workgroups finished (with done_flag)
+  uint64_t* done_flag;      // non-NULL: the last write workgroup stores *err to done_flag[1]
+  uint64_t done_seq;        // and then done_seq to done_flag[0] (pinned host words)
 };
 
 // One query's share of a batched launch.

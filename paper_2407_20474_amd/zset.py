@@ -425,6 +425,10 @@ class Batch:
 class Server:
     """Request loop over resident generator sets (zset_server_*).
 
+    HIP runs streams on GPU_MAX_HW_QUEUES hardware queues (4 by default), which
+    bounds how many queries run on the device at once: set it to the slot count
+    (at most 32) in the environment before the runtime starts.
+
     `arena` is a contiguous int32 CUDA tensor that the outputs are carved from;
     the caller keeps it alive while the server runs.  Submission never blocks;
     wait() blocks until a query is done (the GIL is released meanwhile)."""
