@@ -551,7 +551,11 @@ def main():
         # One hardware queue per server slot (HIP maps streams onto
         # GPU_MAX_HW_QUEUES queues, 4 by default, which caps how many queries
         # run at once); it must be set before the runtime starts.
-        os.environ.setdefault("GPU_MAX_HW_QUEUES", str(min(32, max(4, args.slots))))
+        # An inherited smaller value is raised.
+        want = min(32, max(4, args.slots))
+        have = os.environ.get("GPU_MAX_HW_QUEUES", "")
+        if not have.isdigit() or int(have) < want:
+            os.environ["GPU_MAX_HW_QUEUES"] = str(want)
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the enumeration shards by rank ranges with no "
               "communication, and this build runs on a single MI355X (use --gpus 1).",

@@ -74,6 +74,9 @@ std::map<int, Ctx*> g_ctx;
 
 // Slice start states each write workgroup keeps in LDS, at least.
 constexpr uint32_t kMinTileStates = 16;
+// Slices per wavefront above which a query sharing the device gets more
+// workgroups than its share.
+constexpr uint64_t kSharedSlicesPerWave = 8;
 
 // misc layout (uint64 words): [0] status word (int), [1] checksum, [2..] the
 // count table's row sums, |Z(n)| and row maxima (2 kMaxD + 3 words), then the
@@ -132,7 +135,7 @@ zset_status get_ctx(Ctx** out) {
 // concurrent write streams of a compute unit close together in memory and the
 // end of the pass even).
 zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
-                            bool count_only, bool align16) {
+                            bool count_only, bool align16, int share) {
   const int pct = claim_pct < 0 ? kDefaultClaimPct : claim_pct;
   const size_t lds_max = size_t(write_lds_budget(device));
   P.max_tiles = kMinTileStates;
@@ -158,7 +161,19 @@ zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct
   }
   const uint64_t ntiles = (P.total + T_rows - 1) / T_rows;
   if (ntiles > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
-  const uint64_t resident = uint64_t(cus) * per_cu;
+  // A query that shares the device with share - 1 others gets that share of
+  // the resident workgroups, or more when its wavefronts would otherwise take
+  // over kSharedSlicesPerWave slices each: small queries pay fewer workgroup
+  // prologues per row, large ones keep the whole device (a share fixed at
+  // admission would leave them slow once the others end).  The slice length
+  // above stays that of the whole device.
+  const uint64_t resident_all = uint64_t(cus) * per_cu;
+  uint64_t resident = resident_all;
+  if (share > 1) {
+    const uint64_t by_share = (resident_all + uint64_t(share) - 1) / uint64_t(share);
+    const uint64_t by_work = (ntiles + wpb * kSharedSlicesPerWave - 1) / (wpb * kSharedSlicesPerWave);
+    resident = std::min(resident_all, std::max<uint64_t>({by_share, by_work, 1}));
+  }
   P.static_tiles = P.chunk ? ntiles - (ntiles * uint64_t(pct) + 99) / 100 : ntiles;
   // Give each resident workgroup room for the start states of all of its
   // dealt slices when the LDS left over at this occupancy allows, so that the

@@ -122,6 +122,42 @@ __device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
   if (r >= P.table[uint64_t(P.U) * N + x]) set_error(P.err, kErrUnrank);
 }
 
+// The same slice start computed by one wavefront: per coordinate a_j, the
+// 64 lanes test 64 evenly spaced candidates at once (rows before a_j = a is
+// nondecreasing in a, so the lanes that pass form a prefix) and narrow the
+// interval 64-fold per round: ceil(log64(x / g_j + 1)) dependent loads per
+// coordinate instead of log2.  Lane 0 writes the U + 2 words to st.
+__device__ inline void plan_tile_wave(const EnumParams& P, uint64_t tile, uint32_t* st,
+                                      int lane) {
+  const uint64_t N = P.table_stride;
+  const int U = P.U;
+  uint64_t r = tile * P.rows_per_tile;
+  uint32_t x = P.n;
+  for (int j = 0; j < U; ++j) {
+    const uint64_t* Cj = P.table + uint64_t(j) * N;
+    const uint32_t g = P.g.g[j];
+    const uint64_t all = Cj[x];
+    uint32_t lo = 0, hi = x / g;  // the answer lies in [lo, hi]; lo passes
+    while (lo < hi) {
+      const uint32_t step = (hi - lo + 63) / 64;
+      const uint64_t a = uint64_t(lo) + uint64_t(lane + 1) * step;
+      const bool pass = a <= hi && all - Cj[x - a * g] <= r;
+      const uint32_t t = uint32_t(__popcll(ballot64(pass)));
+      const uint64_t fail_a = uint64_t(lo) + uint64_t(t + 1) * step;
+      hi = fail_a <= hi ? uint32_t(fail_a - 1) : hi;
+      lo += t * step;
+    }
+    r -= all - Cj[x - uint64_t(lo) * g];
+    x -= lo * g;
+    if (lane == 0) st[j] = lo;
+  }
+  if (lane == 0) {
+    st[U] = uint32_t(r);
+    st[U + 1] = uint32_t(r >> 32);
+    if (r >= P.table[uint64_t(U) * N + x]) set_error(P.err, kErrUnrank);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
   if (tile == 0) {
@@ -586,9 +622,17 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     if (threadIdx.x == 0) set_error(P.err, kErrTileRows);
     my_tiles = 0;
   }
-  for (uint32_t i = threadIdx.x; i < my_tiles * S; i += blockDim.x) {
-    const uint32_t t = i / S, w = i - t * S;
-    tstates[i] = P.tiles[(B + uint64_t(t) * NB) * S + w];
+  if (P.tiles) {
+    for (uint32_t i = threadIdx.x; i < my_tiles * S; i += blockDim.x) {
+      const uint32_t t = i / S, w = i - t * S;
+      tstates[i] = P.tiles[(B + uint64_t(t) * NB) * S + w];
+    }
+  } else {
+    // No slice table: the wavefronts compute the starts of the workgroup's
+    // slices themselves (every slice is dealt; the host sets chunk = 0).
+    const uint32_t nw = blockDim.x / kWave;
+    for (uint32_t t = uint32_t(wave); t < my_tiles; t += nw)
+      plan_tile_wave(P, B + uint64_t(t) * NB, tstates + t * S, lane);
   }
   // Claimed slices (nstatic.. ntiles-1, in chunks of CH consecutive slices
   // taken from a global counter, from the end of the order backwards: the last
@@ -715,6 +759,10 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
         __threadfence();
         reinterpret_cast<volatile int*>(P.done_flag + 1)[0] =
             __hip_atomic_load(P.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // Every workgroup has counted itself: leave the status word and the
+        // counter clear for the stream's next query.
+        __hip_atomic_store(P.err, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(P.blocks_done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(P.done_flag, P.done_seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
       }
     }
@@ -1075,6 +1123,9 @@ hipError_t launch_plan(const EnumParams& P, hipStream_t s) {
 }
 
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s) {
+  // Without a slice table the kernel plans its dealt slices itself; claimed
+  // chunks need the table.
+  if (!P.tiles && (P.chunk != 0 || P.static_tiles != P.ntiles)) return hipErrorInvalidValue;
   return dispatch<LaunchF>(P, count_only, align16, s);
 }
 

@@ -41,6 +41,8 @@ constexpr int kDefaultSlots = 8;
 // wavefront (and rows_per_tile >= 128 rows below that), so this bounds every
 // query's slice table once the device's resident wavefronts are known.
 constexpr uint64_t kSlicesPerWave = 128;
+// Slices per wavefront up to which the write pass plans its own slices.
+constexpr uint64_t kFusedSlicesPerWave = 4;
 
 double now_us(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t0).count();
@@ -71,7 +73,8 @@ struct Request {
 
 struct Slot {
   hipStream_t s = nullptr;
-  DevBuf tiles, misc;  // misc: [0] status word, [1] checksum, [2] chunk counter
+  DevBuf tiles, misc;  // misc: [0] status word, [1] checksum, [2] chunk counter,
+                       // [3] write workgroups done
   // Pinned host words written by the device when a query ends: [0] the
   // query's sequence number, [1] its status word.
   uint64_t* flag = nullptr;      // host address
@@ -154,8 +157,10 @@ void arena_free(zset_server_s* S, uint64_t off, uint64_t words) {
 // Enqueues one admitted query on its slot's stream.  Called by a dispatcher
 // without the server lock (the resident set is immutable once added; the
 // slot belongs to this dispatcher); every call is asynchronous.
+// share: queries on the device or waiting when this one is admitted (at most
+// the slot count); the write pass gets that share of the device.
 zset_status launch_query(zset_server_s* S, const ResidentSet& R, uint64_t n, uint64_t rows,
-                         uint64_t out_off, Slot& sl) {
+                         uint64_t out_off, Slot& sl, int share) {
   int* err = reinterpret_cast<int*>(sl.misc.p);
   uint64_t* misc = reinterpret_cast<uint64_t*>(sl.misc.p);
   uint32_t* out = S->arena + out_off;
@@ -177,15 +182,29 @@ zset_status launch_query(zset_server_s* S, const ResidentSet& R, uint64_t n, uin
       P.lds_cnt = 1;
       if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
     }
-    zset_status st = size_write_pass(P, 0, -1, S->device, false, true);
+    // Every slice dealt: when that leaves each wavefront at most
+    // kFusedSlicesPerWave slices, the write pass computes the slice starts
+    // itself (one launch, no slice table); otherwise the slice planner runs
+    // first and the write pass claims slices at run time.
+    EnumParams D = P;
+    zset_status st = size_write_pass(D, 0, 0, S->device, false, true, share);
     if (st != ZSET_OK) return st;
-    if (P.ntiles > S->slice_cap) return fail(ZSET_EDEVICE, "internal: slice table too small");
-    P.tiles = reinterpret_cast<uint32_t*>(sl.tiles.p);
+    const bool fused = D.ntiles <= uint64_t(D.write_blocks) *
+                                       uint64_t(write_waves_per_block()) * kFusedSlicesPerWave;
+    if (fused) {
+      P = D;
+      P.tiles = nullptr;
+    } else {
+      st = size_write_pass(P, 0, -1, S->device, false, true, share);
+      if (st != ZSET_OK) return st;
+      if (P.ntiles > S->slice_cap) return fail(ZSET_EDEVICE, "internal: slice table too small");
+      P.tiles = reinterpret_cast<uint32_t*>(sl.tiles.p);
+    }
     // The write pass's last workgroup posts the completion.
     P.blocks_done = reinterpret_cast<uint32_t*>(misc + 3);
     P.done_flag = sl.flag_dev;
     P.done_seq = sl.seq + 1;
-    ZSET_HIP(launch_plan(P, sl.s));
+    if (!fused) ZSET_HIP(launch_plan(P, sl.s));
     ZSET_HIP(launch_write(P, false, true, sl.s));
     ++sl.seq;
     return ZSET_OK;
@@ -271,8 +290,11 @@ void dispatcher(zset_server_s* S, int id, int nth) {
       free_slot->busy = true;  // this dispatcher's slot: no other thread touches it
       const ResidentSet* R = S->sets[r.set];
       const uint64_t qn = r.n, qrows = r.rows, qoff = r.out_off;
+      uint64_t share = S->queue.size() + 1;
+      for (const Slot& o : S->slots) share += o.busy && &o != free_slot ? 1 : 0;
+      share = std::min<uint64_t>(share, uint64_t(nslots));
       lock.unlock();
-      zset_status st = launch_query(S, *R, qn, qrows, qoff, *free_slot);
+      zset_status st = launch_query(S, *R, qn, qrows, qoff, *free_slot, int(share));
       std::string msg = st != ZSET_OK ? g_last_error : std::string();
       lock.lock();
       S->launch_us += now_us(S->t0) - r.t_admit;
@@ -375,6 +397,12 @@ zset_status zset_server_create(const zset_server_opts* opts, zset_server* out) {
     sl.flag[0] = 0;
     sl.flag[1] = 0;
     zset_status st = ensure(sl.misc, 4 * sizeof(uint64_t));
+    // Status word and workgroup counter start clear; the write pass's last
+    // workgroup leaves them clear after every query.
+    if (st == ZSET_OK && hipMemset(sl.misc.p, 0, 4 * sizeof(uint64_t)) != hipSuccess) {
+      (void)hipGetLastError();
+      st = fail(ZSET_EDEVICE, "clearing the slot's status words");
+    }
     if (st == ZSET_OK)
       st = ensure(sl.tiles, size_t(S->slice_cap) * (kMaxD + 2) * sizeof(uint32_t));
     if (st != ZSET_OK) return bail(st);

@@ -43,8 +43,10 @@ int write_lds_budget(int device);
 struct EnumParams;
 // Write-pass sizing (slice length, claimed chunks, slice-state capacity, grid)
 // and the leaf-order row format; shared by the single-query path and the server.
+// share: queries expected on the device at once (the grid gets 1/share of the
+// resident workgroups; 1 = the whole device).
 zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
-                            bool count_only, bool align16);
+                            bool count_only, bool align16, int share = 1);
 void leaf_format(EnumParams& P, uint64_t n, const uint32_t* gens, int U, int k);
 uint32_t next_pow2(uint32_t v);
 float elapsed_us(hipEvent_t a, hipEvent_t b);
