@@ -327,8 +327,9 @@ zset_status zset_server_create(const zset_server_opts *opts, zset_server *server
 /*
  * zset_server_add_set -- make generator set gens (host, d uint32, each >= 1,
  * in the caller's order) resident up to n_max (<= 2^31 - 2) with memo
- * dimension k (-1 = the largest k whose packed memo fits the write pass's LDS,
- * else 0).  Synchronous.  *set_id receives the set's index (0, 1, ...).
+ * dimension k (-1 = the largest k >= 2 whose memo of the trailing k generators
+ * over p <= n_max (Section 2.2, Lemma 2.3) takes at most 32 MiB, else 1; d = 1
+ * sets use 0).  Synchronous.  *set_id receives the set's index (0, 1, ...).
  * Errors: EINVAL, EOVERFLOW, ENOMEM, EDEVICE.
  */
 zset_status zset_server_add_set(zset_server server, const uint32_t *gens, int d, uint64_t n_max,

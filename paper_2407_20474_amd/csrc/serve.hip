@@ -41,6 +41,9 @@ constexpr int kDefaultSlots = 8;
 // wavefront (and rows_per_tile >= 128 rows below that), so this bounds every
 // query's slice table once the device's resident wavefronts are known.
 constexpr uint64_t kSlicesPerWave = 128;
+// Automatic memo dimension of a resident set: the largest k whose memo
+// takes at most this many bytes.
+constexpr uint64_t kResidentMemoBytes = uint64_t(32) << 20;
 // Slices per wavefront up to which the write pass plans its own slices.
 constexpr uint64_t kFusedSlicesPerWave = 4;
 
@@ -469,10 +472,12 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
   }
   const size_t lds_max = size_t(write_lds_budget(S->device));
 
-  // Memo dimension: the requested one, else the largest k whose packed memo
-  // over p <= n_max fits in the write pass's LDS; else the single-query
-  // rule (the largest k whose memo stays small beside the output, read from
-  // global memory).
+  // Memo dimension: the requested one, else the largest k whose memo over
+  // p <= n_max takes at most kResidentMemoBytes.  The memo is built once per
+  // set, so only the write pass counts: a larger k leaves fewer outer
+  // coordinates and longer segments per outer prefix, and that gain outweighs
+  // reading the memo from global memory instead of LDS up to memos of tens of
+  // megabytes.
   auto tmpl_for = [&](int kk, EnumParams& P) {
     std::memset(&P, 0, sizeof P);
     const int L = d - std::max(kk, 1);
@@ -502,21 +507,16 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
   if (d == 1) {
     kk = 0;
   } else if (kk < 0) {
-    for (int c = d - 1; c >= 1 && kk < 0; --c) {
+    kk = 1;
+    for (int c = d - 1; c >= 2; --c) {
+      const uint64_t Rc = sums[d - c];
+      if (Rc == ~uint64_t(0) || Rc >= (uint64_t(1) << 32)) continue;
       EnumParams P;
       tmpl_for(c, P);
-      if (P.pack != 0 && write_lds_bytes(P) <= lds_max) kk = c;
-    }
-    if (kk < 0) {
-      kk = 1;
-      const uint64_t total = R->c0[n_max];
-      for (int c = d - 1; c >= 1; --c) {
-        const uint64_t Rc = sums[d - c];
-        if (Rc != ~uint64_t(0) && Rc <= std::max<uint64_t>(uint64_t(1) << 16, total / 16) &&
-            Rc * (c + 1) * 4 <= (uint64_t(512) << 20)) {
-          kk = c;
-          break;
-        }
+      const uint64_t words = P.pack ? Rc * uint64_t(P.pack) : Rc * uint64_t(c + 1);
+      if (words * 4 <= kResidentMemoBytes) {
+        kk = c;
+        break;
       }
     }
   }
