@@ -70,6 +70,7 @@ struct Request {
   double t_submit = 0, t_admit = 0, t_done = 0;
   int state = kQueued;
   int slot = -1;
+  int waiters = 0;  // threads in zset_server_wait on this query
   zset_status status = ZSET_OK;
   std::string msg;
 };
@@ -111,7 +112,8 @@ struct zset_server_s {
   std::map<uint64_t, uint64_t> free_list;  // word offset -> words, coalesced
   uint64_t slice_cap = 0;                  // slices one slot's table holds
   std::mutex mu;
-  std::condition_variable cv;
+  std::condition_variable cv;       // dispatchers: submissions, arena room, stop
+  std::condition_variable cv_done;  // zset_server_wait: a waited-for query ended
   std::deque<uint64_t> queue;
   std::map<uint64_t, zset::Request> reqs;
   uint64_t next_ticket = 1;
@@ -263,7 +265,7 @@ void dispatcher(zset_server_s* S, int id, int nth) {
       }
       sl.busy = false;
       ++S->completed;
-      S->cv.notify_all();
+      if (r.waiters) S->cv_done.notify_all();
     }
     // Admissions, in arrival order: the head waits for a slot and for room in
     // the arena.
@@ -283,7 +285,7 @@ void dispatcher(zset_server_s* S, int id, int nth) {
         r.state = kDone;
         ++S->admitted;
         ++S->completed;
-        S->cv.notify_all();
+        if (r.waiters) S->cv_done.notify_all();
         continue;
       }
       if (r.words > 0 && !arena_alloc(S, r.words, &r.out_off)) break;
@@ -307,7 +309,7 @@ void dispatcher(zset_server_s* S, int id, int nth) {
         r.status = st;
         r.msg = msg;
         r.t_done = now_us(S->t0);
-        S->cv.notify_all();
+        if (r.waiters) S->cv_done.notify_all();
         continue;
       }
       free_slot->t_launch = r.t_admit;
@@ -325,6 +327,7 @@ void dispatcher(zset_server_s* S, int id, int nth) {
       }
       S->queue.clear();
       S->cv.notify_all();
+      S->cv_done.notify_all();
     }
     uint64_t inflight = 0;
     for (const Slot& sl : S->slots) inflight += sl.busy ? 1 : 0;
@@ -630,7 +633,9 @@ zset_status zset_server_wait(zset_server S, uint64_t ticket, zset_server_result*
   std::unique_lock<std::mutex> lock(S->mu);
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return fail(ZSET_EINVAL, "unknown ticket");
-  S->cv.wait(lock, [&] { return it->second.state >= kDone; });
+  ++it->second.waiters;
+  S->cv_done.wait(lock, [&] { return it->second.state >= kDone; });
+  --it->second.waiters;
   const Request& r = it->second;
   if (res) {
     res->rows = r.rows;
@@ -650,6 +655,7 @@ zset_status zset_server_release(zset_server S, uint64_t ticket) {
   auto it = S->reqs.find(ticket);
   if (it == S->reqs.end()) return fail(ZSET_EINVAL, "unknown ticket");
   if (it->second.state < kDone) return fail(ZSET_EINVAL, "the query has not finished");
+  if (it->second.waiters > 0) return fail(ZSET_EINVAL, "another thread is waiting on the query");
   if (it->second.t_admit > 0 && it->second.words > 0)
     arena_free(S, it->second.out_off, it->second.words);
   S->reqs.erase(it);
@@ -675,6 +681,7 @@ void zset_server_free(zset_server S) {
     std::lock_guard<std::mutex> lock(S->mu);
     S->stop = true;
     S->cv.notify_all();
+    S->cv_done.notify_all();
   }
   for (std::thread& w : S->workers)
     if (w.joinable()) w.join();
