@@ -75,6 +75,38 @@ def test_served_mix_matches_each_query_alone(slots, dispatchers):
     srv.free()
 
 
+def test_served_slice_plans_alone_and_shared():
+    """Queries from one row to millions of rows, each served alone (the whole
+    device) and then all at once (a share of it): small ones plan their own
+    slices inside the write pass, large ones run the slice planner and claim
+    slices; every result equals zset_enumerate_ex's bytes."""
+    arena = torch.empty(160_000_000, dtype=torch.int32, device="cuda")  # 640 MB
+    srv = zset.Server(arena, slots=8)
+    g = [13, 34, 37, 54, 65, 83]
+    sid = srv.add_set(g, 5600, -1)
+    k = srv.set_info(sid)["k"]
+    ns = [0, 13, 200, 700, 1500, 2400, 3300, 4200, 5000, 5600, 4700, 3900, 2900, 1800, 900]
+    rows = [srv.count(sid, n) for n in ns]
+    say(f"k={k} rows {rows}")
+    assert max(rows) > 4_000_000 and min(rows) <= 1
+    want = {n: zset.enumerate_ex(n, g, k=k).out for n in ns}
+    def check(mode, n, t):
+        res = srv.wait(t)
+        assert res["rows"] == srv.count(sid, n)
+        if res["rows"]:
+            got = srv.rows_of(sid, res)
+            assert torch.equal(got, want[n][: res["rows"]]), (mode, n)
+        srv.release(t)  # in arrival order: the arena (smaller than the sum) frees up
+
+    for n in ns:
+        check("alone", n, srv.submit(sid, n))
+    say("alone: every query equal")
+    for n, t in [(n, srv.submit(sid, n)) for n in ns]:
+        check("shared", n, t)
+    say("shared: every query equal")
+    srv.free()
+
+
 def test_server_errors():
     arena = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
     srv = zset.Server(arena, slots=2)
