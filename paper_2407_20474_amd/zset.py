@@ -23,6 +23,7 @@ MAX_D = 32
 SYMBOLS = (
     "zset_default_opts", "zset_count", "zset_count_table", "zset_memo_build",
     "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
+    "zset_enumerate_walk",
     "zset_batch_default_opts", "zset_batch_create", "zset_batch_info", "zset_batch_run",
     "zset_batch_times", "zset_batch_free",
     "zset_server_default_opts", "zset_server_create", "zset_server_add_set",
@@ -120,6 +121,8 @@ def load():
     lib.zset_enumerate_ex.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
                                       _u64p, _u64p, ctypes.POINTER(Stats)]
+    lib.zset_enumerate_walk.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, _u64p]
     lib.zset_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
     lib.zset_batch_default_opts.restype = None
     _i32p = ctypes.POINTER(ctypes.c_int)
@@ -309,6 +312,18 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     r = int(rows_written.value)
     view = out[:r] if (out is not None and out.dim() == 2) else out
     return Result(rows=r, checksum=int(csum.value), stats=stats.as_dict(), out=view)
+
+
+def enumerate_walk(n: int, gens, out, *, order: int = 0, stream=None) -> int:
+    """Z(n; g) through zset_enumerate_walk (no count table) into `out`, an int32
+    CUDA tensor of at least |Z(n)| * d elements; returns |Z(n)|."""
+    g = _gens(gens)
+    cap = out.numel() // len(g)
+    rows = ctypes.c_uint64()
+    _check(load().zset_enumerate_walk(n, g.ctypes.data_as(_u32p), len(g), out.data_ptr(), cap,
+                                      order, _stream_handle(stream), ctypes.byref(rows)),
+           "zset_enumerate_walk")
+    return int(rows.value)
 
 
 def enumerate(n: int, gens, out=None):
