@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch", "memo", "serve"])
+    ap.add_argument("--workload", default="large", choices=["large", "plain", "sweep", "batch", "memo", "serve", "walk"])
     ap.add_argument("--sweep-d", type=int, default=5, choices=[5, 7, 9],
                     help="dimension of the memo-dimension sweep workload")
     ap.add_argument("--seed", type=int, default=0, help="large workload seed (0, 1 or 2)")
@@ -252,6 +252,70 @@ def run_batch(args):
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = batch_cpu_baseline(allq, args.cpu_sample_rows / 10)
+    print(json.dumps(line), flush=True)
+
+
+# The table-free walk's workloads: elements above 1e9, where the count table
+# of the main path would take tens of gigabytes.
+#  - "scaled": the large workload's generators and an element scaled by
+#    c = 200003 (Z(c n; c g) = Z(n; g)), n = 8000 c: 6.2e7 rows.
+#  - "coprime": generators of gcd 1 near 1e6..1.3e7, n = 1,300,000,040.
+WALK_CASES = [
+    ("scaled", 8000 * 200003, [200003 * x for x in (13, 34, 37, 54, 65, 83)]),
+    ("coprime", 1300000040, [2000000, 3000000, 7000000, 11000000, 13000001]),
+]
+
+
+def run_walk(args):
+    """zset_enumerate_walk on elements above 1e9 (no count table): rows/s per
+    case, checked against the oracle's walk on a sample of first coordinates
+    (the whole output for the coprime case), with the count-table bytes the
+    main path would need for the same query."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2407_20474_amd import zset
+
+    cases = []
+    for name, n, g in WALK_CASES:
+        d = len(g)
+        t = time.perf_counter()
+        a1_hi = 10 if name == "scaled" else None
+        sample = oracle.enumerate_rows(n, g, 0, a1_hi)  # rows with a_1 < a1_hi (all if None)
+        cpu_s = time.perf_counter() - t
+        # Rows in all: the scaled case's count is that of the small problem.
+        rows = oracle.count(n // 200003, [x // 200003 for x in g]) if name == "scaled" else len(sample)
+        out = torch.empty(max(rows, 1) * d, dtype=torch.int32, device="cuda")
+        for _ in range(args.warmup):
+            zset.enumerate_walk(n, g, out)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t = time.perf_counter()
+            got = zset.enumerate_walk(n, g, out)
+            ts.append(time.perf_counter() - t)
+        assert got == rows
+        view = out[: len(sample) * d].view(len(sample), d).cpu().numpy().view(np.uint32)
+        assert np.array_equal(view, sample), name
+        sec = float(np.median(ts))
+        cases.append({"case": name, "n": n, "gens": g, "rows": rows, "ms": round(sec * 1e3, 3),
+                      "rows_per_s": rows / sec,
+                      "count_table_bytes_avoided": (d + 1) * (n + 1) * 8,
+                      "checked_rows": len(sample),
+                      "oracle_rows_per_s": len(sample) / cpu_s if cpu_s > 0 else None})
+        print(f"# walk {name}: {rows} rows in {sec * 1e3:.2f} ms", file=sys.stderr, flush=True)
+    main = cases[0]
+    line = {
+        "metric": "Z(n) factorizations/s emitted (bit-exact), table-free walk",
+        "value": main["rows_per_s"], "unit": "factorizations/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": main["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "walk: elements above 1e9 without the count table (value: the "
+                               "scaled case)"},
+        "walk": cases,
+    }
     print(json.dumps(line), flush=True)
 
 
@@ -581,6 +645,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "walk":
+        run_walk(args)
         return
     if args.workload == "sweep" and args.k is None:
         run_sweep(args)

@@ -176,21 +176,23 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t 
 /*
  * zset_enumerate_walk -- Z(n; g) without the count table: the lexicographic
  * walk of Section 2 (each coordinate takes its values in order, the last one
- * is forced by division), split over the prefixes of the first coordinates.
- * A pass that counts each prefix's completions, an exclusive sum, and a pass
- * that writes them place every row exactly.  Device memory beyond `out` is
- * O(prefixes) (at most 2^22 of them) instead of the count table's
- * (d + 1)(n + 1) words: the path for large n with large generators, where that
- * table would dwarf the output.  Its work is the number of vectors
- * (a_1..a_{d-1}) with a_1 g_1 + ... + a_{d-1} g_{d-1} <= n, about g_d times
- * the number of rows, so small generators belong on zset_enumerate_ex.
+ * is forced by division), split over prefixes of the first coordinates that
+ * the host refines where the estimated work is large.  A pass that counts each
+ * prefix's completions, an exclusive sum, and a pass that writes them place
+ * every row exactly.  Device memory beyond `out` is O(prefixes) (at most 2^22
+ * of them) instead of the count table's (d + 1)(n + 1) words: the path for
+ * large n with large generators, where that table would dwarf the output.
+ * The last two coordinates are solved as an arithmetic progression, so the
+ * work is the vectors (a_1..a_{d-2}) with a_1 g_1 + ... + a_{d-2} g_{d-2} <= n
+ * plus the rows; small generators make the first term large and belong on
+ * zset_enumerate_ex.
  *   out           device, out_rows_cap * d uint32
  *   out_rows_cap  rows `out` holds; ECAPACITY (nothing written) if < |Z(n)|
  *   order         0 = ascending lexicographic, 1 = descending
  *   stream        hipStream_t or NULL; the call is synchronous
  *   rows_written  host: |Z(n)|
- * Errors: EINVAL (bad d/gens/n/order, `out` NULL or not device memory,
- *         n / g_1 + 1 > 2^22), EOVERFLOW, ECAPACITY, ENOMEM, EDEVICE.
+ * Errors: EINVAL (bad d/gens/n/order, `out` NULL or not device memory),
+ *         EOVERFLOW, ECAPACITY, ENOMEM, EDEVICE.
  */
 zset_status zset_enumerate_walk(uint64_t n, const uint32_t *gens, int d, uint32_t *out,
                                 uint64_t out_rows_cap, int order, void *stream,

@@ -2,24 +2,34 @@
 //
 // The count-table path keeps (d + 1)(n + 1) counts on the device.  When n is
 // large and the generators are large too, that table dwarfs the output: at
-// n = 2e9 and d = 6 it would take 112 GB for perhaps a million rows.  This
-// path keeps O(prefixes) instead.  It is the lexicographic walk of Section 2
-// (each coordinate takes its values in order, the last one is forced by
-// division), split over the prefixes (a_1..a_m) of the first m coordinates:
+// n = 1.6e9 and d = 6 it would take 90 GB for 6e7 rows.  This path keeps
+// O(prefixes) instead.  It is the lexicographic walk of Section 2 (each
+// coordinate takes its values in order, the last one is forced by division),
+// split over prefixes (a_1..a_m):
 //
-//   host:   the prefixes with a_1 g_1 + ... + a_m g_m <= n, in lexicographic
-//           order, m grown until there are enough of them to fill the device
-//           (or m = d - 1); each is stored with its remainder.
-//   pass 1: one thread per prefix walks the rest of the coordinates and
-//           counts the rows that complete it;
+//   host:   prefixes in lexicographic order, refined where the work below
+//           them is large: a prefix whose estimated work exceeds its share is
+//           replaced by its children (the prefixes one coordinate longer), in
+//           order, until the work is spread over enough prefixes (the static
+//           counterpart of re-splitting the heaviest remaining range);
+//   pass 1: one thread per prefix walks the rest and counts the rows;
 //   scan:   exclusive sum of the counts = each prefix's first output row;
 //   pass 2: the same walk again, writing every row at its place.
+//
+// The walk below a prefix takes coordinates m..d-3 one value at a time.  For
+// the last free coordinate a_{d-1} only values that leave a remainder divisible
+// by g_d can complete a row: with h = gcd(g_{d-1}, g_d) they are the
+// progression a = a0 (mod g_d / h), a0 = (R / h) (g_{d-1} / h)^{-1} mod (g_d / h),
+// when h divides the remainder R.  So the walk's cost is its nodes above the
+// last two coordinates plus its rows, not the (g_d times larger) number of
+// vectors (a_1..a_{d-1}).
 //
 // Prefixes in ascending order and each walk ascending give the rows in
 // ascending lexicographic order; both reversed give descending order, the
 // order of the paper's streams.  Every row is found twice (count, then
 // write), the price of exact placement without counts.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -32,57 +42,88 @@ namespace zset {
 namespace {
 
 constexpr int kWalkThreads = 256;
-constexpr uint64_t kWantPrefixes = 1 << 16;   // enough threads for the device
-constexpr uint64_t kMaxPrefixes = 1 << 22;    // host enumeration bound
+constexpr uint64_t kWantPrefixes = 1 << 17;   // lanes the work is spread over
+constexpr uint64_t kMaxPrefixes = 1 << 22;    // host refinement bound
 
 struct WalkArgs {
   Gens g;
-  int d, m;                  // dimension, coordinates fixed by a prefix
+  int d;
   int desc;                  // 1: descending order
+  uint32_t h, step, inv;     // gcd(g_{d-1}, g_d), g_d / h, (g_{d-1} / h)^{-1} mod step
   uint64_t nprefix;
-  const uint32_t* pre;       // nprefix x (m + 1): remainder, a_1..a_m
+  const uint32_t* pre;       // nprefix x (d + 3): m, remainder, lo, hi, a_1..a_m
   uint64_t* cnt;             // pass 1 output
   const uint64_t* off;       // pass 2 input (exclusive sums of cnt)
   uint32_t* out;             // rows, d uint32 each
 };
 
-// The walk below one prefix: free coordinates m..d-2 take their values in
-// order (ascending, or descending when desc), coordinate d-1 is forced.
-// WRITE = false counts the rows, WRITE = true stores them from row `first`.
+// The walk below one prefix record: a_1..a_m fixed, a_{m+1} in [lo, hi],
+// later coordinates free.  WRITE = false counts the rows, WRITE = true stores
+// them from row `first`.
 template <bool WRITE>
 __device__ uint64_t walk_prefix(const WalkArgs& A, uint64_t i, uint64_t first) {
-  const int d = A.d, m = A.m;
-  const uint32_t* p = A.pre + i * uint64_t(m + 1);
+  const int d = A.d;
+  const uint32_t* p = A.pre + i * uint64_t(d + 3);
+  const int m = int(p[0]);
+  const uint32_t lo = p[2], hi = p[3];
   uint32_t a[kMaxD], r[kMaxD];
-  r[m] = p[0];
   uint64_t rows = 0;
-  auto emit = [&](uint32_t last) {
+  auto emit = [&](uint32_t al, uint32_t last) {  // al = a_{d-1}
     if (WRITE) {
       uint32_t* row = A.out + (first + rows) * uint64_t(d);
-      for (int j = 0; j < m; ++j) row[j] = p[1 + j];
-      for (int j = m; j < d - 1; ++j) row[j] = a[j];
+      for (int j = 0; j < m; ++j) row[j] = p[4 + j];
+      for (int j = m; j < d - 2; ++j) row[j] = a[j];
+      row[d - 2] = al;
       row[d - 1] = last;
     }
     ++rows;
   };
-  const uint32_t gl = A.g.g[d - 1];
-  if (m == d - 1) {
-    if (r[m] % gl == 0) emit(r[m] / gl);
+  const uint32_t g2 = A.g.g[d - 2], g1 = A.g.g[d - 1];
+  // Rows of the last two coordinates for remainder R with a_{d-1} in
+  // [vlo, vhi], in order: a_{d-1} runs over a progression of difference step.
+  auto progression = [&](uint32_t R, uint32_t vlo, uint32_t vhi) {
+    if (R % A.h != 0) return;
+    const uint64_t amax = min(uint64_t(R / g2), uint64_t(vhi));
+    const uint64_t a0 = (uint64_t((R / A.h) % A.step) * A.inv) % A.step;
+    const uint64_t v0 = vlo > a0 ? a0 + (uint64_t(vlo) - a0 + A.step - 1) / A.step * A.step : a0;
+    if (v0 > amax) return;
+    const uint64_t nv = (amax - v0) / A.step + 1;
+    for (uint64_t t = 0; t < nv; ++t) {
+      const uint32_t v = uint32_t(A.desc ? v0 + (nv - 1 - t) * A.step : v0 + t * A.step);
+      emit(v, (R - v * g2) / g1);
+    }
+  };
+  if (m == d - 1) {  // only the last coordinate is left: forced
+    if (p[1] % g1 == 0) {
+      if (WRITE) {
+        uint32_t* row = A.out + first * uint64_t(d);
+        for (int j = 0; j < d - 1; ++j) row[j] = p[4 + j];
+        row[d - 1] = p[1] / g1;
+      }
+      ++rows;
+    }
+    return rows;
+  }
+  if (m == d - 2) {
+    progression(p[1], lo, hi);
     return rows;
   }
   int j = m;
-  a[j] = A.desc ? r[j] / A.g.g[j] : 0;
+  r[j] = p[1];
+  a[j] = A.desc ? hi : lo;
   for (;;) {
-    // Descend to the forced coordinate with the first value at each level.
-    while (j < d - 2) {
+    // Descend to coordinate d - 3 with the first value at each level.
+    while (j < d - 3) {
       r[j + 1] = r[j] - a[j] * A.g.g[j];
       ++j;
       a[j] = A.desc ? r[j] / A.g.g[j] : 0;
     }
-    const uint32_t rest = r[j] - a[j] * A.g.g[j];
-    if (rest % gl == 0) emit(rest / gl);
-    // Next value at the deepest level that has one.
-    while (j >= m && (A.desc ? a[j] == 0 : a[j] == r[j] / A.g.g[j])) --j;
+    progression(r[j] - a[j] * A.g.g[j], 0, 0xffffffffu);
+    // Next value at the deepest level that has one (level m keeps to [lo, hi]).
+    for (; j >= m; --j) {
+      const uint32_t end = A.desc ? (j == m ? lo : 0u) : (j == m ? hi : r[j] / A.g.g[j]);
+      if (a[j] != end) break;
+    }
     if (j < m) break;
     a[j] = A.desc ? a[j] - 1 : a[j] + 1;
   }
@@ -101,40 +142,116 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
     (void)walk_prefix<true>(A, i, A.off[i]);
 }
 
-// Prefixes (remainder, a_1..a_m) of the first m coordinates in ascending
-// lexicographic order, m grown while the next level stays within
-// kMaxPrefixes and the current one has fewer than kWantPrefixes.
-void make_prefixes(uint64_t n, const uint32_t* g, int d, std::vector<uint32_t>* pre, int* m_out) {
-  // Level m = 1 (the caller has checked that n / g_1 + 1 <= kMaxPrefixes).
-  std::vector<uint32_t> cur;
-  cur.reserve(2 * (n / g[0] + 1));
-  int m = 1;
-  for (uint64_t a = 0; a * g[0] <= n; ++a) {
-    cur.push_back(uint32_t(n - a * g[0]));
-    cur.push_back(uint32_t(a));
-  }
-  while (m < d - 1 && cur.size() / (m + 1) < kWantPrefixes) {
-    std::vector<uint32_t> next;
-    bool over = false;
-    const uint64_t np = cur.size() / (m + 1);
-    for (uint64_t i = 0; i < np && !over; ++i) {
-      const uint32_t* p = &cur[i * (m + 1)];
-      for (uint64_t a = 0; uint64_t(a) * g[m] <= p[0]; ++a) {
-        if (next.size() / (m + 2) >= kMaxPrefixes) {
-          over = true;
-          break;
-        }
-        next.push_back(uint32_t(p[0] - a * g[m]));
-        for (int j = 0; j < m; ++j) next.push_back(p[1 + j]);
-        next.push_back(uint32_t(a));
-      }
+// Host side: prefix records and their estimated work.
+struct Prefix {
+  int m;
+  uint64_t x, lo, hi;        // remainder before a_{m+1}; a_{m+1} in [lo, hi]
+  uint32_t a[kMaxD];         // a_1..a_m
+};
+
+// Progressions run below coordinate m with remainder y when a_{m+1} takes
+// every value: the simplex volume of (a_{m+1}..a_{d-2}), sum a_j g_j <= y.
+double walk_volume(double y, int m, const uint32_t* g, int d) {
+  if (y < 0) return 0;
+  double e = 1.0;
+  for (int j = m, t = 1; j < d - 2; ++j, ++t) e *= y / double(g[j]) / double(t);
+  return e;
+}
+
+// Estimated work of a record: its progressions (the volume between the
+// remainders left by lo and by hi + 1), each with the rows of an average
+// progression; at the progression level, its rows.
+double walk_estimate(const Prefix& p, const uint32_t* g, int d, uint32_t step) {
+  if (p.m >= d - 1) return 0;
+  if (p.m == d - 2) return double(p.hi - p.lo + 1) / double(step);
+  const double y0 = double(p.x) - double(p.lo) * g[p.m];
+  const double y1 = double(p.x) - double(p.hi + 1) * g[p.m];
+  const double vol = walk_volume(y0, p.m, g, d) - walk_volume(y1, p.m, g, d);
+  const double prog = double(p.x) / double(d - 1 - p.m) / double(g[d - 2]) / double(step);
+  return vol * (1.0 + prog);
+}
+
+// The record of a_1..a_m = a[0..m) with a_{m+1} over all its values.
+Prefix full_prefix(int m, uint64_t x, const uint32_t* a, const uint32_t* g, int d) {
+  Prefix p;
+  p.m = m;
+  p.x = x;
+  std::memcpy(p.a, a, sizeof(uint32_t) * size_t(m));
+  p.lo = 0;
+  p.hi = m < d - 1 ? x / g[m] : 0;
+  return p;
+}
+
+// Prefix records in lexicographic order: from the whole range, every record
+// whose estimate exceeds twice the share of one of kWantPrefixes lanes (and
+// one unit) is split -- a range of a_{m+1} in two halves of about equal work,
+// a single value into the next coordinate's range -- until the list holds
+// kMaxPrefixes.  This is the static counterpart of re-splitting the heaviest
+// remaining lexicographic range.  Depth first with an explicit stack, so the
+// records come out in order in one pass.
+std::vector<Prefix> make_prefixes(uint64_t n, const uint32_t* g, int d, uint32_t step) {
+  Prefix root = full_prefix(0, n, nullptr, g, d);
+  const double share =
+      std::max(1.0, 2.0 * walk_estimate(root, g, d, step) / double(kWantPrefixes));
+  std::vector<Prefix> out, stack;
+  stack.push_back(std::move(root));
+  while (!stack.empty()) {
+    Prefix p = std::move(stack.back());
+    stack.pop_back();
+    if (p.m >= d - 1 || out.size() + stack.size() + 2 > kMaxPrefixes ||
+        walk_estimate(p, g, d, step) <= share) {
+      out.push_back(std::move(p));
+      continue;
     }
-    if (over) break;
-    cur.swap(next);
-    ++m;
+    if (p.hi > p.lo) {
+      // Equal-work split point: the volume is a power of the remainder.
+      uint64_t mid = p.lo + (p.hi - p.lo) / 2;
+      if (p.m < d - 2) {
+        const double k = double(d - 2 - p.m);
+        const double y0 = double(p.x) - double(p.lo) * g[p.m];
+        const double y1 = std::max(0.0, double(p.x) - double(p.hi + 1) * g[p.m]);
+        const double ym = std::pow(0.5 * (std::pow(y0, k) + std::pow(y1, k)), 1.0 / k);
+        const double cut = (double(p.x) - ym) / double(g[p.m]);
+        if (cut >= double(p.lo) && cut < double(p.hi)) mid = uint64_t(cut);
+      }
+      Prefix l = p;
+      l.hi = mid;
+      p.lo = mid + 1;
+      stack.push_back(std::move(p));  // the upper half is taken after the lower
+      stack.push_back(std::move(l));
+    } else {
+      p.a[p.m] = uint32_t(p.lo);
+      stack.push_back(full_prefix(p.m + 1, p.x - p.lo * g[p.m], p.a, g, d));
+    }
   }
-  pre->swap(cur);
-  *m_out = m;
+  return out;
+}
+
+uint32_t gcd32(uint32_t a, uint32_t b) {
+  while (b) {
+    const uint32_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// x^{-1} mod m for gcd(x, m) = 1 (0 when m = 1), by the extended Euclidean
+// algorithm.
+uint32_t inverse_mod(uint32_t x, uint32_t m) {
+  if (m == 1) return 0;
+  int64_t t = 0, nt = 1, r = m, nr = x % m;
+  while (nr != 0) {
+    const int64_t q = r / nr;
+    int64_t tmp = t - q * nt;
+    t = nt;
+    nt = tmp;
+    tmp = r - q * nr;
+    r = nr;
+    nr = tmp;
+  }
+  if (t < 0) t += m;
+  return uint32_t(t);
 }
 
 struct WalkCtx {
@@ -184,16 +301,20 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
     return ZSET_OK;
   }
 
-  if (n / gens[0] + 1 > kMaxPrefixes)
-    return fail(ZSET_EINVAL, "n / g_1 + 1 exceeds 2^22 first-coordinate values: use "
-                             "zset_enumerate_ex");
-  std::vector<uint32_t> pre;
-  int m = 1;
-  make_prefixes(n, gens, d, &pre, &m);
-  const uint64_t np = pre.size() / uint64_t(m + 1);
-  if (order == 1) {  // descending: prefixes in reverse order
-    for (uint64_t i = 0, j = np - 1; i < j; ++i, --j)
-      for (int w = 0; w <= m; ++w) std::swap(pre[i * (m + 1) + w], pre[j * (m + 1) + w]);
+  const uint32_t h = gcd32(gens[d - 2], gens[d - 1]);
+  std::vector<Prefix> list = make_prefixes(n, gens, d, gens[d - 1] / h);
+  if (order == 1) std::reverse(list.begin(), list.end());  // descending: reverse order
+  const uint64_t W = uint64_t(d + 3);
+  const uint64_t np = list.size();
+  std::vector<uint32_t> pre(np * W, 0);
+  for (uint64_t i = 0; i < np; ++i) {
+    const Prefix& p = list[i];
+    uint32_t* r = &pre[i * W];
+    r[0] = uint32_t(p.m);
+    r[1] = uint32_t(p.x);
+    r[2] = uint32_t(p.lo);
+    r[3] = uint32_t(p.hi);
+    for (int j = 0; j < p.m; ++j) r[4 + j] = p.a[j];
   }
   if ((st = ensure(c.pre, pre.size() * sizeof(uint32_t))) != ZSET_OK) return st;
   if ((st = ensure(c.cnt, (np + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
@@ -205,8 +326,10 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
   std::memset(&A, 0, sizeof A);
   for (int i = 0; i < d; ++i) A.g.g[i] = gens[i];
   A.d = d;
-  A.m = m;
   A.desc = order;
+  A.h = h;
+  A.step = gens[d - 1] / A.h;
+  A.inv = inverse_mod((gens[d - 2] / A.h) % A.step, A.step);
   A.nprefix = np;
   A.pre = reinterpret_cast<const uint32_t*>(c.pre.p);
   A.cnt = reinterpret_cast<uint64_t*>(c.cnt.p);

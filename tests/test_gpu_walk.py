@@ -83,7 +83,7 @@ def test_walk_edges_and_errors():
     out = torch.empty(3 * 2, dtype=torch.int32, device="cuda")
     with pytest.raises(zset.ZsetError):  # 4 rows do not fit in 2
         zset.enumerate_walk(30, [5, 6, 10], out)
-    with pytest.raises(zset.ZsetError):  # 2^30 first-coordinate values
-        zset.enumerate_walk(1 << 30, [1, 5], torch.empty(64, dtype=torch.int32, device="cuda"))
+    # 2^29 first-coordinate values (no prefix refinement fits): one prefix.
+    assert walk(1 << 29, [1, 1 << 28], 0, 3).tolist() == [[0, 2], [1 << 28, 1], [1 << 29, 0]]
     with pytest.raises(zset.ZsetError):
         zset.enumerate_walk(10, [3, 5], out, order=2)
