@@ -31,6 +31,7 @@
 // Z(x; G, h) = {(a, m) : m in Memo[x - a G]} are one contiguous run that
 // starts at end[x mod G] - |Z(x; G, h)|, in ascending lex order, and each
 // memo row carries floor(p / G) so that a = floor(x / G) - floor(p / G).
+#include <algorithm>
 #include <cstring>
 
 #include <map>
@@ -421,10 +422,40 @@ __device__ inline void memo_leaf_element(const LeafJob& J, uint32_t p, int* __re
   }
 }
 
+// One thread per memo row t, in natural order: its element p is the last one
+// with off[p] <= t (bisection of the offsets), and its place in the leaf
+// layout is end[p mod G] - C_U[p] + (t - off[p]).  Rows of one element are
+// adjacent in both layouts, so neighbouring threads read and write
+// neighbouring rows, and a long list costs no more than many short ones.
 __global__ __launch_bounds__(256) void k_memo_leaf(LeafJob J, int* __restrict__ err) {
-  const uint64_t p64 = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (p64 > J.n) return;
-  memo_leaf_element(J, uint32_t(p64), err);
+  const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (t == 0 && J.off[uint64_t(J.n) + 1] != J.leaf_rows) set_error(err, kErrMemoTotal);
+  if (t >= J.leaf_rows) return;
+  uint32_t lo = 0, hi = J.n;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (J.off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t p = lo;
+  const int k = J.k;
+  const uint32_t q = J.dG.div(p);
+  const uint32_t rho = J.dG.mod(p, q);
+  const uint64_t pos = J.endc[rho] - J.cu[p] + (t - J.off[p]);
+  if (pos >= J.leaf_rows) {
+    set_error(err, kErrMemoTotal);
+    return;
+  }
+  const uint32_t* src = J.nat + t * k;
+  if (J.pack == 0) {
+    uint32_t* dst = J.leaf + pos * (k + 1);
+    dst[0] = q;
+    for (int c = 0; c < k; ++c) dst[1 + c] = src[c];
+  } else {
+    uint64_t w = uint64_t(q) << J.fshift[0];
+    for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << J.fshift[1 + c];
+    if (J.pack == 1) J.leaf[pos] = uint32_t(w);
+    else reinterpret_cast<uint64_t*>(J.leaf)[pos] = w;
+  }
 }
 
 // Batched: the workgroups of job j are [jobs[j].block0, jobs[j + 1].block0).
@@ -569,8 +600,9 @@ LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const 
 }
 
 hipError_t launch_memo_leaf(const LeafJob& J, int* err, hipStream_t s) {
-  const uint32_t blocks = uint32_t((uint64_t(J.n) + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_memo_leaf, dim3(blocks), dim3(256), 0, s, J, err);
+  const uint64_t blocks = std::max<uint64_t>(1, (J.leaf_rows + 255) / 256);
+  if (blocks > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_memo_leaf, dim3(uint32_t(blocks)), dim3(256), 0, s, J, err);
   return hipGetLastError();
 }
 
