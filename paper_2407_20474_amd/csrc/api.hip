@@ -61,7 +61,7 @@ namespace {
 // Per-device scratch, reused across calls.
 struct Ctx {
   int device = -1;
-  DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount;
+  DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount, cnt2;
   uint64_t* pinned = nullptr;  // host readback area
   hipEvent_t ev[7] = {};
   // Side stream for a memo recurrence that runs beside the count table, with
@@ -294,7 +294,8 @@ int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
 // (k_memo_chain_wave), which also writes the offsets; larger ones by one
 // wavefront with a ring of the last lists in LDS (k_memo_chain_window) when
 // that ring fits, else by the global schedule after a scan.
-// ZSET_MEMO_PATH=global / window forces those paths (tests).
+// ZSET_MEMO_PATH=global / window forces those paths (tests); =chain keeps the
+// recurrence for k = 2 memos that the single path would build in closed form.
 zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint64_t rowmax,
                             uint32_t* nat, hipStream_t s) {
@@ -550,13 +551,14 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   } side_join;
   bool early = false;
   uint64_t early_cap = 0;
-  // The recurrence is enqueued first: it is the longer of the two and the
-  // rest of the call waits for it.  The fork event orders it after the status
-  // reset.
+  // The memo build (closed form for k = 2, else the recurrence) is enqueued
+  // first: the rest of the call waits for it.  The fork event orders it after
+  // the status reset.
   ZSET_HIP(hipEventRecord(c->fork, s));
   {
     const char* path = std::getenv("ZSET_MEMO_PATH");
     const bool force_global = path && std::strcmp(path, "global") == 0;
+    const bool force_chain = path && std::strcmp(path, "chain") == 0;
     if (!memo && opts.k >= 1 && d >= 2 && !force_global) {
       const int kk = opts.k, L0 = d - kk;
       uint32_t b = gens[L0], hmax = gens[L0];
@@ -577,9 +579,18 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
           ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
           side_join.c = c;
           ZSET_HIP(hipEventRecord(c->memo0, c->side));
-          ZSET_HIP(launch_memo_chain_wave(gens + L0, kk, N, step, W, early_cap, 0,
-                                          reinterpret_cast<uint32_t*>(c->nat.p),
-                                          reinterpret_cast<uint64_t*>(c->off.p), err, c->side));
+          if (kk == 2 && !force_chain) {
+            // Two coordinates: the closed form, element-parallel.
+            if ((st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+            ZSET_HIP(launch_memo_k2(gens[L0], gens[L0 + 1], N, early_cap,
+                                    reinterpret_cast<uint32_t*>(c->nat.p),
+                                    reinterpret_cast<uint64_t*>(c->off.p),
+                                    reinterpret_cast<uint64_t*>(c->cnt2.p), c->side));
+          } else {
+            ZSET_HIP(launch_memo_chain_wave(gens + L0, kk, N, step, W, early_cap, 0,
+                                            reinterpret_cast<uint32_t*>(c->nat.p),
+                                            reinterpret_cast<uint64_t*>(c->off.p), err, c->side));
+          }
           ZSET_HIP(hipEventRecord(c->memo1, c->side));
           early = true;
         }

@@ -329,6 +329,53 @@ __global__ __launch_bounds__(256) void k_memo_k1(uint32_t h, uint32_t top, uint3
   memo_k1_item(h, top, R, uint64_t(blockIdx.x) * 256 + threadIdx.x, nat, off);
 }
 
+// k = 2: Z(p; h_1, h_2) in closed form.  With c = gcd(h_1, h_2), p has rows
+// only when c divides p; then m_1 runs over the progression
+// m_1 = m0 (mod h_2 / c), m0 = (p / c) (h_1 / c)^{-1} mod (h_2 / c), from m0
+// to (p / c) / (h_1 / c), and m_2 = (p - m_1 h_1) / h_2.  Every element is
+// independent: a counting pass, an exclusive sum (the natural offsets) and a
+// filling pass replace the recurrence's top / min(h) dependent batches with
+// the same lists in the same ascending order.
+struct Memo2 {
+  uint32_t h1, h2, c, h1c, h2c, inv;  // inv = (h1 / c)^{-1} mod (h2 / c)
+};
+
+__device__ inline bool memo2_first(const Memo2& M, uint32_t p, uint32_t* m0, uint32_t* rows) {
+  if (p % M.c != 0) return false;
+  const uint32_t q = p / M.c;
+  const uint32_t mmax = q / M.h1c;
+  const uint32_t a = uint32_t((uint64_t(q % M.h2c) * M.inv) % M.h2c);
+  if (a > mmax) return false;
+  *m0 = a;
+  *rows = (mmax - a) / M.h2c + 1;
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_memo2_count(Memo2 M, uint32_t top,
+                                                     uint64_t* __restrict__ cnt) {
+  const uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p > top) return;
+  uint32_t m0 = 0, rows = 0;
+  cnt[p] = (p < top && memo2_first(M, uint32_t(p), &m0, &rows)) ? rows : 0;  // cnt[top] = 0
+}
+
+// Rows beyond cap (the buffer's capacity) are not written; the caller
+// compares the total with cap.
+__global__ __launch_bounds__(256) void k_memo2_fill(Memo2 M, uint32_t top, uint64_t cap,
+                                                    const uint64_t* __restrict__ off,
+                                                    uint32_t* __restrict__ nat) {
+  const uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (p >= top) return;
+  uint32_t m0 = 0, rows = 0;
+  if (!memo2_first(M, uint32_t(p), &m0, &rows)) return;
+  const uint64_t o = off[p];
+  for (uint32_t t = 0; t < rows && o + t < cap; ++t) {
+    const uint32_t m1 = m0 + t * M.h2c;
+    nat[(o + t) * 2] = m1;
+    nat[(o + t) * 2 + 1] = (uint32_t(p) - m1 * M.h1) / M.h2;
+  }
+}
+
 // Batched: the workgroups of job j are [jobs[j].block0, jobs[j + 1].block0).
 __global__ __launch_bounds__(256) void k_memo_k1_batch(const MemoJob* __restrict__ jobs,
                                                        uint32_t njobs) {
@@ -545,6 +592,45 @@ hipError_t launch_memo_chain_window(const uint32_t* h, int k, uint64_t top, uint
 }
 
 uint32_t memo_k1_blocks(uint64_t top) { return uint32_t((top + 1 + 255) / 256); }
+
+hipError_t launch_memo_k2(uint32_t h1, uint32_t h2, uint64_t top, uint64_t cap, uint32_t* nat,
+                          uint64_t* off, uint64_t* cnt, hipStream_t s) {
+  if (top == 0 || top >= 0xffffffffull) return hipErrorInvalidValue;
+  auto gcd = [](uint32_t a, uint32_t b) {
+    while (b) {
+      const uint32_t t = a % b;
+      a = b;
+      b = t;
+    }
+    return a;
+  };
+  Memo2 M;
+  M.h1 = h1;
+  M.h2 = h2;
+  M.c = gcd(h1, h2);
+  M.h1c = h1 / M.c;
+  M.h2c = h2 / M.c;
+  // (h1 / c)^{-1} mod (h2 / c) by the extended Euclidean algorithm.
+  int64_t t0 = 0, t1 = 1, r0 = M.h2c, r1 = M.h1c % M.h2c;
+  while (r1 != 0) {
+    const int64_t q = r0 / r1;
+    int64_t x = t0 - q * t1;
+    t0 = t1;
+    t1 = x;
+    x = r0 - q * r1;
+    r0 = r1;
+    r1 = x;
+  }
+  M.inv = M.h2c == 1 ? 0 : uint32_t(t0 < 0 ? t0 + M.h2c : t0);
+  const uint32_t blocks = uint32_t((top + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_memo2_count, dim3(blocks), dim3(256), 0, s, M, uint32_t(top), cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = launch_exclusive_scan(cnt, top + 1, off, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_memo2_fill, dim3(blocks), dim3(256), 0, s, M, uint32_t(top), cap, off, nat);
+  return hipGetLastError();
+}
 
 hipError_t launch_memo_k1(uint32_t h, uint64_t top, uint64_t R, uint32_t* nat, uint64_t* off,
                           hipStream_t s) {

@@ -151,6 +151,11 @@ LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const 
 hipError_t launch_memo_leaf(const LeafJob& J, int* err, hipStream_t s);
 hipError_t launch_memo_leaf_batch(const LeafJob* jobs, uint32_t njobs, uint32_t blocks,
                                   int* err, hipStream_t s);
+// k = 2 in closed form: counts per element into cnt (top + 1 words), their
+// exclusive sum into off (top + 1 words: off[top] = rows over p < top) and
+// the rows into nat (at most cap rows written).
+hipError_t launch_memo_k2(uint32_t h1, uint32_t h2, uint64_t top, uint64_t cap, uint32_t* nat,
+                          uint64_t* off, uint64_t* cnt, hipStream_t s);
 // k = 1: the closed solution of the recurrence, one parallel pass.
 uint32_t memo_k1_blocks(uint64_t top);
 hipError_t launch_memo_k1(uint32_t h, uint64_t top, uint64_t R, uint32_t* nat, uint64_t* off,

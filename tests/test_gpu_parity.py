@@ -244,6 +244,22 @@ def test_windowed_memo_in_the_single_path(monkeypatch):
             assert_same(got, want, f"window memo n={n} g={g} k={k}")
 
 
+@pytest.mark.parametrize("path", ["default", "chain"])
+def test_two_coordinate_memo_in_the_single_path(path, monkeypatch):
+    """k = 2 memos of the single path: the closed form (default) and the
+    recurrence (forced), inside full enumerations against the oracle; also
+    generators with a common factor and a first generator larger than the
+    second."""
+    if path == "chain":
+        monkeypatch.setenv("ZSET_MEMO_PATH", "chain")
+    for n, g in [(2000, [7, 11, 13, 17]), (1500, [13, 34, 37, 54, 65, 83]),
+                 (900, [5, 9, 6, 10]), (700, [3, 4, 12, 8]), (400, [2, 3, 1, 1]),
+                 (3000, [38, 40, 45, 36])]:
+        want = oracle.enumerate_rows(n, g)
+        got, r = gpu_rows(n, g, k=2, rows_per_tile=256)
+        assert_same(got, want, f"k=2 memo ({path}) n={n} g={g}")
+
+
 def test_memo_lists_of_the_table1_groups():
     """The FactorizationsUpToElement lists of the paper's Table 1 memo groups
     (generators the first d of 13, 37, 38, 40..45; memo of the trailing k up to
