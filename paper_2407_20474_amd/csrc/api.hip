@@ -294,8 +294,9 @@ int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
 // (k_memo_chain_wave), which also writes the offsets; larger ones by one
 // wavefront with a ring of the last lists in LDS (k_memo_chain_window) when
 // that ring fits, else by the global schedule after a scan.
-// ZSET_MEMO_PATH=global / window forces those paths (tests); =chain keeps the
-// recurrence for k = 2 memos that the single path would build in closed form.
+// ZSET_MEMO_PATH=global / window forces those paths (tests); =chain (and
+// either of those) keeps the recurrence for k = 2 memos, which the single path
+// otherwise builds in closed form.
 zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint64_t rowmax,
                             uint32_t* nat, hipStream_t s) {
@@ -739,9 +740,20 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
         if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
         uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
-        st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
-                             reinterpret_cast<uint32_t*>(c->nat.p), s);
-        if (st != ZSET_OK) return st;
+        const char* path = std::getenv("ZSET_MEMO_PATH");
+        const bool closed2 = k == 2 && !(path && (std::strcmp(path, "chain") == 0 ||
+                                                  std::strcmp(path, "global") == 0 ||
+                                                  std::strcmp(path, "window") == 0));
+        if (closed2) {  // two coordinates: the closed form, element-parallel
+          if ((st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+          ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn,
+                                  reinterpret_cast<uint32_t*>(c->nat.p), o,
+                                  reinterpret_cast<uint64_t*>(c->cnt2.p), s));
+        } else {
+          st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
+                               reinterpret_cast<uint32_t*>(c->nat.p), s);
+          if (st != ZSET_OK) return st;
+        }
         off = o;
         nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       }

@@ -254,7 +254,8 @@ def test_two_coordinate_memo_in_the_single_path(path, monkeypatch):
         monkeypatch.setenv("ZSET_MEMO_PATH", "chain")
     for n, g in [(2000, [7, 11, 13, 17]), (1500, [13, 34, 37, 54, 65, 83]),
                  (900, [5, 9, 6, 10]), (700, [3, 4, 12, 8]), (400, [2, 3, 1, 1]),
-                 (3000, [38, 40, 45, 36])]:
+                 (3000, [38, 40, 45, 36]), (30000, [1000, 1500, 7, 11])]:
+        # The last case's memo (5.8e6 rows) exceeds what the early build holds.
         want = oracle.enumerate_rows(n, g)
         got, r = gpu_rows(n, g, k=2, rows_per_tile=256)
         assert_same(got, want, f"k=2 memo ({path}) n={n} g={g}")
