@@ -11,10 +11,13 @@
 //
 // Row j is a column-wise inclusive prefix sum of row j+1 viewed as a matrix
 // with g_j columns (x = t * g_j + rho): column rho is the residue class
-// rho mod g_j.  One workgroup computes all rows with a three-phase blocked scan
-// per row (chunk sums, carries per column, rescan), which keeps every load
-// coalesced across adjacent residues; the row sums are reduced on the way.
-// In a batch, each workgroup computes the table of one query.
+// rho mod g_j.  Tables of at most 16384 entries per row: one workgroup
+// computes all rows in LDS with a three-phase blocked scan per row (chunk
+// sums, carries per column, rescan), the row sums reduced on the way.  Larger
+// tables: one launch per row over all workgroups, every residue class scanned
+// at once.  In a batch, each workgroup computes the table of one query.
+#include <algorithm>
+
 #include "zset_internal.h"
 
 namespace zset {
@@ -53,8 +56,9 @@ __device__ inline uint64_t block_sum_u64(uint64_t v, uint64_t* red) {
   return t;
 }
 
-// The whole table by one workgroup in global memory (any N), with the row
-// sums sums[j] = sum_x C[j][x] (saturating) when sums is non-NULL.  `gs` is
+// The whole table by one workgroup in global memory (any N; the batched form
+// for tables beyond LDS), with the row sums sums[j] = sum_x C[j][x]
+// (saturating) when sums is non-NULL.  `gs` is
 // a copy of the generators in LDS.
 __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs,
                                    int d, uint64_t* __restrict__ sums,
@@ -241,17 +245,6 @@ __device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint
   }
 }
 
-__global__ __launch_bounds__(kCtThreads) void k_count_table(uint64_t* __restrict__ T,
-                                                            uint32_t N, Gens gs, int d,
-                                                            uint64_t* __restrict__ sums) {
-  __shared__ uint32_t g[kMaxD];
-  if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
-  __syncthreads();
-  count_table_global(T, N, g, d, sums, sums ? sums + d + 2 : nullptr);
-  __syncthreads();
-  if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
-}
-
 __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
                                                                 uint32_t N, Gens gs, int d,
                                                                 uint64_t* __restrict__ sums) {
@@ -262,6 +255,111 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf);
   __syncthreads();
   if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
+}
+
+// ---------------------------------------------------------------------------
+// Tables beyond LDS (n + 1 > kCtLdsMax): one launch per row, all workgroups.
+// Row j's residue classes mod g_j are independent prefix sums of row j+1, so
+// a launch scans every class at once: classes of at most kShortClass entries
+// one per thread, longer ones one per workgroup (a blocked scan in tiles of
+// 1024 entries).  Row sums and maxima follow in one launch, a workgroup per
+// row.
+constexpr int kRowThreads = 256;
+constexpr uint32_t kShortClass = 64;
+
+// Row d = [x == 0].
+__global__ __launch_bounds__(kRowThreads) void k_count_init(uint64_t* __restrict__ T, uint32_t N,
+                                                            int d) {
+  const uint64_t i = uint64_t(blockIdx.x) * kRowThreads + threadIdx.x;
+  uint64_t* last = T + uint64_t(d) * N;
+  for (uint64_t x = i; x < N; x += uint64_t(gridDim.x) * kRowThreads) last[x] = (x == 0) ? 1 : 0;
+}
+
+// Row sums and maxima, one workgroup per row j = 0..d (no atomics), and
+// |Z(n)| = C[0][n].
+__global__ __launch_bounds__(kCtThreads) void k_count_stats(const uint64_t* __restrict__ T,
+                                                            uint32_t N, int d,
+                                                            uint64_t* __restrict__ sums) {
+  __shared__ uint64_t red[kCtThreads / kWave];
+  const int j = blockIdx.x;
+  const uint64_t* V = T + uint64_t(j) * N;
+  uint64_t acc = 0, mx = 0;
+  for (uint64_t x = threadIdx.x; x < N; x += kCtThreads) {
+    const uint64_t v = V[x];
+    acc = sat_add_u64(acc, v);
+    mx = v > mx ? v : mx;
+  }
+  const uint64_t total = block_sum_u64(acc, red);
+  const uint64_t top = block_max_u64(mx, red);
+  if (threadIdx.x == 0) {
+    sums[j] = total;
+    sums[d + 2 + j] = top;
+    if (j == 0) sums[d + 1] = V[N - 1];
+  }
+}
+
+// Row j from row j + 1, one thread per residue class (classes of at most
+// kShortClass entries, or g_j >= N: a copy).
+__global__ __launch_bounds__(kRowThreads) void k_count_row_short(uint64_t* __restrict__ T,
+                                                                 uint32_t N, uint32_t G, int j) {
+  const uint64_t rho = uint64_t(blockIdx.x) * kRowThreads + threadIdx.x;
+  const uint64_t* U = T + uint64_t(j + 1) * N;
+  uint64_t* V = T + uint64_t(j) * N;
+  if (rho < G && rho < N) {
+    uint64_t run = 0;
+    for (uint64_t x = rho; x < N; x += G) {
+      run = sat_add_u64(run, U[x]);
+      V[x] = run;
+    }
+  }
+}
+
+// Row j from row j + 1, one workgroup per residue class (longer classes).
+__global__ __launch_bounds__(kRowThreads) void k_count_row_long(uint64_t* __restrict__ T,
+                                                                uint32_t N, uint32_t G, int j) {
+  __shared__ uint64_t wsum[kRowThreads / kWave];
+  const uint32_t rho = blockIdx.x;
+  const uint64_t L = (uint64_t(N) - rho + G - 1) / G;  // entries of the class
+  const uint64_t* U = T + uint64_t(j + 1) * N;
+  uint64_t* V = T + uint64_t(j) * N;
+  constexpr uint32_t kItems = 4;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < L; base += uint64_t(kRowThreads) * kItems) {
+    const uint64_t t0 = base + uint64_t(threadIdx.x) * kItems;
+    uint64_t v[kItems];
+    uint64_t local = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+      v[q] = (t0 + q < L) ? U[rho + (t0 + q) * G] : 0;
+      local = sat_add_u64(local, v[q]);
+    }
+    // Exclusive scan of the threads' sums: in the wavefront, then across.
+    uint64_t incl = local;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint64_t y = __shfl_up(incl, off, kWave);
+      if (lane >= off) incl = sat_add_u64(incl, y);
+    }
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    uint64_t before = carry, total = carry;
+    for (int w = 0; w < kRowThreads / kWave; ++w) {
+      if (w < wave) before = sat_add_u64(before, wsum[w]);
+      total = sat_add_u64(total, wsum[w]);
+    }
+    __syncthreads();
+    const uint64_t prev = __shfl_up(incl, 1, kWave);  // the previous lane's inclusive sum
+    uint64_t run = sat_add_u64(before, lane ? prev : 0);
+#pragma unroll
+    for (uint32_t q = 0; q < kItems; ++q) {
+      if (t0 + q < L) {
+        run = sat_add_u64(run, v[q]);
+        V[rho + (t0 + q) * G] = run;
+      }
+    }
+    carry = total;
+  }
 }
 
 // Batched forms: workgroup b computes the table of jobs[first + b], and
@@ -313,7 +411,23 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   if (N <= kCtLdsMax) {
     hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
   } else {
-    hipLaunchKernelGGL(k_count_table, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
+    const uint32_t ib = uint32_t(std::min<uint64_t>((uint64_t(N) + kRowThreads - 1) / kRowThreads,
+                                                    4096));
+    hipLaunchKernelGGL(k_count_init, dim3(ib), dim3(kRowThreads), 0, s, table, N, d);
+    for (int j = d - 1; j >= 0; --j) {
+      const uint32_t G = gs.g[j];
+      const uint64_t classes = std::min<uint64_t>(G, N);
+      const uint64_t len = (uint64_t(N) + G - 1) / G;
+      if (len <= kShortClass) {
+        hipLaunchKernelGGL(k_count_row_short, dim3(uint32_t((classes + kRowThreads - 1) / kRowThreads)),
+                           dim3(kRowThreads), 0, s, table, N, G, j);
+      } else {
+        hipLaunchKernelGGL(k_count_row_long, dim3(uint32_t(classes)), dim3(kRowThreads), 0, s,
+                           table, N, G, j);
+      }
+    }
+    if (sums)
+      hipLaunchKernelGGL(k_count_stats, dim3(d + 1), dim3(kCtThreads), 0, s, table, N, d, sums);
   }
   return hipGetLastError();
 }
