@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "zset.h"
@@ -44,6 +45,7 @@ namespace {
 constexpr int kWalkThreads = 256;
 constexpr uint64_t kWantPrefixes = 1 << 17;   // lanes the work is spread over
 constexpr uint64_t kMaxPrefixes = 1 << 22;    // host refinement bound
+constexpr int kSplitThreads = 8;              // host threads that refine records
 
 struct WalkArgs {
   Gens g;
@@ -182,48 +184,92 @@ Prefix full_prefix(int m, uint64_t x, const uint32_t* a, const uint32_t* g, int 
   return p;
 }
 
+// One split: a range into two halves of about equal estimated work (the
+// volume is a power of the remainder), a single value into the next
+// coordinate's range.  Pushes the parts in reverse order onto `stack`.
+void split_record(Prefix p, const uint32_t* g, int d, std::vector<Prefix>* stack) {
+  if (p.hi > p.lo) {
+    uint64_t mid = p.lo + (p.hi - p.lo) / 2;
+    if (p.m < d - 2) {
+      const double k = double(d - 2 - p.m);
+      const double y0 = double(p.x) - double(p.lo) * g[p.m];
+      const double y1 = std::max(0.0, double(p.x) - double(p.hi + 1) * g[p.m]);
+      const double ym = std::pow(0.5 * (std::pow(y0, k) + std::pow(y1, k)), 1.0 / k);
+      const double cut = (double(p.x) - ym) / double(g[p.m]);
+      if (cut >= double(p.lo) && cut < double(p.hi)) mid = uint64_t(cut);
+    }
+    Prefix l = p;
+    l.hi = mid;
+    p.lo = mid + 1;
+    stack->push_back(std::move(p));  // the upper half is taken after the lower
+    stack->push_back(std::move(l));
+  } else {
+    p.a[p.m] = uint32_t(p.lo);
+    stack->push_back(full_prefix(p.m + 1, p.x - p.lo * g[p.m], p.a, g, d));
+  }
+}
+
+// The records below one seed, depth first, in order, at most `cap` of them.
+void split_below(Prefix seed, const uint32_t* g, int d, uint32_t step, double share,
+                 uint64_t cap, std::vector<Prefix>* out) {
+  std::vector<Prefix> stack;
+  stack.push_back(std::move(seed));
+  while (!stack.empty()) {
+    Prefix p = std::move(stack.back());
+    stack.pop_back();
+    if (p.m >= d - 1 || out->size() + stack.size() + 2 > cap ||
+        walk_estimate(p, g, d, step) <= share) {
+      out->push_back(std::move(p));
+      continue;
+    }
+    split_record(std::move(p), g, d, &stack);
+  }
+}
+
 // Prefix records in lexicographic order: from the whole range, every record
 // whose estimate exceeds twice the share of one of kWantPrefixes lanes (and
 // one unit) is split -- a range of a_{m+1} in two halves of about equal work,
 // a single value into the next coordinate's range -- until the list holds
 // kMaxPrefixes.  This is the static counterpart of re-splitting the heaviest
 // remaining lexicographic range.  Depth first with an explicit stack, so the
-// records come out in order in one pass.
+// records come out in order in one pass per seed.
+// The first splits, heaviest record first, make up to kSplitThreads seeds in
+// order; each is refined below by its own host thread and the lists are
+// concatenated in seed order.
 std::vector<Prefix> make_prefixes(uint64_t n, const uint32_t* g, int d, uint32_t step) {
   Prefix root = full_prefix(0, n, nullptr, g, d);
   const double share =
       std::max(1.0, 2.0 * walk_estimate(root, g, d, step) / double(kWantPrefixes));
-  std::vector<Prefix> out, stack;
-  stack.push_back(std::move(root));
-  while (!stack.empty()) {
-    Prefix p = std::move(stack.back());
-    stack.pop_back();
-    if (p.m >= d - 1 || out.size() + stack.size() + 2 > kMaxPrefixes ||
-        walk_estimate(p, g, d, step) <= share) {
-      out.push_back(std::move(p));
-      continue;
-    }
-    if (p.hi > p.lo) {
-      // Equal-work split point: the volume is a power of the remainder.
-      uint64_t mid = p.lo + (p.hi - p.lo) / 2;
-      if (p.m < d - 2) {
-        const double k = double(d - 2 - p.m);
-        const double y0 = double(p.x) - double(p.lo) * g[p.m];
-        const double y1 = std::max(0.0, double(p.x) - double(p.hi + 1) * g[p.m]);
-        const double ym = std::pow(0.5 * (std::pow(y0, k) + std::pow(y1, k)), 1.0 / k);
-        const double cut = (double(p.x) - ym) / double(g[p.m]);
-        if (cut >= double(p.lo) && cut < double(p.hi)) mid = uint64_t(cut);
+  std::vector<Prefix> seeds{std::move(root)};
+  while (seeds.size() < size_t(kSplitThreads)) {
+    size_t heavy = 0;
+    double most = -1;
+    for (size_t i = 0; i < seeds.size(); ++i) {
+      const double e = seeds[i].m >= d - 1 ? -1 : walk_estimate(seeds[i], g, d, step);
+      if (e > most) {
+        most = e;
+        heavy = i;
       }
-      Prefix l = p;
-      l.hi = mid;
-      p.lo = mid + 1;
-      stack.push_back(std::move(p));  // the upper half is taken after the lower
-      stack.push_back(std::move(l));
-    } else {
-      p.a[p.m] = uint32_t(p.lo);
-      stack.push_back(full_prefix(p.m + 1, p.x - p.lo * g[p.m], p.a, g, d));
     }
+    if (most <= share) break;
+    std::vector<Prefix> parts;
+    split_record(seeds[heavy], g, d, &parts);
+    std::reverse(parts.begin(), parts.end());
+    seeds.erase(seeds.begin() + long(heavy));
+    seeds.insert(seeds.begin() + long(heavy), parts.begin(), parts.end());
   }
+  std::vector<std::vector<Prefix>> lists(seeds.size());
+  const uint64_t cap = kMaxPrefixes / seeds.size();
+  std::vector<std::thread> pool;
+  for (size_t i = 0; i < seeds.size(); ++i)
+    pool.emplace_back(split_below, seeds[i], g, d, step, share, cap, &lists[i]);
+  for (auto& t : pool) t.join();
+  std::vector<Prefix> out;
+  size_t total = 0;
+  for (const auto& l : lists) total += l.size();
+  out.reserve(total);
+  for (auto& l : lists) out.insert(out.end(), std::make_move_iterator(l.begin()),
+                                   std::make_move_iterator(l.end()));
   return out;
 }
 
