@@ -263,28 +263,44 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
 // a launch scans every class at once: classes of at most kShortClass entries
 // one per thread, longer ones one per workgroup (a blocked scan in tiles of
 // 1024 entries).  Row sums and maxima follow in one launch, a workgroup per
-// row.
+// chunk of 32768 entries of each row.
 constexpr int kRowThreads = 256;
 constexpr uint32_t kShortClass = 64;
 
-// Row d = [x == 0].
+// Row d = [x == 0]; the sums and maxima start clear (the stats launch adds
+// into them).
 __global__ __launch_bounds__(kRowThreads) void k_count_init(uint64_t* __restrict__ T, uint32_t N,
-                                                            int d) {
+                                                            int d, uint64_t* __restrict__ sums) {
   const uint64_t i = uint64_t(blockIdx.x) * kRowThreads + threadIdx.x;
   uint64_t* last = T + uint64_t(d) * N;
   for (uint64_t x = i; x < N; x += uint64_t(gridDim.x) * kRowThreads) last[x] = (x == 0) ? 1 : 0;
+  if (sums && i < uint64_t(2 * d + 3)) sums[i] = 0;
 }
 
-// Row sums and maxima, one workgroup per row j = 0..d (no atomics), and
-// |Z(n)| = C[0][n].
+__device__ inline void sat_atomic_add(uint64_t* p, uint64_t v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  unsigned long long old = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const unsigned long long seen = atomicCAS(q, old, sat_add_u64(old, v));
+    if (seen == old) break;
+    old = seen;
+  }
+}
+
+// Row sums and maxima: workgroup (c, j) reduces chunk c of row j and adds its
+// result into sums[j] and sums[d + 2 + j] (a saturating compare-and-swap and
+// an atomic maximum, a few dozen per word); also |Z(n)| = C[0][n].
+constexpr uint32_t kStatsChunk = 1 << 15;
 __global__ __launch_bounds__(kCtThreads) void k_count_stats(const uint64_t* __restrict__ T,
                                                             uint32_t N, int d,
                                                             uint64_t* __restrict__ sums) {
   __shared__ uint64_t red[kCtThreads / kWave];
-  const int j = blockIdx.x;
+  const int j = blockIdx.y;
   const uint64_t* V = T + uint64_t(j) * N;
+  const uint64_t lo = uint64_t(blockIdx.x) * kStatsChunk;
+  const uint64_t hi = std::min<uint64_t>(N, lo + kStatsChunk);
   uint64_t acc = 0, mx = 0;
-  for (uint64_t x = threadIdx.x; x < N; x += kCtThreads) {
+  for (uint64_t x = lo + threadIdx.x; x < hi; x += kCtThreads) {
     const uint64_t v = V[x];
     acc = sat_add_u64(acc, v);
     mx = v > mx ? v : mx;
@@ -292,9 +308,10 @@ __global__ __launch_bounds__(kCtThreads) void k_count_stats(const uint64_t* __re
   const uint64_t total = block_sum_u64(acc, red);
   const uint64_t top = block_max_u64(mx, red);
   if (threadIdx.x == 0) {
-    sums[j] = total;
-    sums[d + 2 + j] = top;
-    if (j == 0) sums[d + 1] = V[N - 1];
+    sat_atomic_add(sums + j, total);
+    atomicMax(reinterpret_cast<unsigned long long*>(sums + d + 2 + j),
+              static_cast<unsigned long long>(top));
+    if (j == 0 && hi == N) sums[d + 1] = V[N - 1];
   }
 }
 
@@ -413,7 +430,7 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   } else {
     const uint32_t ib = uint32_t(std::min<uint64_t>((uint64_t(N) + kRowThreads - 1) / kRowThreads,
                                                     4096));
-    hipLaunchKernelGGL(k_count_init, dim3(ib), dim3(kRowThreads), 0, s, table, N, d);
+    hipLaunchKernelGGL(k_count_init, dim3(ib), dim3(kRowThreads), 0, s, table, N, d, sums);
     for (int j = d - 1; j >= 0; --j) {
       const uint32_t G = gs.g[j];
       const uint64_t classes = std::min<uint64_t>(G, N);
@@ -426,8 +443,11 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
                            table, N, G, j);
       }
     }
-    if (sums)
-      hipLaunchKernelGGL(k_count_stats, dim3(d + 1), dim3(kCtThreads), 0, s, table, N, d, sums);
+    if (sums) {
+      const uint32_t chunks = uint32_t((uint64_t(N) + kStatsChunk - 1) / kStatsChunk);
+      hipLaunchKernelGGL(k_count_stats, dim3(chunks, uint32_t(d + 1)), dim3(kCtThreads), 0, s,
+                         table, N, d, sums);
+    }
   }
   return hipGetLastError();
 }
