@@ -10,8 +10,13 @@
  * It follows the paper's parallel bounded lexicographic enumeration with
  * low-dimension tabulation (Section 3, Alg 3.2): workers own bounded slices of
  * the output, step over the leading coordinates, and copy whole blocks of the
- * trailing k coordinates from a memo built on the GPU by the dynamic recurrence
- * of Lemma 2.3 run in elementwise batches (Section 2.2, Alg 2.9).
+ * trailing k coordinates from a memo built on the GPU.  zset_memo_build builds
+ * it by the dynamic recurrence of Lemma 2.3 run in elementwise batches
+ * (Section 2.2, Alg 2.9).  Inside zset_enumerate_ex, memos of one or two
+ * coordinates are built from the recurrence's closed solution instead (the
+ * same lists, every element independent), and memos of three or more by the
+ * recurrence; ZSET_MEMO_PATH=chain in the environment keeps the recurrence
+ * for two coordinates too.
  *
  * Conventions shared by every entry point:
  *   - Pointers documented as "host" are read before the call returns and are

@@ -6,8 +6,7 @@ calls it, and it shares no code with the HIP path.
 
 The arithmetic lives in ``zset_oracle.c`` (plain C, built with gcc into
 ``liboracle.so`` next to it); this module only marshals numpy arrays through
-ctypes.  ``method.py`` holds pure-Python transcriptions of the paper's own
-algorithms (Alg 2.8, Alg 2.9, Alg 3.1, Alg 3.2) for small cross-checks.
+ctypes.
 
 Definition followed (paper, Section 1): Z(n; g) = {a in N^d : sum a_i g_i = n},
 rows of d uint32 values, strictly ascending in lexicographic order.

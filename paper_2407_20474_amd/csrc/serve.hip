@@ -13,8 +13,8 @@
 // host synchronisation.  Queries run on `slots` streams at once (continuous
 // batching): a dispatcher thread admits waiting queries in arrival order as a
 // slot and room in the output arena become free, launches them, watches their
-// completion events and stamps submit / admit / done times on the host's
-// steady clock.  The rows of a query are the bytes zset_enumerate_ex writes
+// completion flags (pinned host words that the last kernel of a query writes)
+// and stamps submit / admit / done times on the host's steady clock.  The rows of a query are the bytes zset_enumerate_ex writes
 // for it alone: the kernels and their arguments are the same, only the memo
 // covers more elements.
 #include <algorithm>
@@ -246,7 +246,11 @@ void dispatcher(zset_server_s* S, int id, int nth) {
           busy = true;
           continue;
         }
-        if (q == hipSuccess) q = hipErrorUnknown;  // stream done, flag never written
+        // The stream is done: the flag was written before it drained unless
+        // the query failed, so it is read again now that the stream is idle
+        // (it may have landed between the first read and the query).
+        if (q == hipSuccess && __atomic_load_n(sl.flag, __ATOMIC_ACQUIRE) != sl.seq)
+          q = hipErrorUnknown;  // stream done, flag never written
       }
       Request& r = S->reqs[sl.ticket];
       r.t_done = now_us(S->t0);

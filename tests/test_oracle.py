@@ -13,7 +13,6 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import method
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -251,14 +250,6 @@ def test_dynamic_memo_matches_the_definition():
         assert dt >= 0
 
 
-def test_dynamic_memo_against_alg_2_8_reversed():
-    for n, g in tiny_cases(12, 40, dmax=4, nmax=40):
-        off, rows = oracle.memo_dynamic(g, n + 1)
-        F = method.lex_lists_up_to(n, g)
-        for m in range(n + 1):
-            assert as_tuples(rows[int(off[m]):int(off[m + 1])]) == F[m][::-1], (g, m)
-
-
 def test_threaded_enumeration_matches():
     n, g = 1500, [7, 11, 13, 17]
     full = oracle.enumerate_rows(n, g)
@@ -304,19 +295,59 @@ def test_checksum_is_order_sensitive_and_splittable():
 
 
 # --------------------------------------------------------------------------
-# The paper's own algorithms reach the same lists
+# The identities the method rests on, checked on the oracle's own sets
 # --------------------------------------------------------------------------
 
-def test_alg_2_8_lists_are_descending_factorization_sets():
+def incr(a, i):
+    """incr_i (Section 2): add one to coordinate i (0-based)."""
+    b = list(a)
+    b[i] += 1
+    return tuple(b)
+
+
+def zero_left_of(a, i):
+    """a lies in Z_{>=i}: every coordinate left of i is zero."""
+    return all(x == 0 for x in a[:i])
+
+
+def sets_up_to(n, g):
+    """Z(m; g) for m = 0..n from the oracle's enumerator, ascending tuples."""
+    return [as_tuples(oracle.enumerate_rows(m, g)) for m in range(n + 1)]
+
+
+def test_disjoint_recurrence_in_lex_order():
+    # Lemma 2.3 with the order of Lemma 2.6: in descending order Z(m) is the
+    # concatenation over i = 1..d of incr_i(Z_{>=i}(m - g_i)), the blocks
+    # being exactly the rows whose first nonzero coordinate is i.  The
+    # ascending form reverses both the blocks and the rows inside them.
     for n, g in tiny_cases(6, 60, dmax=4, nmax=40):
-        F = method.lex_lists_up_to(n, g)
-        for m in range(n + 1):
-            assert F[m] == brute(m, g)[::-1], (n, g, m)
+        Z = sets_up_to(n, g)
+        for m in range(1, n + 1):
+            desc = []
+            for i in range(len(g)):
+                if m - g[i] >= 0:
+                    src = [a for a in Z[m - g[i]][::-1] if zero_left_of(a, i)]
+                    desc.extend(incr(a, i) for a in src)
+            assert desc == Z[m][::-1], (n, g, m)
 
 
-def test_alg_2_9_matches_alg_2_8():
+def test_saved_cardinalities_locate_every_block():
+    # Section 2.3: |Z_{=i}(m)| = |Z_{>=i}(m - g_i)|, and in descending order
+    # Z_{>=i}(m) is one contiguous run of Z(m) that starts after the rows of
+    # Z_{=j}(m), j < i.  (Z(0) = {0}: |Z_{>=i}(0)| = 1 for every i.)
     for n, g in tiny_cases(7, 60, dmax=4, nmax=40):
-        assert method.lex_lists_factorizationwise(n, g) == method.lex_lists_up_to(n, g)
+        Z = sets_up_to(n, g)
+        d = len(g)
+        for m in range(n + 1):
+            desc = Z[m][::-1]
+            eq = [sum(1 for a in desc if zero_left_of(a, i) and a[i] > 0) for i in range(d)]
+            for i in range(d):
+                if m >= 1:
+                    src = Z[m - g[i]] if m - g[i] >= 0 else []
+                    assert eq[i] == sum(1 for a in src if zero_left_of(a, i)), (g, m, i)
+                start = sum(eq[:i])
+                run = [a for a in desc if zero_left_of(a, i)]
+                assert desc[start:start + len(run)] == run, (g, m, i)
 
 
 def test_ascending_memo_blocks_are_prefixes():
@@ -333,27 +364,40 @@ def test_ascending_memo_blocks_are_prefixes():
                 src = m - h[i]
                 if src < 0:
                     continue
-                ge = [r for r in Z[src] if all(r[j] == 0 for j in range(i))]
+                ge = [r for r in Z[src] if zero_left_of(r, i)]
                 assert Z[src][:len(ge)] == ge
-                built.extend(method.incr(r, i) for r in ge)
+                built.extend(incr(r, i) for r in ge)
             assert built == Z[m], (h, m)
 
 
-def test_alg_3_1_stream_matches_oracle():
-    for n, g in tiny_cases(8, 150, dmax=5, nmax=45):
-        s = method.next_candidate_stream(n, g)
-        assert s[::-1] == as_tuples(oracle.enumerate_rows(n, g)), (n, g)
-
-
-def test_alg_3_2_stream_matches_oracle_for_every_memo_dim_and_top():
+def test_tabulation_blocks_are_contiguous_memo_lists():
+    # Low-dimension tabulation (Section 3.1): once the leading d - k
+    # coordinates are fixed, the rows with that prefix form one contiguous
+    # run of the ordered output, and that run is the prefix followed by the
+    # list Z(p; g_{d-k+1..d}) of p = n - phi(prefix), in the same order.  With a
+    # memo that stops at top, runs with p >= top are the same rows obtained
+    # without it.
     rng = np.random.default_rng(9)
     for n, g in tiny_cases(10, 120, dmax=5, nmax=45):
         d = len(g)
-        want = as_tuples(oracle.enumerate_rows(n, g))
+        rows = as_tuples(oracle.enumerate_rows(n, g))
         for k in range(1, d):
-            h = g[d - k:]
-            for top in {n + 1, int(rng.integers(0, n + 2))}:
-                off, rows = oracle.memo(h, max(top, 1))
-                memo = [as_tuples(rows[int(off[p]):int(off[p + 1])])[::-1] for p in range(top)]
-                s = method.next_candidate_stream(n, g, memo, k, top)
-                assert s[::-1] == want, (n, g, k, top)
+            h, lead = g[d - k:], d - k
+            top = int(rng.integers(1, n + 2))
+            off, mrows = oracle.memo(h, max(top, 1))
+            seen = set()
+            i = 0
+            while i < len(rows):
+                pre = rows[i][:lead]
+                assert pre not in seen, (n, g, k)  # each prefix occurs in one run
+                seen.add(pre)
+                j = i
+                while j < len(rows) and rows[j][:lead] == pre:
+                    j += 1
+                p = n - sum(a * b for a, b in zip(pre, g))
+                if p < top:
+                    lst = as_tuples(mrows[int(off[p]):int(off[p + 1])])
+                else:
+                    lst = as_tuples(oracle.enumerate_rows(p, h))
+                assert [r[lead:] for r in rows[i:j]] == lst, (n, g, k, pre)
+                i = j
