@@ -43,7 +43,9 @@ def build(force: bool = False) -> str:
 def _lib():
     global _lib_handle
     if _lib_handle is None:
-        lib = ctypes.CDLL(build())
+        # ZSET_ORACLE_LIB names another build of zset_oracle.c (the sanitizer
+        # build of the CPU tests).
+        lib = ctypes.CDLL(os.environ.get("ZSET_ORACLE_LIB") or build())
         lib.oracle_count.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, _u64p]
         lib.oracle_count_table.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, _u64p]
         lib.oracle_enumerate.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, _u32p,

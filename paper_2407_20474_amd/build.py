@@ -39,14 +39,17 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     """Compile all HIP sources and link libzset.so; returns its path."""
+    from concurrent.futures import ThreadPoolExecutor
     with tempfile.TemporaryDirectory(prefix="zset_build_") as tmp:
-        objs = []
-        for src in SOURCES:
-            obj = os.path.join(tmp, src.replace(".hip", ".o"))
-            out = _run([HIPCC, *CFLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-            if verbose and out.strip():
-                print(out)
-            objs.append(obj)
+        objs = [os.path.join(tmp, src.replace(".hip", ".o")) for src in SOURCES]
+        jobs = min(len(SOURCES), max(1, (os.cpu_count() or 1)))
+        with ThreadPoolExecutor(max_workers=jobs) as ex:
+            outs = list(ex.map(lambda so: _run([HIPCC, *CFLAGS, "-c", os.path.join(CSRC, so[0]),
+                                                "-o", so[1]]), zip(SOURCES, objs)))
+        if verbose:
+            for out in outs:
+                if out.strip():
+                    print(out)
         tmp_lib = os.path.join(tmp, "libzset.so")
         _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-o", tmp_lib, *objs])
         _install(tmp_lib)

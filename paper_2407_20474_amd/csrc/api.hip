@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -297,9 +298,12 @@ int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
 // ZSET_MEMO_PATH=global / window forces those paths (tests); =chain (and
 // either of those) keeps the recurrence for k = 2 memos, which the single path
 // otherwise builds in closed form.
-zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint64_t* off,
+// `srcw_for(bytes, &ptr)` provides the global schedule's source table.
+zset_status build_memo_rows(const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint64_t rowmax,
-                            uint32_t* nat, hipStream_t s) {
+                            uint32_t* nat, int* err, size_t lds,
+                            const std::function<zset_status(size_t, uint64_t**)>& srcw_for,
+                            hipStream_t s) {
   if (k == 1) {
     if (R != (top - 1) / h[0] + 1) return fail(ZSET_EDEVICE, "memo row count disagrees (k = 1)");
     ZSET_HIP(launch_memo_k1(h[0], top, R, nat, off, s));
@@ -316,8 +320,6 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint
   const uint32_t step = std::min<uint32_t>(b, kWave);
   const uint64_t Wl = uint64_t(hmax) + step;
   const uint32_t W = Wl < (uint64_t(1) << 30) ? next_pow2(uint32_t(Wl)) : 0;
-  int* err = reinterpret_cast<int*>(c->misc.p);
-  const size_t lds = size_t(max_lds_bytes(c));
   if (!force_global && !force_window && W != 0 && R < (uint64_t(1) << 30) &&
       memo_wave_lds_bytes(k, R, W) <= lds) {
     ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, R, nat, off, err, s));
@@ -334,11 +336,91 @@ zset_status build_memo_rows(Ctx* c, const uint32_t* h, int k, uint64_t top, uint
     }
   }
   ZSET_HIP(launch_exclusive_scan(ge, top, off, s));
-  zset_status st = ensure(c->srcw, size_t(R) * sizeof(uint64_t));
+  uint64_t* srcw = nullptr;
+  zset_status st = srcw_for(size_t(R) * sizeof(uint64_t), &srcw);
   if (st != ZSET_OK) return st;
-  ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride,
-                              reinterpret_cast<uint64_t*>(c->srcw.p), nat, err, s));
+  ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride, srcw, nat, err, s));
   return ZSET_OK;
+}
+
+// Two-coordinate memos in closed form, unless ZSET_MEMO_PATH asks for one of
+// the recurrence's schedules.
+bool memo2_closed_form() {
+  const char* path = std::getenv("ZSET_MEMO_PATH");
+  return !(path && (std::strcmp(path, "chain") == 0 || std::strcmp(path, "global") == 0 ||
+                    std::strcmp(path, "window") == 0));
+}
+
+// The global schedule's source table from the context's grow-only buffer.
+std::function<zset_status(size_t, uint64_t**)> ctx_srcw(Ctx* c) {
+  return [c](size_t bytes, uint64_t** p) {
+    zset_status st = ensure(c->srcw, bytes);
+    *p = reinterpret_cast<uint64_t*>(c->srcw.p);
+    return st;
+  };
+}
+
+// Automatic memo dimension: the largest k whose memo stays small beside the
+// output (at most 1/16 of the rows and 512 MiB); k = 1 always qualifies in
+// practice.  sums[j] = rows of the count table's row j over x <= n.
+int auto_memo_dim(const uint64_t* sums, int d, uint64_t total) {
+  for (int kk = d - 1; kk >= 1; --kk) {
+    const uint64_t R = sums[d - kk];
+    if (R != ~uint64_t(0) && R <= std::max<uint64_t>(uint64_t(1) << 16, total / 16) &&
+        R * (kk + 1) * 4 <= (uint64_t(512) << 20))
+      return kk;
+  }
+  return 1;
+}
+
+// The write pass's descriptor for memo dimension k: generators, coordinates
+// fixed by a slice start (U), the division by g_U and the staging ring; for
+// k >= 1 also the leaf-order row format and what the write pass keeps in LDS
+// (packed memo rows, segment counts and class ends), decided from the row
+// sums alone.  Returns the leaf layout's uint32 words.
+uint64_t init_params(EnumParams& P, uint64_t n, const uint32_t* gens, int d, int k,
+                     uint64_t total, const uint64_t* sums, const uint64_t* T, int* err,
+                     uint64_t* checksum, uint32_t* out, size_t lds_max) {
+  const uint64_t N = n + 1;
+  const int L = d - std::max(k, 1);
+  const int U = (k == 0) ? d - 1 : L - 1;
+  const uint32_t G = gens[U];
+  std::memset(&P, 0, sizeof P);
+  for (int i = 0; i < d; ++i) P.g.g[i] = gens[i];
+  P.n = uint32_t(n);
+  P.d = d;
+  P.U = U;
+  P.k = k;
+  P.total = total;
+  P.table = T;
+  P.table_stride = N;
+  P.err = err;
+  P.checksum = checksum;
+  P.out = out;
+  P.dG = DivMod32::make(G);
+  P.ring = d <= 16 ? 128 : 64;
+  P.flush = P.ring / 2;
+  P.max_tiles = kMinTileStates;  // grown by size_write_pass to what LDS leaves
+  if (k < 1) return 0;
+  const uint64_t Rn = sums[L];  // rows of Memo[p] over p <= n
+  leaf_format(P, n, gens, U, k);
+  P.nclass = uint32_t(std::min<uint64_t>(G, N));
+  const char* lds_env = std::getenv("ZSET_MEMO_LDS");
+  const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
+  if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
+  if (P.pack != 0) {
+    P.memo_words = Rn * uint64_t(P.pack);
+    if (write_lds_bytes(P) > lds_max) P.pack = 0;
+  }
+  if (P.pack == 0) P.memo_words = 0;
+  // Segment counts and class ends in LDS too when every value fits 32 bits
+  // (their sum over x <= n bounds each) and the space is there.
+  if (!lds_off && sums[U] < (uint64_t(1) << 32) && Rn < (uint64_t(1) << 32)) {
+    P.lds_cnt = 1;
+    if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
+  }
+  P.leaf_rows = Rn;
+  return P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
 }
 
 }  // namespace
@@ -357,7 +439,11 @@ void zset_default_opts(zset_opts* o) {
 }
 
 const char* zset_strerror(zset_status s) {
-  switch (s) {
+  // A caller may pass any int (the C ABI): read the bits as an int, since a
+  // value outside the enumerators' range is not a valid zset_status in C++.
+  int v = 0;
+  std::memcpy(&v, &s, sizeof v);
+  switch (v) {
     case ZSET_OK: return "success";
     case ZSET_EINVAL: return "invalid argument";
     case ZSET_EOVERFLOW: return "count overflows 64 bits";
@@ -459,7 +545,8 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   int* err = reinterpret_cast<int*>(c->misc.p);
   e = hipMemsetAsync(err, 0, sizeof(int), s);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync"));
-  st = build_memo_rows(c, m->h, k, top, m->off, CT, top, R, rowmax, m->nat, s);
+  st = build_memo_rows(m->h, k, top, m->off, CT, top, R, rowmax, m->nat, err,
+                       size_t(max_lds_bytes(c)), ctx_srcw(c), s);
   if (st != ZSET_OK) return cleanup(st);
   e = hipMemcpyAsync(c->pinned, err, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -622,17 +709,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if (d == 1) {
     k = 0;
   } else if (k < 0) {
-    // Largest k whose memo stays small beside the output (at most 1/16 of
-    // the rows and 512 MiB); k = 1 always qualifies in practice.
-    k = 1;
-    for (int kk = d - 1; kk >= 1; --kk) {
-      const uint64_t R = sums[d - kk];
-      if (R != ~uint64_t(0) && R <= std::max<uint64_t>(uint64_t(1) << 16, total / 16) &&
-          R * (kk + 1) * 4 <= (uint64_t(512) << 20)) {
-        k = kk;
-        break;
-      }
-    }
+    k = auto_memo_dim(sums, d, total);
   }
 
   double memo_us = 0, plan_us = 0, write_us = 0;
@@ -649,55 +726,21 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     const int U = (k == 0) ? d - 1 : L - 1;
     const uint32_t G = gens[U];
     EnumParams P;
-    std::memset(&P, 0, sizeof P);
-    for (int i = 0; i < d; ++i) P.g.g[i] = gens[i];
-    P.n = uint32_t(n);
-    P.d = d;
-    P.U = U;
-    P.k = k;
-    P.total = total;
-    P.table = T;
-    P.table_stride = N;
-    P.err = err;
-    P.checksum = misc + kMiscSum;
-    P.out = out;
-    P.dG = DivMod32::make(G);
-    P.ring = d <= 16 ? 128 : 64;
-    P.flush = P.ring / 2;
-    P.max_tiles = kMinTileStates;  // grown by size_write_pass to what LDS leaves
-
     // 3. Leaf-order row format and what the write pass keeps in LDS (from the
     // row sums alone), slices, class ends and the slice plan.  None of these
     // needs the memo's rows, so while the recurrence runs on the side stream
     // they run beside it.
+    const uint64_t leaf_words = init_params(P, n, gens, d, k, total, sums, T, err,
+                                            misc + kMiscSum, out,
+                                            size_t(write_lds_budget(c->device)));
     const uint64_t Rn = k >= 1 ? sums[L] : 0;  // rows of Memo[p] over p <= n
-    uint64_t leaf_words = 0;
     if (k >= 1) {
       memo_rows = Rn;
-      leaf_format(P, n, gens, U, k);
-      P.nclass = uint32_t(std::min<uint64_t>(G, N));
-      const char* lds_env = std::getenv("ZSET_MEMO_LDS");
-      const bool lds_off = lds_env && std::strcmp(lds_env, "0") == 0;
-      const size_t lds_max = size_t(write_lds_budget(c->device));
-      if (lds_off || Rn >= (uint64_t(1) << 32)) P.pack = 0;
-      if (P.pack != 0) {
-        P.memo_words = Rn * uint64_t(P.pack);
-        if (write_lds_bytes(P) > lds_max) P.pack = 0;
-      }
-      if (P.pack == 0) P.memo_words = 0;
-      // Segment counts and class ends in LDS too when every value fits 32 bits
-      // (their sum over x <= n bounds each) and the space is there.
-      if (!lds_off && sums[U] < (uint64_t(1) << 32) && Rn < (uint64_t(1) << 32)) {
-        P.lds_cnt = 1;
-        if (write_lds_bytes(P) > lds_max) P.lds_cnt = 0;
-      }
-      leaf_words = P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
       const uint64_t nclass_max = std::min<uint64_t>(G, N);
       if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
       if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
       P.endc = reinterpret_cast<uint64_t*>(c->endc.p);
       P.leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
-      P.leaf_rows = Rn;
       memo_bytes = leaf_words * 4;
     }
     // Slices: exact rank ranges, starts unranked on the device; about 128
@@ -740,18 +783,16 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
         if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
         uint64_t* o = reinterpret_cast<uint64_t*>(c->off.p);
-        const char* path = std::getenv("ZSET_MEMO_PATH");
-        const bool closed2 = k == 2 && !(path && (std::strcmp(path, "chain") == 0 ||
-                                                  std::strcmp(path, "global") == 0 ||
-                                                  std::strcmp(path, "window") == 0));
+        const bool closed2 = k == 2 && memo2_closed_form();
         if (closed2) {  // two coordinates: the closed form, element-parallel
           if ((st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
           ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn,
                                   reinterpret_cast<uint32_t*>(c->nat.p), o,
                                   reinterpret_cast<uint64_t*>(c->cnt2.p), s));
         } else {
-          st = build_memo_rows(c, gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
-                               reinterpret_cast<uint32_t*>(c->nat.p), s);
+          st = build_memo_rows(gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
+                               reinterpret_cast<uint32_t*>(c->nat.p), err,
+                               size_t(max_lds_bytes(c)), ctx_srcw(c), s);
           if (st != ZSET_OK) return st;
         }
         off = o;

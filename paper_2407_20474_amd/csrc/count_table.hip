@@ -17,6 +17,8 @@
 // tables: one launch per row over all workgroups, every residue class scanned
 // at once.  In a batch, each workgroup computes the table of one query.
 #include <algorithm>
+#include <cstdlib>
+#include <cstring>
 
 #include "zset_internal.h"
 
@@ -143,94 +145,126 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
   }
 }
 
-// The same table with the working row held in LDS (`buf`, N entries): each
-// row is transformed in place from row j+1 into row j by the three-phase
-// column scan, copied out with coalesced stores, and summed on the way.
+// The same table with the working row held in LDS (`buf`, N entries).  Row j
+// is row j+1 scanned down each residue class mod g_j in place: a class x =
+// r, r + g_j, r + 2 g_j, ... is one column of the row viewed as a matrix with
+// g_j columns.  Columns of at most kColWalk entries are walked by one thread
+// each (neighbouring threads take neighbouring columns).  Longer columns go
+// to one wavefront each: lane l takes a run of E consecutive entries of the
+// column, scans it in registers, and a wave-wide inclusive scan of the run
+// totals (DPP, no LDS round trip) gives each run its carry; E is odd so that
+// the lanes' runs fall in different LDS banks, and a column longer than 64 E
+// takes several passes with a running carry.  Between rows the workgroup
+// synchronises on LDS only: the row's global copy-out need not complete before
+// the next row starts.  Row sums and maxima are reduced per wavefront as the
+// row is copied and combined once at the end.
 constexpr uint32_t kCtLdsMax = 16384;
+constexpr uint32_t kColWalk = 32;
+constexpr uint32_t kColRun = 15;  // longest run per lane (odd)
 
-__device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint32_t* gs, int d,
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// One DPP step on a 64-bit value (lanes outside the pattern read 0).
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ inline uint64_t dpp_u64(uint64_t v) {
+  const uint32_t lo = uint32_t(
+      __builtin_amdgcn_update_dpp(0, int(uint32_t(v)), CTRL, ROW_MASK, 0xf, false));
+  const uint32_t hi = uint32_t(
+      __builtin_amdgcn_update_dpp(0, int(uint32_t(v >> 32)), CTRL, ROW_MASK, 0xf, false));
+  return (uint64_t(hi) << 32) | lo;
+}
+
+// Saturating inclusive prefix sum over the 64 lanes: row_shr 1/2/4/8 inside
+// each 16-lane row, then row_bcast 15 and 31 across rows.
+__device__ inline uint64_t wave_incl_scan_sat_u64(uint64_t v) {
+  v = sat_add_u64(v, dpp_u64<0x111>(v));
+  v = sat_add_u64(v, dpp_u64<0x112>(v));
+  v = sat_add_u64(v, dpp_u64<0x114>(v));
+  v = sat_add_u64(v, dpp_u64<0x118>(v));
+  v = sat_add_u64(v, dpp_u64<0x142, 0xa>(v));
+  v = sat_add_u64(v, dpp_u64<0x143, 0xc>(v));
+  return v;
+}
+
+__device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N,
+                                                const uint32_t* gs, int d,
                                 uint64_t* __restrict__ sums, uint64_t* __restrict__ maxes,
                                 uint64_t* buf) {
-  __shared__ uint64_t part[kCtPart];
-  __shared__ uint64_t red[kCtThreads / kWave];
-  const int tid = threadIdx.x;
+  constexpr int kWaves = kCtThreads / kWave;
+  __shared__ uint64_t wsum[kMaxD][kWaves];
+  __shared__ uint64_t wmax[kMaxD][kWaves];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   for (uint32_t x = tid; x < N; x += kCtThreads) {
     buf[x] = (x == 0) ? 1 : 0;
     T[size_t(d) * N + x] = (x == 0) ? 1 : 0;
   }
   if (tid == 0 && sums) sums[d] = 1;
   if (tid == 0 && maxes) maxes[d] = 1;
-  __syncthreads();
+  lds_barrier();
 
   for (int j = d - 1; j >= 0; --j) {
     const uint32_t G = gs[j];
-    if (G < N) {
-      const uint32_t rows = (N + G - 1) / G;
-      for (uint32_t c0 = 0; c0 < G; c0 += kCtThreads) {
-        const uint32_t CG = (G - c0) < uint32_t(kCtThreads) ? (G - c0) : uint32_t(kCtThreads);
-        // At most 64 chunks per column, so that one wavefront scans a column's
-        // chunk sums in one pass.
-        uint32_t B = kCtPart / CG;
-        if (B > uint32_t(kWave)) B = kWave;
-        if (B > rows) B = rows;
-        if (B < 1) B = 1;
-        const uint32_t RB = (rows + B - 1) / B;
-        const uint32_t items = B * CG;
-        for (uint32_t it = tid; it < items; it += kCtThreads) {
-          const uint32_t b = it / CG, rho = c0 + it % CG;
-          const uint32_t t0 = b * RB;
-          const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
-          uint64_t acc = 0;
-#pragma unroll 8
-          for (uint32_t t = t0; t < t1; ++t) {
-            const uint32_t x = t * G + rho;
-            if (x < N) acc = sat_add_u64(acc, buf[x]);
-          }
-          part[it] = acc;
-        }
-        __syncthreads();
-        {
-          const int wave = tid / kWave, lane = tid & (kWave - 1);
-          for (uint32_t col = wave; col < CG; col += kCtThreads / kWave) {
-            const uint64_t v = uint32_t(lane) < B ? part[lane * CG + col] : 0;
-            uint64_t incl = v;
+    if (G < N) {  // else no x - g_j >= 0: row j equals row j + 1
+      const uint32_t L = (N + G - 1) / G;  // entries of the longest column
+      if (L <= kColWalk) {
+        for (uint32_t r = tid; r < G; r += kCtThreads) {
+          uint64_t run = 0;
+          for (uint32_t t0 = 0; t0 < L; t0 += 8) {
+            uint64_t v[8];
 #pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-              const uint64_t y = __shfl_up(incl, off, kWave);
-              if (lane >= off) incl = sat_add_u64(incl, y);
-            }
-            const uint64_t up = __shfl_up(incl, 1, kWave);
-            if (uint32_t(lane) < B) part[lane * CG + col] = lane ? up : 0;
-          }
-        }
-        __syncthreads();
-        for (uint32_t it = tid; it < items; it += kCtThreads) {
-          const uint32_t b = it / CG, rho = c0 + it % CG;
-          const uint32_t t0 = b * RB;
-          const uint32_t t1 = (t0 + RB < rows) ? t0 + RB : rows;
-          uint64_t run = part[it];
-          // Read a group of the chunk's entries before writing any back.
-          constexpr uint32_t kGroup = 8;
-          for (uint32_t t = t0; t < t1; t += kGroup) {
-            uint64_t v[kGroup];
-#pragma unroll
-            for (uint32_t q = 0; q < kGroup; ++q) {
-              const uint32_t x = (t + q) * G + rho;
-              v[q] = (t + q < t1 && x < N) ? buf[x] : 0;
+            for (uint32_t q = 0; q < 8; ++q) {
+              const uint32_t x = r + (t0 + q) * G;
+              v[q] = (t0 + q < L && x < N) ? buf[x] : 0;
             }
 #pragma unroll
-            for (uint32_t q = 0; q < kGroup; ++q) {
-              const uint32_t x = (t + q) * G + rho;
-              if (t + q < t1 && x < N) {
+            for (uint32_t q = 0; q < 8; ++q) {
+              const uint32_t x = r + (t0 + q) * G;
+              if (t0 + q < L && x < N) {
                 run = sat_add_u64(run, v[q]);
                 buf[x] = run;
               }
             }
           }
         }
-        __syncthreads();
+      } else {
+        uint32_t E = (L + kWave - 1) / kWave;
+        E = (E < kColRun ? E : kColRun) | 1u;
+        const uint32_t span = E * kWave;
+        const uint32_t passes = (L + span - 1) / span;
+        for (uint32_t r = wave; r < G; r += kWaves) {
+          uint64_t carry = 0;
+          for (uint32_t ps = 0; ps < passes; ++ps) {
+            const uint32_t t0 = ps * span + uint32_t(lane) * E;
+            uint64_t v[kColRun];
+#pragma unroll
+            for (uint32_t q = 0; q < kColRun; ++q) {
+              const uint32_t x = (t0 + q) * G + r;
+              v[q] = (q < E && x < N) ? buf[x] : 0;
+            }
+            uint64_t run = 0;
+#pragma unroll
+            for (uint32_t q = 0; q < kColRun; ++q) {
+              run = sat_add_u64(run, v[q]);
+              v[q] = run;
+            }
+            const uint64_t incl = wave_incl_scan_sat_u64(run);
+            const uint64_t up = __shfl_up(incl, 1, kWave);
+            const uint64_t base = sat_add_u64(carry, lane ? up : 0);
+#pragma unroll
+            for (uint32_t q = 0; q < kColRun; ++q) {
+              const uint32_t x = (t0 + q) * G + r;
+              if (q < E && x < N) buf[x] = sat_add_u64(base, v[q]);
+            }
+            carry = sat_add_u64(carry, __shfl(incl, kWave - 1, kWave));
+          }
+        }
       }
     }
+    lds_barrier();
     uint64_t acc = 0, mx = 0;
     for (uint32_t x = tid; x < N; x += kCtThreads) {
       const uint64_t v = buf[x];
@@ -238,10 +272,26 @@ __device__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N, const uint
       acc = sat_add_u64(acc, v);
       mx = v > mx ? v : mx;
     }
-    const uint64_t total = block_sum_u64(acc, red);
-    if (tid == 0 && sums) sums[j] = total;
-    const uint64_t top = block_max_u64(mx, red);
-    if (tid == 0 && maxes) maxes[j] = top;
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+      acc = sat_add_u64(acc, __shfl_xor(acc, off, kWave));
+      const uint64_t y = __shfl_xor(mx, off, kWave);
+      mx = y > mx ? y : mx;
+    }
+    if (lane == 0) {
+      wsum[j][wave] = acc;
+      wmax[j][wave] = mx;
+    }
+    lds_barrier();
+  }
+  if (tid < d) {
+    uint64_t s = 0, m = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      s = sat_add_u64(s, wsum[tid][w]);
+      m = wmax[tid][w] > m ? wmax[tid][w] : m;
+    }
+    if (sums) sums[tid] = s;
+    if (maxes) maxes[tid] = m;
   }
 }
 
@@ -253,8 +303,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
   count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf);
-  __syncthreads();
-  if (threadIdx.x == 0 && sums) sums[d + 1] = T[N - 1];  // |Z(n)| = C[0][n]
+  if (threadIdx.x == 0 && sums) sums[d + 1] = buf[N - 1];  // |Z(n)| = C[0][n] (row 0 in LDS)
 }
 
 // ---------------------------------------------------------------------------
@@ -402,8 +451,7 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_batch_lds(
   int d;
   load_job(jobs, g, &T, &N, &d, &sums, &total);
   count_table_lds(T, N, g, d, sums, nullptr, dyn_buf);
-  __syncthreads();
-  if (threadIdx.x == 0) *total = T[N - 1];
+  if (threadIdx.x == 0) *total = dyn_buf[N - 1];  // row 0 in LDS
 }
 
 __global__ __launch_bounds__(kCtThreads) void k_count_table_batch_global(
@@ -425,7 +473,10 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   Gens gs{};
   for (int i = 0; i < d; ++i) gs.g[i] = gens[i];
   const uint32_t N = uint32_t(n + 1);
-  if (N <= kCtLdsMax) {
+  // ZSET_COUNT_PATH=rows takes the one-launch-per-row form at any size (tests).
+  const char* path = std::getenv("ZSET_COUNT_PATH");
+  const bool rows_form = path && std::strcmp(path, "rows") == 0;
+  if (N <= kCtLdsMax && !rows_form) {
     hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
   } else {
     const uint32_t ib = uint32_t(std::min<uint64_t>((uint64_t(N) + kRowThreads - 1) / kRowThreads,

@@ -55,48 +55,78 @@ __device__ inline uint32_t wave_incl_sum_u32(uint32_t v) {
   return v;
 }
 
-// One wavefront, no barriers: the schedule for memos that fit in LDS.  Steps
-// take `step` = min(64, min(h)) consecutive elements, one per lane; a step
-// never reads an element of its own (p - h_i < x0), so steps are the paper's
-// elementwise batches cut to the wave width.  The cardinalities
-// |Z_{>=i}(p)| are saved as they are computed (Section 2.3), in a ring GE of
-// the last W elements, with the start OFF of each list; a wave prefix sum of
-// the list sizes gives each element its output location, and each lane then
-// copies-and-increments its element's source blocks.  The natural offsets are
-// written to off_out as they are found.
-// Dynamic LDS layout (uint32): GE[W*k] | OFF[W] | M[Rcap*k], W a power of two
-// >= max(h) + step and M 16-byte aligned.  A memo that would outgrow Rcap rows
-// stops and marks off_out[top] = ~0 (the caller then uses the global
-// schedule); Rexp, when non-zero, is the row count the count table predicts.
-template <int KMAX>
-__device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32_t top,
-                                       uint32_t step, uint32_t W, uint32_t Rcap, uint32_t Rexp,
-                                       uint32_t* __restrict__ nat, uint64_t* __restrict__ off_out,
-                                       int* __restrict__ err, uint32_t* lds) {
+// Inclusive prefix max over the wave (same DPP pattern as the sum above).
+__device__ inline uint32_t wave_incl_max_u32(uint32_t v) {
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x111, 0xf, 0xf, false)));
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x112, 0xf, 0xf, false)));
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x114, 0xf, 0xf, false)));
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x118, 0xf, 0xf, false)));
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x142, 0xa, 0xf, false)));
+  v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), 0x143, 0xc, 0xf, false)));
+  return v;
+}
+
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One wavefront, no barriers.  Steps take `step` = min(64, min(h)) consecutive
+// elements, one per lane; a step never reads an element of its own (p - h_i <
+// x0), so steps are the paper's elementwise batches cut to the wave width.
+// Per step:
+//  * every lane reads, for each i, |Z_{>=i}(p - h_i)| and where the list
+//    Z(p - h_i) starts, from rings GE and OFF of the last W elements (the
+//    cardinalities saved as they are computed, Section 2.3);
+//  * |Z_{=i}(p)| = |Z_{>=i}(p - h_i)|, so |Z_{>=i}(p)| is a suffix sum over i,
+//    saved for later steps, and |Z(p)| = |Z_{>=1}(p)|; a wave prefix sum of the
+//    sizes places every list;
+//  * the copy-and-increment runs one lane per copied row (factorizationwise
+//    parallelism, Alg 2.9), 64 rows at a time: the first row of each element
+//    is marked in LDS and a wave prefix max gives every row its element, whose
+//    saved cardinalities then give the row's block i (blocks in the order
+//    i = k..1) and its source row.
+// Dynamic LDS layout (uint32): GE[W*k] | OFF[W] | marks[64] | M rows, W a power
+// of two >= max(h) + step and M 16-byte aligned (memo_ring_words).
+//  * WINDOW = false: M holds the whole memo (Rcap rows); a memo that would
+//    outgrow it stops and marks off_out[top] = ~0 (the caller then takes
+//    another schedule); the rows are copied to `nat` at the end.
+//  * WINDOW = true: M is a ring of Mmask + 1 rows holding the lists of the last
+//    max(h) + step elements (the only ones a step reads), and every row is also
+//    stored to `nat` as it is made; a step that would overrun the ring stops
+//    the build with an error (the caller sizes the ring from the longest list).
+// Rexp, when non-zero, is the row count the count table predicts.
+template <int KMAX, bool WINDOW>
+__device__ inline void memo_chain(const uint32_t (&hg)[KMAX], int k, uint32_t top, uint32_t step,
+                                  uint32_t W, uint32_t hmax, uint32_t Mmask, uint32_t Rcap,
+                                  uint32_t Rexp, uint32_t* __restrict__ nat,
+                                  uint64_t* __restrict__ off_out, int* __restrict__ err,
+                                  uint32_t* lds) {
   uint32_t* GE = lds;
   uint32_t* OFF = GE + size_t(W) * k;
+  uint32_t* marks = lds + memo_ring_words(k, W) - kWave;
   uint32_t* M = lds + memo_ring_words(k, W);
   const uint32_t lane = threadIdx.x;
   const uint32_t Wm = W - 1;
+  auto mrow = [&](uint32_t row) { return WINDOW ? (row & Mmask) : row; };
 
   // Z(0) = [0]: one all-zero row, and |Z_{>=i}(0)| = 1 for every i.
   if (lane < uint32_t(k)) {
     M[lane] = 0;
     GE[lane] = 1;
+    if (WINDOW) nat[lane] = 0;
   }
   if (lane == 0) {
     OFF[0] = 0;
     off_out[0] = 0;
   }
   uint32_t running = 1;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  wave_sync_lds();
 
   for (uint32_t x0 = 1; x0 < top; x0 += step) {
     const uint32_t p = x0 + lane;
     const bool valid = lane < step && p < top;
-    // |Z_{=i}(p)| = |Z_{>=i}(p - h_i)| and where Z(p - h_i) starts.
     uint32_t s[KMAX], so[KMAX];
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) {
@@ -108,7 +138,8 @@ __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32
         so[i] = OFF[slot];
       }
     }
-    // Saved cardinalities: |Z_{>=i}(p)| = sum over i' >= i of |Z_{=i'}(p)|.
+    // ge[i] = |Z_{>=i}(p)| = sum over i' >= i of |Z_{=i'}(p)|.
+    uint32_t ge[KMAX];
     uint32_t acc = 0;
 #pragma unroll
     for (int i = KMAX - 1; i >= 0; --i) {
@@ -116,51 +147,88 @@ __device__ inline void memo_chain_wave(const uint32_t (&hg)[KMAX], int k, uint32
         acc += s[i];
         if (valid) GE[(p & Wm) * k + i] = acc;
       }
+      ge[i] = acc;
     }
     const uint32_t size = valid ? acc : 0;
     const uint32_t incl = wave_incl_sum_u32(size);
     const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-    if (uint64_t(running) + tot > Rcap) {  // the memo outgrows its LDS: report and stop
-      if (lane == 0) off_out[top] = ~uint64_t(0);
+    bool over;
+    if (WINDOW) {
+      const uint32_t oldest = x0 > hmax ? OFF[(x0 - hmax) & Wm] : 0;
+      over = uint64_t(running) + tot - oldest > uint64_t(Mmask) + 1;
+    } else {
+      over = uint64_t(running) + tot > Rcap;
+    }
+    if (over) {
+      if (lane == 0) {
+        off_out[top] = ~uint64_t(0);
+        if (WINDOW) set_error(err, kErrMemoTotal);
+      }
       return;
     }
-    const uint32_t off_p = running + incl - size;
+    const uint32_t first = incl - size;  // this element's first row in the step
     if (valid) {
-      OFF[p & Wm] = off_p;
-      off_out[p] = off_p;
+      OFF[p & Wm] = running + first;
+      off_out[p] = running + first;
     }
-    // Copy-and-increment, blocks in ascending order i = k..1.
-    uint32_t dst = off_p;
+    // Copy-and-increment, one lane per row of the step.
+    uint32_t carry = 0;
+    for (uint32_t beta = 0; beta < tot; beta += kWave) {
+      marks[lane] = 0;
+      wave_sync_lds();
+      if (size != 0 && first >= beta && first - beta < uint32_t(kWave)) marks[first - beta] = lane + 1;
+      wave_sync_lds();
+      uint32_t m = wave_incl_max_u32(marks[lane]);
+      m = max(m, carry);
+      carry = __builtin_amdgcn_readlane(m, kWave - 1);
+      const int owner = int(m) - 1;  // row 0 of a step always starts an element
+      const uint32_t rho = beta + lane;
+      const uint32_t t = rho - uint32_t(__shfl(int(first), owner, kWave));
+      // Block i holds the rows t in [ge[i + 1], ge[i]) of the element.
+      uint32_t src = 0, inc = 0, hi_prev = 0;
 #pragma unroll
-    for (int i = KMAX - 1; i >= 0; --i) {
-      if (i < k) {
-        for (uint32_t r = 0; r < s[i]; ++r) {
-          uint32_t v[KMAX];
-#pragma unroll
-          for (int c = 0; c < KMAX; ++c)
-            if (c < k) v[c] = M[(so[i] + r) * k + c];
-#pragma unroll
-          for (int c = 0; c < KMAX; ++c)
-            if (c < k) M[(dst + r) * k + c] = v[c] + (c == i ? 1u : 0u);
+      for (int i = KMAX - 1; i >= 0; --i) {
+        if (i < k) {
+          const uint32_t hi = uint32_t(__shfl(int(ge[i]), owner, kWave));
+          const uint32_t o = uint32_t(__shfl(int(so[i]), owner, kWave));
+          if (t >= hi_prev && t < hi) {
+            src = o + (t - hi_prev);
+            inc = uint32_t(i);
+          }
+          hi_prev = hi;
         }
-        dst += s[i];
       }
+      if (rho < tot) {
+        uint32_t v[KMAX];
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c)
+          if (c < k) v[c] = M[mrow(src) * k + c];
+        const uint32_t dst = running + rho;
+#pragma unroll
+        for (int c = 0; c < KMAX; ++c) {
+          if (c < k) {
+            const uint32_t w = v[c] + (uint32_t(c) == inc ? 1u : 0u);
+            M[mrow(dst) * k + c] = w;
+            if (WINDOW) nat[uint64_t(dst) * k + c] = w;
+          }
+        }
+      }
+      wave_sync_lds();
     }
     running += tot;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (lane == 0) {
     off_out[top] = running;
     if (Rexp != 0 && running != Rexp) set_error(err, kErrMemoTotal);
   }
-  const uint32_t words = running * uint32_t(k);
-  const uint32_t nvec = words / 4;
-  const uint4* src = reinterpret_cast<const uint4*>(M);
-  uint4* dstv = reinterpret_cast<uint4*>(nat);
-  for (uint32_t v = lane; v < nvec; v += kWave) dstv[v] = src[v];
-  for (uint32_t w = nvec * 4 + lane; w < words; w += kWave) nat[w] = M[w];
+  if (!WINDOW) {
+    const uint32_t words = running * uint32_t(k);
+    const uint32_t nvec = words / 4;
+    const uint4* src = reinterpret_cast<const uint4*>(M);
+    uint4* dstv = reinterpret_cast<uint4*>(nat);
+    for (uint32_t v = lane; v < nvec; v += kWave) dstv[v] = src[v];
+    for (uint32_t w = nvec * 4 + lane; w < words; w += kWave) nat[w] = M[w];
+  }
 }
 
 template <int KMAX>
@@ -174,111 +242,7 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_wave(Gens h, int k, uint32
   uint32_t hg[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) hg[i] = h.g[i];
-  memo_chain_wave<KMAX>(hg, k, top, step, W, Rcap, Rexp, nat, off_out, err, lds);
-}
-
-// The same recurrence for memos larger than LDS: the sources of a batch are
-// lists of the last max(h) elements only, so LDS keeps a ring of Mmask + 1
-// rows (a power of two) holding those lists, and every row is also stored to
-// `nat` as it is made.  Before each batch the rows still needed (those of the
-// elements x0 - max(h) and later) plus the batch's own must fit the ring; the
-// caller sizes it from the largest list (max(h) + step lists at most), and a
-// batch that would not fit stops the build with an error.
-template <int KMAX>
-__device__ inline void memo_chain_window(const uint32_t (&hg)[KMAX], int k, uint32_t top,
-                                         uint32_t step, uint32_t W, uint32_t hmax,
-                                         uint32_t Mmask, uint32_t Rexp,
-                                         uint32_t* __restrict__ nat,
-                                         uint64_t* __restrict__ off_out, int* __restrict__ err,
-                                         uint32_t* lds) {
-  uint32_t* GE = lds;
-  uint32_t* OFF = GE + size_t(W) * k;
-  uint32_t* M = lds + memo_ring_words(k, W);
-  const uint32_t lane = threadIdx.x;
-  const uint32_t Wm = W - 1;
-
-  if (lane < uint32_t(k)) {
-    M[lane] = 0;
-    GE[lane] = 1;
-    nat[lane] = 0;
-  }
-  if (lane == 0) {
-    OFF[0] = 0;
-    off_out[0] = 0;
-  }
-  uint32_t running = 1;
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-  for (uint32_t x0 = 1; x0 < top; x0 += step) {
-    const uint32_t p = x0 + lane;
-    const bool valid = lane < step && p < top;
-    uint32_t s[KMAX], so[KMAX];
-#pragma unroll
-    for (int i = 0; i < KMAX; ++i) {
-      s[i] = 0;
-      so[i] = 0;
-      if (i < k && valid && p >= hg[i]) {
-        const uint32_t slot = (p - hg[i]) & Wm;
-        s[i] = GE[slot * k + i];
-        so[i] = OFF[slot];
-      }
-    }
-    uint32_t acc = 0;
-#pragma unroll
-    for (int i = KMAX - 1; i >= 0; --i) {
-      if (i < k) {
-        acc += s[i];
-        if (valid) GE[(p & Wm) * k + i] = acc;
-      }
-    }
-    const uint32_t size = valid ? acc : 0;
-    const uint32_t incl = wave_incl_sum_u32(size);
-    const uint32_t tot = __builtin_amdgcn_readlane(incl, kWave - 1);
-    const uint32_t oldest = x0 > hmax ? OFF[(x0 - hmax) & Wm] : 0;
-    if (uint64_t(running) + tot - oldest > uint64_t(Mmask) + 1) {
-      if (lane == 0) {
-        off_out[top] = ~uint64_t(0);
-        set_error(err, kErrMemoTotal);
-      }
-      return;
-    }
-    const uint32_t off_p = running + incl - size;
-    if (valid) {
-      OFF[p & Wm] = off_p;
-      off_out[p] = off_p;
-    }
-    uint32_t dst = off_p;
-#pragma unroll
-    for (int i = KMAX - 1; i >= 0; --i) {
-      if (i < k) {
-        for (uint32_t r = 0; r < s[i]; ++r) {
-          uint32_t v[KMAX];
-#pragma unroll
-          for (int c = 0; c < KMAX; ++c)
-            if (c < k) v[c] = M[((so[i] + r) & Mmask) * k + c];
-#pragma unroll
-          for (int c = 0; c < KMAX; ++c) {
-            if (c < k) {
-              const uint32_t w = v[c] + (c == i ? 1u : 0u);
-              M[((dst + r) & Mmask) * k + c] = w;
-              nat[uint64_t(dst + r) * k + c] = w;
-            }
-          }
-        }
-        dst += s[i];
-      }
-    }
-    running += tot;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  }
-  if (lane == 0) {
-    off_out[top] = running;
-    if (Rexp != 0 && running != Rexp) set_error(err, kErrMemoTotal);
-  }
+  memo_chain<KMAX, false>(hg, k, top, step, W, 0, 0, Rcap, Rexp, nat, off_out, err, lds);
 }
 
 template <int KMAX>
@@ -293,7 +257,7 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_window(Gens h, int k, uint
   uint32_t hg[KMAX];
 #pragma unroll
   for (int i = 0; i < KMAX; ++i) hg[i] = h.g[i];
-  memo_chain_window<KMAX>(hg, k, top, step, W, hmax, Mmask, Rexp, nat, off_out, err, lds);
+  memo_chain<KMAX, true>(hg, k, top, step, W, hmax, Mmask, 0, Rexp, nat, off_out, err, lds);
 }
 
 // Batched: workgroup b (one wavefront) builds the memo of jobs[b].
@@ -310,7 +274,7 @@ __global__ __launch_bounds__(kWave) void k_memo_chain_batch(const MemoJob* __res
   const uint32_t step = __builtin_amdgcn_readfirstlane(J.step);
   const uint32_t W = __builtin_amdgcn_readfirstlane(J.W);
   const uint32_t R = __builtin_amdgcn_readfirstlane(J.R);
-  memo_chain_wave<KMAX>(hg, k, top, step, W, R, R, J.nat, J.off, err, lds);
+  memo_chain<KMAX, false>(hg, k, top, step, W, 0, 0, R, R, J.nat, J.off, err, lds);
 }
 
 // k = 1: the recurrence Memo[p] = incr_1(Memo[p - h]) from Memo[0] = {()}

@@ -125,10 +125,11 @@ hipError_t launch_class_ends(const uint64_t* count_row_u, uint64_t n, uint32_t G
 hipError_t launch_class_ends_batch(const ClassJob* jobs, uint32_t njobs, hipStream_t s);
 
 // memo.hip
-// Words of the one-wavefront recurrence's cardinality rings (GE and OFF),
-// rounded up so that the memo rows after them start 16-byte aligned.
+// Words of the one-wavefront recurrence's cardinality rings (GE and OFF) and
+// its 64 row marks, rounded up so that the memo rows after them start 16-byte
+// aligned.
 __host__ __device__ inline uint32_t memo_ring_words(int k, uint32_t W) {
-  return (W * uint32_t(k + 1) + 3u) & ~3u;
+  return ((W * uint32_t(k + 1) + 3u) & ~3u) + 64u;
 }
 size_t memo_wave_lds_bytes(int k, uint64_t R, uint32_t W);
 // Rows of memo that fit beside the rings in lds_bytes of LDS.

@@ -14,7 +14,9 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libzset.so")
+# ZSET_LIB_PATH names another build of the same library (the host-sanitizer
+# build of the CPU tests); by default the in-tree one.
+LIB_PATH = os.environ.get("ZSET_LIB_PATH") or os.path.join(_HERE, "libzset.so")
 
 OK, EINVAL, EOVERFLOW, ENOMEM, ECAPACITY, EDEVICE = 0, -1, -2, -3, -4, -5
 MAX_D = 32
@@ -156,7 +158,8 @@ def load():
     lib.zset_last_error.argtypes = []
     lib.zset_last_error.restype = ctypes.c_char_p
     for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
-                 "zset_enumerate", "zset_enumerate_ex", "zset_batch_create", "zset_batch_info",
+                 "zset_enumerate", "zset_enumerate_ex",
+                 "zset_batch_create", "zset_batch_info",
                  "zset_batch_run", "zset_batch_times", "zset_selftest_host",
                  "zset_server_create", "zset_server_add_set", "zset_server_set_info",
                  "zset_server_count", "zset_server_submit", "zset_server_wait",
