@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--serve-queries", type=int, default=10000,
                     help="queries per arrival rate of the served workload")
     ap.add_argument("--slots", type=int, default=16, help="server slots (batched and served)")
+    ap.add_argument("--memo-bytes", type=int, default=0,
+                    help="served: memo budget per resident set (0: the library's 32 MiB); "
+                         "larger memos are capped (partial memos)")
     ap.add_argument("--dispatchers", type=int, default=1, help="server dispatcher threads")
     ap.add_argument("--kmode", default="server", choices=["server", "tuned"],
                     help="memo dimension of the resident sets of the batched and served "
@@ -466,12 +469,15 @@ def run_serve(args):
                 n_need[s] = max(n_need[s], int(n))
         del c0, run
     arena = torch.empty((64 << 30) // 4, dtype=torch.int32, device="cuda")
-    srv = zset.Server(arena, slots=args.slots, dispatchers=args.dispatchers)
+    srv = zset.Server(arena, slots=args.slots, dispatchers=args.dispatchers,
+                      memo_bytes=args.memo_bytes)
     kq = k_chooser(args)
-    ks = []
+    ks, capped = [], 0
     for s, g in enumerate(sets):
         srv.add_set(g, max(n_need[s], 1), k=kq(max(n_need[s], 1), g))
-        ks.append(srv.set_info(s)["k"])
+        info = srv.set_info(s)
+        ks.append(info["k"])
+        capped += info["memo_top"] <= info["n_max"]
     queries = [(s, ns[i]) for i, (s, _) in enumerate(stream)]
     rows = [srv.count(s, n) for s, n in queries]
     total_rows = sum(rows)
@@ -576,7 +582,8 @@ def run_serve(args):
                                 f"({total_rows} rows), Poisson arrivals at 0.5/1/2 x the plain "
                                 f"path's saturation rate and all at once (value: the last), "
                                 f"64 GiB output arena, {args.slots} slots"),
-                   "k_histogram": {int(k): ks.count(k) for k in sorted(set(ks))}},
+                   "k_histogram": {int(k): ks.count(k) for k in sorted(set(ks))},
+                   "memo_bytes": args.memo_bytes or (32 << 20), "capped_memos": capped},
         "serve": {"plain_qps": mu_plain, "plain_rows_per_s": plain_rows_s,
                   "verified": {"queries": len(sample), "rows": checked_rows,
                                "against": "zset_enumerate_ex, byte for byte"},
@@ -724,18 +731,23 @@ def main():
 
     write_us = avg("write_us")
     bytes_written = rows * d * 4
+    stages = {key: round(avg(key), 2) for key in
+              ("count_us", "memo_us", "plan_us", "write_us", "total_us")}
+    if k == 2:
+        # The library builds two-coordinate memos in closed form; the paper's
+        # recurrence (Lemma 2.3 in elementwise batches) is timed here beside
+        # the step, on the same call, as its memo stage.
+        os.environ["ZSET_MEMO_PATH"] = "chain"
+        rec = [step().stats["memo_us"] for _ in range(3)]
+        del os.environ["ZSET_MEMO_PATH"]
+        stages["memo_recurrence_us"] = round(sum(rec) / len(rec), 2)
     ceiling = None
     if out is not None:
-        # Measured store ceiling: a plain fill of the same buffer.
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        out.fill_(0)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(5):
-            out.fill_(1)
-        ev1.record()
-        torch.cuda.synchronize()
-        ceiling = round(5 * out.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+        # Measured store ceiling: the library's store-only kernels (16-byte
+        # non-temporal stores, the write pass's store form; the fastest of
+        # three launch shapes) over the same buffer.
+        us = zset.store_ceiling(out, reps=5)
+        ceiling = round(out.numel() * 4 / (us * 1e-6) / 1e9, 1)
     if args.count_only:
         # Count-only is integer-ALU bound: FNV-1a over 8 + 4d bytes per row,
         # ~7 lane-ops per byte (xor, 64-bit multiply by 2^40 + 0x1b3).
@@ -770,8 +782,7 @@ def main():
             "rows": rows, "n": n, "gens": g, "k": k,
             "rows_per_tile": stats[-1]["rows_per_tile"], "tiles": stats[-1]["tiles"],
         },
-        "stages_us": {key: round(avg(key), 2) for key in
-                      ("count_us", "memo_us", "plan_us", "write_us", "total_us")},
+        "stages_us": stages,
         "step_hbm_write_frac": round(bytes_written / (ms_per_step * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
         "store_ceiling_gbs": ceiling,
         "roofline": roof,

@@ -73,6 +73,14 @@ typedef struct {
                                 instead of being dealt round-robin; -1 =
                                 automatic (100), 0 = none.  Output is the same
                                 for every value.                               */
+    uint64_t memo_top;       /* 0 = the memo covers every p <= n; else it covers
+                                p < memo_top only (a partial memo, Section 3.1
+                                and Alg 3.2): rows whose trailing remainder p is
+                                >= memo_top are unranked from the count table
+                                instead of copied (Alg 3.2's Else branch).  The
+                                output is the same for every value.  Ignored
+                                when k = 0 or a memo handle is passed (the
+                                handle's own top applies).                    */
 } zset_opts;
 
 /* Per-call timings (device time between HIP events on the call's stream) and
@@ -162,16 +170,16 @@ zset_status zset_enumerate(uint64_t n, const uint32_t *gens, int d, uint32_t *ou
  *   out_rows_cap  rows `out` holds; ECAPACITY before any launch if < |Z(n)|
  *   opts          host, or NULL for the defaults
  *   memo          optional memo handle whose generators equal g_{d-k+1..d}
- *                 (then k = the memo's k) and whose top exceeds n; NULL = the
- *                 call builds its own memo
+ *                 (then k = the memo's k); a handle whose top is <= n is
+ *                 used as a partial memo (see memo_top); NULL = the call
+ *                 builds its own memo
  *   rows_written  host, optional: |Z(n)|
  *   checksum      host, optional: sum over rows r (ascending rank r) of
  *                 FNV-1a-64(LE64(r) || LE32(a_1) .. LE32(a_d)) mod 2^64,
  *                 computed on the GPU only when count_only is set (else 0)
  *   stats         host, optional: timings and sizes
  * Errors: EINVAL (bad d/gens/n/k/order/rows_per_tile, `out` not device
- *         memory, memo mismatch or memo top <= n), EOVERFLOW, ECAPACITY,
- *         ENOMEM, EDEVICE.
+ *         memory, memo mismatch), EOVERFLOW, ECAPACITY, ENOMEM, EDEVICE.
  */
 zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t *out,
                               uint64_t out_rows_cap, const zset_opts *opts,
@@ -336,6 +344,9 @@ typedef struct {
                                 owning an equal share of the slots; 0 = 1 (more
                                 threads measured slower: launches serialise in
                                 the runtime)                                   */
+    uint64_t memo_bytes;     /* memo budget of each resident set (its leaf-order
+                                layout), bytes; 0 = 32 MiB.  A larger memo is
+                                capped (zset_server_add_set)                   */
 } zset_server_opts;
 
 typedef struct {
@@ -346,7 +357,7 @@ typedef struct {
     double done_us;          /* slot, and completion seen by the dispatcher      */
 } zset_server_result;
 
-/* Fill *opts with the defaults (8 slots, no arena, 1 dispatcher). */
+/* Fill *opts with the defaults (8 slots, no arena, 1 dispatcher, 32 MiB memos). */
 void zset_server_default_opts(zset_server_opts *opts);
 
 /* Start a server (its dispatcher thread) on the current device.
@@ -358,16 +369,23 @@ zset_status zset_server_create(const zset_server_opts *opts, zset_server *server
  * zset_server_add_set -- make generator set gens (host, d uint32, each >= 1,
  * in the caller's order) resident up to n_max (<= 2^31 - 2) with memo
  * dimension k (-1 = the largest k >= 2 whose memo of the trailing k generators
- * over p <= n_max (Section 2.2, Lemma 2.3) takes at most 32 MiB, else 1; d = 1
- * sets use 0).  Synchronous.  *set_id receives the set's index (0, 1, ...).
+ * over p <= n_max (Section 2.2, Lemma 2.3) fits opts.memo_bytes, else 1; d = 1
+ * sets use 0).  The memo covers p < top: top = n_max + 1 when that memo fits
+ * opts.memo_bytes, else the largest top whose memo does (at least 1).  With
+ * top <= n a query's rows whose memo remainder is >= top are unranked from the
+ * count table (Section 3.1, Alg 3.2's Else branch); the rows are the same.
+ * Synchronous.  *set_id receives the set's index (0, 1, ...).
  * Errors: EINVAL, EOVERFLOW, ENOMEM, EDEVICE.
  */
 zset_status zset_server_add_set(zset_server server, const uint32_t *gens, int d, uint64_t n_max,
                                 int k, int *set_id);
 
-/* A resident set's memo dimension, n_max, memo rows and device bytes. */
+/* A resident set's memo dimension, n_max, memo rows, device bytes and memo
+ * top (the memo covers p < memo_top; n_max + 1 = every p).  Any output
+ * pointer may be NULL. */
 zset_status zset_server_set_info(zset_server server, int set_id, int *k, uint64_t *n_max,
-                                 uint64_t *memo_rows, uint64_t *resident_bytes);
+                                 uint64_t *memo_rows, uint64_t *resident_bytes,
+                                 uint64_t *memo_top);
 
 /* |Z(n)| of a resident set from its host copy (no device work).
  * Errors: EINVAL (no such set, n > n_max), EOVERFLOW. */
@@ -400,6 +418,22 @@ void zset_server_free(zset_server server);
 
 /* Static text for a status code. */
 const char *zset_strerror(zset_status status);
+
+/*
+ * zset_store_ceiling -- measurement only (no part of the enumeration): the
+ * device's achievable HBM store rate in the write pass's store form.  Fills
+ * `bytes` of `buf` (device, 16-byte aligned, bytes a multiple of 4) with
+ * 16-byte non-temporal coalesced stores in three launch shapes (a one-shot
+ * grid of 256-lane workgroups, one store per lane; a grid-stride loop with
+ * one 256-lane workgroup per compute unit; 64 KiB blocks per wavefront with
+ * four 256-lane workgroups per compute unit), each once untimed and then
+ * `reps` times between HIP events on `stream` (hipStream_t or NULL);
+ * *us_per_pass receives the mean time of one pass of the fastest shape, in
+ * microseconds.  The buffer's contents are overwritten.
+ * Errors: EINVAL, EDEVICE.
+ */
+zset_status zset_store_ceiling(void *buf, uint64_t bytes, int reps, void *stream,
+                               double *us_per_pass);
 
 /*
  * zset_selftest_host -- checks of host-side helpers that need no GPU (the

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libzset.so")
 SOURCES = ["count_table.hip", "scan.hip", "memo.hip", "enumerate.hip", "api.hip", "batch.hip",
-           "serve.hip", "walk.hip"]
+           "serve.hip", "walk.hip", "ceiling.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

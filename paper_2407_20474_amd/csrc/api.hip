@@ -69,10 +69,17 @@ struct Ctx {
   // its fork event and start / end events.
   hipStream_t side = nullptr;
   hipEvent_t fork = nullptr, memo0 = nullptr, memo1 = nullptr;
+  // Stream of the class ends and slice plan when they run before the host's
+  // readback (k fixed by the caller), with the count table's end and their
+  // own end.
+  hipStream_t plan = nullptr;
+  hipEvent_t counted = nullptr, planned = nullptr;
 };
 
 std::map<int, Ctx*> g_ctx;
 
+// Pair lanes in the write pass when n / g_{U-1} is below this (init_params).
+constexpr uint64_t kPairBelow = 200;
 // Slice start states each write workgroup keeps in LDS, at least.
 constexpr uint32_t kMinTileStates = 16;
 // Slices per wavefront above which a query sharing the device gets more
@@ -113,7 +120,10 @@ zset_status get_ctx(Ctx** out) {
   }
   if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
       hipEventCreate(&c->memo0) != hipSuccess || hipEventCreate(&c->memo1) != hipSuccess ||
-      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->counted, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->planned, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->plan, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ZSET_EDEVICE, "side stream or event creation failed");
   }
@@ -136,7 +146,7 @@ zset_status get_ctx(Ctx** out) {
 // concurrent write streams of a compute unit close together in memory and the
 // end of the pass even).
 zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
-                            bool count_only, bool align16, int share) {
+                            bool count_only, bool align16, int share, uint64_t want_tiles) {
   const int pct = claim_pct < 0 ? kDefaultClaimPct : claim_pct;
   const size_t lds_max = size_t(write_lds_budget(device));
   P.max_tiles = kMinTileStates;
@@ -153,13 +163,7 @@ zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct
   const uint64_t wpb = uint64_t(write_waves_per_block());
   const uint64_t resident_waves = uint64_t(cus) * per_cu * wpb;
   uint64_t T_rows = rows_per_tile;
-  if (T_rows == 0) {
-    const uint64_t want_tiles = resident_waves * 128;
-    T_rows = (P.total + want_tiles - 1) / want_tiles;
-    T_rows = (T_rows + 127) / 128 * 128;
-    T_rows = std::max<uint64_t>(T_rows, 128);
-    T_rows = std::min<uint64_t>(T_rows, uint64_t(1) << 30);
-  }
+  if (T_rows == 0) T_rows = slice_rows(P.total, want_tiles ? want_tiles : resident_waves * 128);
   const uint64_t ntiles = (P.total + T_rows - 1) / T_rows;
   if (ntiles > 0x7fffffffull) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
   // A query that shares the device with share - 1 others gets that share of
@@ -197,6 +201,15 @@ zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct
   P.rows_per_tile = T_rows;
   P.ntiles = ntiles;
   return ZSET_OK;
+}
+
+uint64_t plan_want_tiles(int device) {
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+    (void)hipGetLastError();
+    cus = 1;
+  }
+  return uint64_t(cus) * uint64_t(write_waves_per_block()) * 128;
 }
 
 // Leaf-order row format for elements p <= n: fields floor(p / G) <= n / G and
@@ -299,16 +312,20 @@ int max_lds_bytes(Ctx* c) { return device_max_lds_bytes(c->device); }
 // either of those) keeps the recurrence for k = 2 memos, which the single path
 // otherwise builds in closed form.
 // `srcw_for(bytes, &ptr)` provides the global schedule's source table.
+// R is the memo's row count when `exact`, else an upper bound (a partial
+// memo sized from the row sums over every p <= n).
 zset_status build_memo_rows(const uint32_t* h, int k, uint64_t top, uint64_t* off,
                             const uint64_t* ge, uint64_t ge_stride, uint64_t R, uint64_t rowmax,
                             uint32_t* nat, int* err, size_t lds,
                             const std::function<zset_status(size_t, uint64_t**)>& srcw_for,
-                            hipStream_t s) {
+                            hipStream_t s, bool exact = true) {
   if (k == 1) {
-    if (R != (top - 1) / h[0] + 1) return fail(ZSET_EDEVICE, "memo row count disagrees (k = 1)");
-    ZSET_HIP(launch_memo_k1(h[0], top, R, nat, off, s));
+    const uint64_t R1 = (top - 1) / h[0] + 1;
+    if (exact ? R != R1 : R < R1) return fail(ZSET_EDEVICE, "memo row count disagrees (k = 1)");
+    ZSET_HIP(launch_memo_k1(h[0], top, R1, nat, off, s));
     return ZSET_OK;
   }
+  const uint64_t Rexp = exact ? R : 0;
   uint32_t b = h[0], hmax = h[0];
   for (int i = 1; i < k; ++i) {
     b = std::min(b, h[i]);
@@ -322,7 +339,7 @@ zset_status build_memo_rows(const uint32_t* h, int k, uint64_t top, uint64_t* of
   const uint32_t W = Wl < (uint64_t(1) << 30) ? next_pow2(uint32_t(Wl)) : 0;
   if (!force_global && !force_window && W != 0 && R < (uint64_t(1) << 30) &&
       memo_wave_lds_bytes(k, R, W) <= lds) {
-    ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, R, nat, off, err, s));
+    ZSET_HIP(launch_memo_chain_wave(h, k, top, step, W, R, Rexp, nat, off, err, s));
     return ZSET_OK;
   }
   if (!force_global && W != 0 && R < (uint64_t(1) << 32) && rowmax < (uint64_t(1) << 24)) {
@@ -330,7 +347,7 @@ zset_status build_memo_rows(const uint32_t* h, int k, uint64_t top, uint64_t* of
     if (need < (uint64_t(1) << 30)) {
       const uint32_t cap = next_pow2(uint32_t(need));
       if (memo_wave_lds_bytes(k, cap, W) <= lds) {
-        ZSET_HIP(launch_memo_chain_window(h, k, top, step, W, hmax, cap, R, nat, off, err, s));
+        ZSET_HIP(launch_memo_chain_window(h, k, top, step, W, hmax, cap, Rexp, nat, off, err, s));
         return ZSET_OK;
       }
     }
@@ -402,6 +419,19 @@ uint64_t init_params(EnumParams& P, uint64_t n, const uint32_t* gens, int d, int
   P.flush = P.ring / 2;
   P.max_tiles = kMinTileStates;  // grown by size_write_pass to what LDS leaves
   if (k < 1) return 0;
+  // Pair lanes when the lane coordinate a_{U-1} takes few values: at most
+  // n / g_{U-1} < kPairBelow (its range after the outer prefix is smaller
+  // still), so that most steps would leave lanes idle; each step then takes
+  // 64 (a_{U-2}, a_{U-1}) pairs.  The threshold is measured: pairs win on the
+  // sweep workloads at d = 7 (n / g_{U-1} = 170 and 194) and 9 (57, 59) and
+  // lose on the large workload (273, whose row assembly is compiled per shape).
+  // ZSET_PAIR=0 / 1 forces the choice (tests).
+  if (U >= 2) {
+    P.dG1 = DivMod32::make(gens[U - 1]);
+    const char* pe = std::getenv("ZSET_PAIR");
+    if (pe && (pe[0] == '0' || pe[0] == '1')) P.pair = pe[0] == '1';
+    else P.pair = n / gens[U - 1] < kPairBelow;
+  }
   const uint64_t Rn = sums[L];  // rows of Memo[p] over p <= n
   leaf_format(P, n, gens, U, k);
   P.nclass = uint32_t(std::min<uint64_t>(G, N));
@@ -425,6 +455,7 @@ uint64_t init_params(EnumParams& P, uint64_t n, const uint32_t* gens, int d, int
 
 }  // namespace
 }  // namespace zset
+
 
 
 using namespace zset;
@@ -607,7 +638,8 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     for (int i = 0; i < memo->k; ++i)
       if (memo->h[i] != gens[d - memo->k + i])
         return fail(ZSET_EINVAL, "memo generators differ from the trailing generators");
-    if (memo->top < n + 1) return fail(ZSET_EINVAL, "memo top must exceed n");
+    // A memo whose top is <= n is partial: rows with memo remainder >= top
+    // come from the count table (Alg 3.2's Else branch).
   }
   if (!count_only && !is_device_pointer(out)) return fail(ZSET_EINVAL, "out is not device memory");
 
@@ -623,6 +655,13 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   int* err = reinterpret_cast<int*>(misc + kMiscErr);
   if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
+  // Memo coverage: every p <= n, or p < top (a partial memo: a memo handle's
+  // top, or opts.memo_top).  Rows whose memo remainder is >= top are then
+  // unranked from the count table by the write pass (Alg 3.2's Else branch).
+  uint64_t top = N;
+  if (memo) top = std::min<uint64_t>(memo->top, N);
+  else if (opts.memo_top) top = std::min<uint64_t>(opts.memo_top, N);
+  const bool partial = top < N;
 
   // 1. Count table, row sums (memo sizes), total.  When k >= 1 is fixed by the
   // caller, the memo recurrence needs nothing from the count table: it starts
@@ -647,7 +686,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     const char* path = std::getenv("ZSET_MEMO_PATH");
     const bool force_global = path && std::strcmp(path, "global") == 0;
     const bool force_chain = path && std::strcmp(path, "chain") == 0;
-    if (!memo && opts.k >= 1 && d >= 2 && !force_global) {
+    if (!memo && opts.k >= 1 && d >= 2 && !force_global && !partial) {
       const int kk = opts.k, L0 = d - kk;
       uint32_t b = gens[L0], hmax = gens[L0];
       for (int i = L0; i < d; ++i) {
@@ -688,6 +727,52 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   // Count table, then one readback of the row sums and |Z(n)|.
   ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
   ZSET_HIP(hipEventRecord(c->ev[1], s));
+  // When the caller fixes k (or passes a memo), the class ends and the slice
+  // plan need only the count table: they run on the plan stream while the
+  // host waits for the readback, the planner reading |Z(n)| on the device
+  // and sizing the slices for plan_want_tiles slices (the host repeats the
+  // same sizing below).
+  const int k_fixed = memo ? memo->k : opts.k;
+  const bool early_plan = k_fixed >= 1 && d >= 2 && opts.rows_per_tile == 0;
+  const uint64_t want_early = early_plan ? plan_want_tiles(c->device) : 0;
+  struct PlanJoin {  // every return after the early plan waits for its stream
+    Ctx* c = nullptr;
+    ~PlanJoin() {
+      if (c) (void)hipStreamSynchronize(c->plan);
+    }
+  } plan_join;
+  if (early_plan) {
+    const int Ue = d - k_fixed - 1;
+    const uint32_t Ge = gens[Ue];
+    if ((st = ensure(c->endc, size_t(std::min<uint64_t>(Ge, top)) * sizeof(uint64_t))) != ZSET_OK)
+      return st;
+    if ((st = ensure(c->tiles, size_t(want_early) * (Ue + 2) * sizeof(uint32_t))) != ZSET_OK)
+      return st;
+    EnumParams Pe;
+    std::memset(&Pe, 0, sizeof Pe);
+    for (int i = 0; i < d; ++i) Pe.g.g[i] = gens[i];
+    Pe.n = uint32_t(n);
+    Pe.d = d;
+    Pe.U = Ue;
+    Pe.k = k_fixed;
+    Pe.table = T;
+    Pe.table_stride = N;
+    Pe.err = err;
+    Pe.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
+    Pe.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
+    Pe.total_dev = misc + kMiscRowSums + d + 1;
+    Pe.want_tiles = want_early;
+    ZSET_HIP(hipEventRecord(c->counted, s));
+    ZSET_HIP(hipStreamWaitEvent(c->plan, c->counted, 0));
+    plan_join.c = c;
+    ZSET_HIP(hipEventRecord(c->ev[2], c->plan));
+    uint32_t nclass = 0;
+    ZSET_HIP(launch_class_ends(T + uint64_t(Ue) * N, top - 1, Ge,
+                               reinterpret_cast<uint64_t*>(c->endc.p), &nclass, c->plan));
+    ZSET_HIP(launch_plan_device_sized(Pe, c->plan));
+    ZSET_HIP(hipEventRecord(c->ev[3], c->plan));
+    ZSET_HIP(hipEventRecord(c->planned, c->plan));
+  }
   ZSET_HIP(hipMemcpyAsync(c->pinned, misc + kMiscRowSums, (2 * d + 3) * sizeof(uint64_t),
                           hipMemcpyDeviceToHost, s));
   ZSET_HIP(hipStreamSynchronize(s));
@@ -733,10 +818,17 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     const uint64_t leaf_words = init_params(P, n, gens, d, k, total, sums, T, err,
                                             misc + kMiscSum, out,
                                             size_t(write_lds_budget(c->device)));
-    const uint64_t Rn = k >= 1 ? sums[L] : 0;  // rows of Memo[p] over p <= n
+    P.desc = opts.order == 1 && !count_only;
+    // Rows of Memo[p] over p <= n: the memo's rows, or a bound on them for a
+    // partial memo (p < top).
+    const uint64_t Rn = k >= 1 ? sums[L] : 0;
+    if (k >= 1 && partial) {
+      P.memo_top = uint32_t(top);
+      P.nclass = uint32_t(std::min<uint64_t>(G, top));
+    }
     if (k >= 1) {
       memo_rows = Rn;
-      const uint64_t nclass_max = std::min<uint64_t>(G, N);
+      const uint64_t nclass_max = std::min<uint64_t>(G, top);
       if ((st = ensure(c->endc, size_t(nclass_max) * sizeof(uint64_t))) != ZSET_OK) return st;
       if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
       P.endc = reinterpret_cast<uint64_t*>(c->endc.p);
@@ -749,21 +841,29 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     // the end of the pass even).
     const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
-    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, c->device, count_only, align16)) !=
-        ZSET_OK)
+    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, c->device, count_only, align16,
+                              1, want_early)) != ZSET_OK)
       return st;
     T_rows = P.rows_per_tile;
     ntiles = P.ntiles;
-    if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
-    P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
-    ZSET_HIP(hipEventRecord(c->ev[2], s));
-    if (k >= 1) {
-      uint32_t nclass = 0;
-      ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc),
-                                 &nclass, s));
+    if (early_plan) {
+      // Planned above on the plan stream, for the same slices.
+      if (ntiles > want_early || U != d - k_fixed - 1)
+        return fail(ZSET_EDEVICE, "internal: early slice plan disagrees with the write pass");
+      P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
+      ZSET_HIP(hipStreamWaitEvent(s, c->planned, 0));
+    } else {
+      if ((st = ensure(c->tiles, size_t(ntiles) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
+      P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
+      ZSET_HIP(hipEventRecord(c->ev[2], s));
+      if (k >= 1) {
+        uint32_t nclass = 0;
+        ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, top - 1, G, const_cast<uint64_t*>(P.endc),
+                                   &nclass, s));
+      }
+      ZSET_HIP(launch_plan(P, s));
+      ZSET_HIP(hipEventRecord(c->ev[3], s));
     }
-    ZSET_HIP(launch_plan(P, s));
-    ZSET_HIP(hipEventRecord(c->ev[3], s));
 
     // 4. Memo rows (k >= 1) -- a memo handle's, the side-stream recurrence's,
     // or built here -- then the leaf-order layout.
@@ -786,22 +886,23 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
         const bool closed2 = k == 2 && memo2_closed_form();
         if (closed2) {  // two coordinates: the closed form, element-parallel
           if ((st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
-          ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn,
+          ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], top, Rn,
                                   reinterpret_cast<uint32_t*>(c->nat.p), o,
                                   reinterpret_cast<uint64_t*>(c->cnt2.p), s));
         } else {
-          st = build_memo_rows(gens + L, k, N, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
+          st = build_memo_rows(gens + L, k, top, o, T + uint64_t(L) * N, N, Rn, rowmax[L],
                                reinterpret_cast<uint32_t*>(c->nat.p), err,
-                               size_t(max_lds_bytes(c)), ctx_srcw(c), s);
+                               size_t(max_lds_bytes(c)), ctx_srcw(c), s, !partial);
           if (st != ZSET_OK) return st;
         }
         off = o;
         nat = reinterpret_cast<const uint32_t*>(c->nat.p);
       }
       ZSET_HIP(hipEventRecord(c->ev[6], s));
-      ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
-                                              const_cast<uint32_t*>(P.leaf), Rn, P),
-                                err, s));
+      LeafJob J = make_leaf_job(k, top - 1, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                const_cast<uint32_t*>(P.leaf), Rn, P);
+      J.exact = !partial;  // else Rn bounds the rows; off[top] on the device counts them
+      ZSET_HIP(launch_memo_leaf(J, err, s));
     } else {
       ZSET_HIP(hipEventRecord(c->ev[6], s));
     }
@@ -817,9 +918,11 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   }
   ZSET_HIP(hipEventRecord(c->ev[5], s));
   if (early) ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
-  if (!count_only && opts.order == 1 && total > 1) ZSET_HIP(launch_reverse(out, total, d, s));
+
+  if (early_plan && !(total > 0 && d > 1)) ZSET_HIP(hipStreamWaitEvent(s, c->planned, 0));
   ZSET_HIP(hipMemcpyAsync(c->pinned, misc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
   ZSET_HIP(hipStreamSynchronize(s));
+  plan_join.c = nullptr;  // the call's stream waited for the plan stream
   const int code = *reinterpret_cast<int*>(c->pinned);
   if (code != 0) return fail(ZSET_EDEVICE, device_error_text(code));
   if (rows_written) *rows_written = total;

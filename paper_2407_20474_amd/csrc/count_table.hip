@@ -150,16 +150,17 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
 // r, r + g_j, r + 2 g_j, ... is one column of the row viewed as a matrix with
 // g_j columns.  Columns of at most kColWalk entries are walked by one thread
 // each (neighbouring threads take neighbouring columns).  Longer columns go
-// to one wavefront each: lane l takes a run of E consecutive entries of the
-// column, scans it in registers, and a wave-wide inclusive scan of the run
-// totals (DPP, no LDS round trip) gives each run its carry; E is odd so that
-// the lanes' runs fall in different LDS banks, and a column longer than 64 E
-// takes several passes with a running carry.  Between rows the workgroup
+// to a segment of 16, 32 or 64 lanes each (2 to 4 short columns share a
+// wavefront): lane l takes a run of E consecutive entries of its column,
+// scans it in registers, and a segmented inclusive scan of the run totals
+// (DPP, no LDS round trip) gives each run its carry; E is odd so that the
+// lanes' runs fall in different LDS banks, and a column longer than the
+// segment's reach takes several passes with a running carry.  Between rows the workgroup
 // synchronises on LDS only: the row's global copy-out need not complete before
 // the next row starts.  Row sums and maxima are reduced per wavefront as the
 // row is copied and combined once at the end.
 constexpr uint32_t kCtLdsMax = 16384;
-constexpr uint32_t kColWalk = 32;
+constexpr uint32_t kColWalk = 64;
 constexpr uint32_t kColRun = 15;  // longest run per lane (odd)
 
 __device__ inline void lds_barrier() {
@@ -178,22 +179,24 @@ __device__ inline uint64_t dpp_u64(uint64_t v) {
   return (uint64_t(hi) << 32) | lo;
 }
 
-// Saturating inclusive prefix sum over the 64 lanes: row_shr 1/2/4/8 inside
-// each 16-lane row, then row_bcast 15 and 31 across rows.
-__device__ inline uint64_t wave_incl_scan_sat_u64(uint64_t v) {
+// Saturating inclusive prefix sums over segments of `seg` = 16, 32 or 64
+// lanes: row_shr 1/2/4/8 inside each 16-lane row, then row_bcast 15 (rows 1
+// and 3 add the last lane of rows 0 and 2: 32-lane segments) and row_bcast 31
+// (rows 2 and 3 add lane 31: the whole wave).
+__device__ inline uint64_t wave_incl_scan_sat_u64(uint64_t v, uint32_t seg) {
   v = sat_add_u64(v, dpp_u64<0x111>(v));
   v = sat_add_u64(v, dpp_u64<0x112>(v));
   v = sat_add_u64(v, dpp_u64<0x114>(v));
   v = sat_add_u64(v, dpp_u64<0x118>(v));
-  v = sat_add_u64(v, dpp_u64<0x142, 0xa>(v));
-  v = sat_add_u64(v, dpp_u64<0x143, 0xc>(v));
+  if (seg >= 32) v = sat_add_u64(v, dpp_u64<0x142, 0xa>(v));
+  if (seg >= 64) v = sat_add_u64(v, dpp_u64<0x143, 0xc>(v));
   return v;
 }
 
 __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N,
                                                 const uint32_t* gs, int d,
                                 uint64_t* __restrict__ sums, uint64_t* __restrict__ maxes,
-                                uint64_t* buf) {
+                                uint64_t* buf, uint32_t walk_max = kColWalk) {
   constexpr int kWaves = kCtThreads / kWave;
   __shared__ uint64_t wsum[kMaxD][kWaves];
   __shared__ uint64_t wmax[kMaxD][kWaves];
@@ -210,7 +213,7 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
     const uint32_t G = gs[j];
     if (G < N) {  // else no x - g_j >= 0: row j equals row j + 1
       const uint32_t L = (N + G - 1) / G;  // entries of the longest column
-      if (L <= kColWalk) {
+      if (L <= walk_max) {
         for (uint32_t r = tid; r < G; r += kCtThreads) {
           uint64_t run = 0;
           for (uint32_t t0 = 0; t0 < L; t0 += 8) {
@@ -231,19 +234,28 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
           }
         }
       } else {
-        uint32_t E = (L + kWave - 1) / kWave;
+        // Segments of `seg` lanes (16, 32 or 64), one column each: the
+        // smallest segment whose runs of at most kColRun entries cover the
+        // column, so that short columns share a wavefront pass.
+        uint32_t seg = 16;
+        while (seg < uint32_t(kWave) && seg * kColRun < L) seg *= 2;
+        uint32_t E = (L + seg - 1) / seg;
         E = (E < kColRun ? E : kColRun) | 1u;
-        const uint32_t span = E * kWave;
+        const uint32_t span = E * seg;
         const uint32_t passes = (L + span - 1) / span;
-        for (uint32_t r = wave; r < G; r += kWaves) {
+        const uint32_t per_wave = uint32_t(kWave) / seg;  // columns per wavefront pass
+        const uint32_t sl = uint32_t(lane) % seg, sb = uint32_t(lane) - sl;
+        for (uint32_t r0 = uint32_t(wave) * per_wave; r0 < G; r0 += kWaves * per_wave) {
+          const uint32_t r = r0 + uint32_t(lane) / seg;
+          const bool col = r < G;
           uint64_t carry = 0;
           for (uint32_t ps = 0; ps < passes; ++ps) {
-            const uint32_t t0 = ps * span + uint32_t(lane) * E;
+            const uint32_t t0 = ps * span + sl * E;
             uint64_t v[kColRun];
 #pragma unroll
             for (uint32_t q = 0; q < kColRun; ++q) {
               const uint32_t x = (t0 + q) * G + r;
-              v[q] = (q < E && x < N) ? buf[x] : 0;
+              v[q] = (col && q < E && x < N) ? buf[x] : 0;
             }
             uint64_t run = 0;
 #pragma unroll
@@ -251,15 +263,15 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
               run = sat_add_u64(run, v[q]);
               v[q] = run;
             }
-            const uint64_t incl = wave_incl_scan_sat_u64(run);
+            const uint64_t incl = wave_incl_scan_sat_u64(run, seg);
             const uint64_t up = __shfl_up(incl, 1, kWave);
-            const uint64_t base = sat_add_u64(carry, lane ? up : 0);
+            const uint64_t base = sat_add_u64(carry, sl ? up : 0);
 #pragma unroll
             for (uint32_t q = 0; q < kColRun; ++q) {
               const uint32_t x = (t0 + q) * G + r;
-              if (q < E && x < N) buf[x] = sat_add_u64(base, v[q]);
+              if (col && q < E && x < N) buf[x] = sat_add_u64(base, v[q]);
             }
-            carry = sat_add_u64(carry, __shfl(incl, kWave - 1, kWave));
+            carry = sat_add_u64(carry, __shfl(incl, int(sb + seg - 1), kWave));
           }
         }
       }
@@ -297,12 +309,13 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
 
 __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
                                                                 uint32_t N, Gens gs, int d,
-                                                                uint64_t* __restrict__ sums) {
+                                                                uint64_t* __restrict__ sums,
+                                                                uint32_t walk_max) {
   __shared__ uint64_t buf[kCtLdsMax];
   __shared__ uint32_t g[kMaxD];
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
-  count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf);
+  count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf, walk_max);
   if (threadIdx.x == 0 && sums) sums[d + 1] = buf[N - 1];  // |Z(n)| = C[0][n] (row 0 in LDS)
 }
 
@@ -477,7 +490,10 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   const char* path = std::getenv("ZSET_COUNT_PATH");
   const bool rows_form = path && std::strcmp(path, "rows") == 0;
   if (N <= kCtLdsMax && !rows_form) {
-    hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums);
+    const char* we = std::getenv("ZSET_COUNT_WALK");
+    const uint32_t walk = we ? uint32_t(std::atoi(we)) : kColWalk;
+    hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums,
+                       walk);
   } else {
     const uint32_t ib = uint32_t(std::min<uint64_t>((uint64_t(N) + kRowThreads - 1) / kRowThreads,
                                                     4096));

@@ -98,9 +98,9 @@ __device__ inline uint32_t wave_incl_sum_sat(uint32_t v, uint32_t cap) {
 }
 
 // Slice start: first U coordinates and the offset t0 inside their block.
-__device__ inline void plan_tile(const EnumParams& P, uint64_t tile) {
+__device__ inline void plan_tile(const EnumParams& P, uint64_t tile, uint64_t T) {
   const uint64_t N = P.table_stride;
-  uint64_t r = tile * P.rows_per_tile;
+  uint64_t r = tile * T;
   uint32_t x = P.n;
   uint32_t* st = P.tiles + tile * uint64_t(P.U + 2);
   for (int j = 0; j < P.U; ++j) {
@@ -168,8 +168,14 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
       if (P.blocks_done) *P.blocks_done = 0;
     }
   }
-  if (tile >= P.ntiles) return;
-  plan_tile(P, tile);
+  uint64_t T = P.rows_per_tile, ntiles = P.ntiles;
+  if (P.total_dev) {  // sized on the device from |Z(n)|
+    const uint64_t total = *P.total_dev;
+    T = slice_rows(total, P.want_tiles);
+    ntiles = (total + T - 1) / T;
+  }
+  if (tile >= ntiles) return;
+  plan_tile(P, tile, T);
 }
 
 // Batched: global slice index -> (query, slice) by bisection of the slice
@@ -186,7 +192,8 @@ __global__ __launch_bounds__(256) void k_plan_batch(const EnumParams* __restrict
     const uint32_t mid = (lo + hi + 1) / 2;
     if (tile_base[mid] <= t) lo = mid; else hi = mid - 1;
   }
-  plan_tile(qp[plan_q[lo]], t - tile_base[lo]);
+  const EnumParams& Q = qp[plan_q[lo]];
+  plan_tile(Q, t - tile_base[lo], Q.rows_per_tile);
 }
 
 // Output rows are written once and never read back by the kernel: the stores
@@ -207,6 +214,22 @@ __device__ inline void flush_rows(const uint32_t* ring, uint32_t slot0, uint32_t
     for (uint32_t v = nd4 + lane; v < nd; v += kWave) __builtin_nontemporal_store(src[v], out_rows + v);
   } else {
     for (uint32_t v = lane; v < nd; v += kWave) __builtin_nontemporal_store(src[v], out_rows + v);
+  }
+}
+
+// Descending output: `rows` staged rows (ascending) written as one block in
+// reverse row order, one word per lane per store (coalesced; the block's
+// start need not be 16-byte aligned).  Row of word v: v / d by a multiply and
+// shift, exact for v < 2^12 (at most 128 rows of at most 32 words).
+__device__ inline void flush_rows_rev(const uint32_t* ring, uint32_t slot0, uint32_t rows, int d,
+                                      uint32_t* out_rows) {
+  const uint32_t nd = rows * uint32_t(d);
+  const uint32_t* src = ring + slot0 * uint32_t(d);
+  const uint32_t m = (1u << 20) / uint32_t(d) + 1u;
+  for (uint32_t v = uint32_t(lane_id()); v < nd; v += kWave) {
+    const uint32_t row = (v * m) >> 20;
+    const uint32_t col = v - row * uint32_t(d);
+    __builtin_nontemporal_store(src[(rows - 1 - row) * uint32_t(d) + col], out_rows + v);
   }
 }
 
@@ -263,6 +286,13 @@ __host__ __device__ inline uint64_t write_shared_words(const EnumParams& P) {
 struct TileArgs {
   uint32_t n, d, U, k;
   uint32_t gseg;               // g_{U-1} (U >= 1): step of the lane coordinate
+  uint32_t gpre;               // g_{U-2} (pair lanes)
+  int pair;                    // 1: lanes range over (a_{U-2}, a_{U-1}) pairs
+  int desc;                    // 1: rows stored in descending order
+  uint32_t top;                // memo covers p < top; top <= n: partial memo (Else branch)
+  uint32_t nclass;             // residue classes of the leaf layout (with rows below top)
+  const uint64_t* table;       // count table (rows U.. unrank the head rows of a partial memo)
+  uint64_t table_stride;
   uint32_t ring, flush;        // staging ring rows (power of two), rows per flush
   uint64_t total;              // |Z(n)|
   uint64_t rows_per_tile;      // slice length
@@ -273,6 +303,7 @@ struct TileArgs {
   uint32_t* out;               // first row of this query
   int* err;
   DivMod32 dG;                 // division by g_U
+  DivMod32 dG1;                // division by g_{U-1} (pair lanes)
 };
 
 __device__ inline TileArgs tile_args(const EnumParams& P) {
@@ -282,6 +313,14 @@ __device__ inline TileArgs tile_args(const EnumParams& P) {
   A.U = uint32_t(P.U);
   A.k = uint32_t(P.k);
   A.gseg = P.U >= 1 ? P.g.g[P.U - 1] : 0;
+  A.gpre = P.U >= 2 ? P.g.g[P.U - 2] : 0;
+  A.pair = P.pair;
+  A.desc = P.desc;
+  A.top = P.memo_top ? P.memo_top : P.n + 1;
+  A.nclass = P.nclass;
+  A.table = P.table;
+  A.table_stride = P.table_stride;
+  A.dG1 = P.dG1;
   A.ring = P.ring;
   A.flush = P.flush;
   A.total = P.total;
@@ -296,12 +335,45 @@ __device__ inline TileArgs tile_args(const EnumParams& P) {
   return A;
 }
 
+// Row t (ascending) of Z(x; g_U, .., g_{d-1}), for a row that the memo does
+// not hold (a partial memo, the Else branch of Alg 3.2): coordinates U..d-2
+// by bisection of the count table's rows (the rows before a_j = a number
+// C_j[x] - C_j[x - a g_j]), the last one by division.  put(j, a_j) is called
+// in coordinate order.  Lane j of gj holds g_j.
+template <class F>
+__device__ inline void unrank_suffix(const TileArgs& P, uint32_t gj, int U, int d, uint32_t x,
+                                     uint64_t t, F&& put) {
+  for (int j = U; j < d - 1; ++j) {
+    const uint32_t g = readlane_u32(gj, j);
+    const uint64_t* Cj = P.table + uint64_t(j) * P.table_stride;
+    const uint64_t all = Cj[x];
+    uint32_t lo = 0, hi = x / g;
+    while (lo < hi) {
+      const uint32_t mid = lo + (hi - lo + 1) / 2;
+      if (all - Cj[x - mid * g] <= t) lo = mid; else hi = mid - 1;
+    }
+    t -= all - Cj[x - lo * g];
+    x -= lo * g;
+    put(j, lo);
+  }
+  put(d - 1, x / readlane_u32(gj, d - 1));
+}
+
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+  const uint32_t lo = __shfl(uint32_t(v), src, kWave), hi = __shfl(uint32_t(v >> 32), src, kWave);
+  return (uint64_t(hi) << 32) | lo;
+}
+
 // One slice: rows [tile * T, tile * T + target) of the query, starting from
 // the slice start `st` (first U coordinates and t0).  Shared by the
 // single-query and the batched write kernels.  NO >= 0 and KF >= 1 fix the
 // outer-prefix length (U - 1) and k at compile time, so that a row is
 // assembled with no loop and with the prefix and field shifts held in scalar
-// registers; -1 leaves them to run time.
+// registers; -1 leaves them to run time, and kNoPartial (generic row
+// assembly too) also serves a partial memo, whose head rows are unranked from
+// the count table: a separate instantiation, so that the others carry none of
+// its registers.
+constexpr int kNoPartial = -2;
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO = -1, int KF = -1>
 __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32_t* st,
                                   uint32_t* ring, uint32_t* marks, const uint32_t* lds_memo,
@@ -315,8 +387,16 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   // staged at once, else in two halves with a flush check between them.
   const uint32_t nphase = (P.flush + uint32_t(kWave) <= P.ring) ? 1u : 2u;
   const uint32_t phase_rows = uint32_t(kWave) / nphase;
-  const int nouter = U >= 1 ? U - 1 : 0;  // coordinates 0..U-2 form the outer prefix
+  // Pair lanes (MODE 1, U >= 2): the lanes range over the pairs (a_{U-2},
+  // a_{U-1}) of the current outer prefix in lex order, 64 pairs per step, so
+  // that a step covers 64 segments even when a_{U-1} alone takes few values.
+  const bool pair = MODE == 1 && NO < 0 && P.pair && U >= 2;  // generic row assembly only
+  // Partial memo (generic row assembly only): the memo covers p < top <= n.
+  const bool partial = MODE == 1 && NO == kNoPartial && P.top <= P.n;
+  // Coordinates 0..nouter-1 form the outer prefix.
+  const int nouter = pair ? U - 2 : (U >= 1 ? U - 1 : 0);
   const uint32_t gseg = P.gseg;
+  const uint32_t gpre = P.gpre;
   const uint64_t* cnt_row = P.cnt_row;
   const uint64_t r0 = tile * P.rows_per_tile;
   const uint64_t left = P.total - r0;
@@ -336,8 +416,10 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
     }
     remj = P.n - ps;
   }
-  uint32_t xouter = (U >= 2) ? readlane_u32(remj, U - 2) : P.n;
+  // Remainder after the outer prefix; first lane-coordinate value (or pair).
+  uint32_t xouter = nouter >= 1 ? readlane_u32(remj, nouter - 1) : P.n;
   uint32_t aseg = (U >= 1) ? readlane_u32(aj, U - 1) : 0;
+  uint32_t tc = pair ? readlane_u32(aj, U - 2) : 0;  // pair of the step's first lane
 
   constexpr bool kSpec = NO >= 0 && KF >= 1;
   uint32_t hsh[kSpec ? KF + 1 : 1], hmk[kSpec ? KF + 1 : 1];
@@ -352,6 +434,15 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
   bool first = true;
   bool single_done = false;
   uint32_t* out_tile = P.out + r0 * uint64_t(d);
+  // Staged rows [f, f + rows) of the slice go to ranks r0 + f ..; in
+  // descending order the rank r is stored at row total - 1 - r, so the block
+  // starts at row total - r0 - f - rows and is written in reverse.
+  auto emit = [&](uint32_t slot0, uint32_t rows, uint32_t f) {
+    if (P.desc)
+      flush_rows_rev(ring, slot0, rows, d, P.out + (P.total - r0 - f - rows) * uint64_t(d));
+    else
+      flush_rows<ALIGN16>(ring, slot0, rows, d, out_tile + uint64_t(f) * d);
+  };
 
   while (produced < target) {
     const uint32_t remaining = target - produced;
@@ -363,7 +454,33 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
     const uint32_t A = aseg + uint32_t(lane);
     bool ok;
     uint32_t xs;
-    if (U >= 1) {
+    uint32_t pt = 0, pa = 0, npairs = 0;  // pair lanes: this lane's (a_{U-2}, a_{U-1})
+    if (pair) {
+      // Row j of the pair space holds a_{U-2} = tc + j and a_{U-1} in
+      // [0, (xouter - a_{U-2} g_{U-2}) / g_{U-1}] (row 0 from aseg on); the
+      // rows' first lanes are marked and a wave prefix max gives each lane
+      // its row.
+      const uint32_t tj = tc + uint32_t(lane);
+      const uint64_t tg = uint64_t(tj) * gpre;
+      uint32_t cnt = tg <= xouter ? P.dG1.div(xouter - uint32_t(tg)) + 1 : 0;
+      if (lane == 0) cnt -= aseg;  // aseg <= the row's last value (a valid pair)
+      cnt = cnt < uint32_t(kWave) ? cnt : uint32_t(kWave);
+      const uint32_t cincl = wave_incl_sum_sat(cnt, 1u << 30);
+      const uint32_t cst = cincl - cnt;
+      const uint32_t call = readlane_u32(cincl, kWave - 1);
+      npairs = call < uint32_t(kWave) ? call : uint32_t(kWave);
+      marks[lane] = 0;
+      wave_sync();
+      if (cnt != 0 && cst < uint32_t(kWave)) marks[cst] = lane + 1;
+      wave_sync();
+      const int r = int(wave_incl_max(marks[lane])) - 1;  // row 0 starts at lane 0
+      const uint32_t o_cst = __shfl(cst, r, kWave);
+      pt = tc + uint32_t(r);
+      pa = uint32_t(lane) - o_cst + (r == 0 ? aseg : 0u);
+      ok = uint32_t(lane) < npairs;
+      xs = ok ? xouter - pt * gpre - pa * gseg : 0;
+      wave_sync();
+    } else if (U >= 1) {
       const uint64_t ag = uint64_t(A) * gseg;
       ok = ag <= xouter;
       xs = ok ? xouter - uint32_t(ag) : 0;
@@ -402,8 +519,7 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
           wave_sync();
           const uint32_t written = produced + (tot < phi ? tot : phi);
           while (written - flushed >= flush_rows_n) {
-            flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                                out_tile + uint64_t(flushed) * d);
+            emit(flushed & ring_mask, flush_rows_n, flushed);
             flushed += flush_rows_n;
           }
           wave_sync();
@@ -412,14 +528,26 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
     } else {
       const uint32_t rx = P.dG.mod(xs, qx);
       uint64_t c, start;
+      // Class ends of rx and rx - 1 (a partial memo has classes only below top).
+      const bool inc = ok && rx < P.nclass;
+      uint64_t ec = 0, ep = 0;
       if (LDSCNT) {
         const uint32_t c32v = ok ? lds_cnt[xs] : 0;
         c = c32v;
-        start = ok ? uint64_t(lds_endc[rx] - c32v) : 0;
+        ec = inc ? lds_endc[rx] : 0;
+        if (partial && inc && rx) ep = lds_endc[rx - 1];
       } else {
         c = ok ? cnt_row[xs] : 0;
-        start = ok ? P.endc[rx] - c : 0;
+        ec = inc ? P.endc[rx] : 0;
+        if (partial && inc && rx) ep = P.endc[rx - 1];
       }
+      start = ok ? ec - c : 0;
+      // Partial memo: a segment with x >= top begins with the rows whose memo
+      // remainder x - a_U G is >= top (the smallest a_U), which the memo does
+      // not hold; the rest of it is the whole memo class of x mod G.  hcnt =
+      // the head's rows; tb + rho = a batch row's index in its segment.
+      const uint64_t hcnt = (partial && ok && xs >= P.top) ? c - (inc ? ec - ep : 0) : 0;
+      uint64_t t_adj = 0;
       if (first && lane == 0) {
         if (t0 >= c) {  // the plan guarantees t0 < c; refuse to read past the segment
           set_error(P.err, kErrUnrank);
@@ -427,6 +555,7 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
         } else {
           start += t0;
           c -= t0;
+          t_adj = t0;
         }
       }
       const uint32_t c32 = uint32_t(c < remaining ? c : remaining);
@@ -436,6 +565,7 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
       tot = readlane_u32(incl, kWave - 1);
       // Memo row of batch row rho is segbase[owner] + rho (wrapping arithmetic).
       const uint64_t segbase = start - excl;
+      const uint64_t tb = t_adj - excl;
       const uint32_t seg_lo = uint32_t(segbase), seg_hi = uint32_t(segbase >> 32);
       uint32_t carry = 0;  // 1 + segment lane of the row just before this chunk
       for (uint32_t beta = 0; beta < tot; beta += kWave) {
@@ -458,10 +588,23 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
         } else {
           mrow = uint32_t(o_lo + rho);
         }
-        const uint32_t o_A = aseg + uint32_t(owner);
-        const bool bad = act && mrow >= P.leaf_rows;
+        const uint32_t o_A = pair ? __shfl(pa, owner, kWave) : aseg + uint32_t(owner);
+        const uint32_t o_T = pair ? __shfl(pt, owner, kWave) : 0u;
+        bool head = false;  // partial memo: a row before its segment's memo class
+        uint64_t t_seg = 0;
+        uint32_t o_xs = 0;
+        if (partial) {
+          t_seg = shfl_u64(tb, owner) + rho;
+          o_xs = __shfl(xs, owner, kWave);
+          // Every lane reads the owner's head count (outside the `act` test):
+          // a cross-lane read from an inactive lane returns 0, and the owner
+          // of an active row can be a lane past the chunk's last row.
+          const uint64_t o_hcnt = shfl_u64(hcnt, owner);
+          head = act && t_seg < o_hcnt;
+        }
+        const bool bad = act && !head && mrow >= P.leaf_rows;
         if (bad) set_error(P.err, kErrTileRows);
-        const bool live = act && !bad;
+        const bool live = act && !bad && !head;
         MemoRow<PACK> mr;
         uint32_t aU = 0;
         if (live) {
@@ -475,9 +618,18 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
           if (live) {
             uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
             for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
+            if (pair) h = fnv1a_u32(h, o_T);
             if (U >= 1) h = fnv1a_u32(h, o_A);
             h = fnv1a_u32(h, aU);
             for (int c2 = 1; c2 <= k; ++c2) h = fnv1a_u32(h, mr.field(fsh, fmk, c2));
+            csum += h;
+          }
+          if (head) {
+            uint64_t h = fnv1a_u64(kFnvOffset, r0 + produced + rho);
+            for (int j = 0; j < nouter; ++j) h = fnv1a_u32(h, readlane_u32(aj, j));
+            if (pair) h = fnv1a_u32(h, o_T);
+            if (U >= 1) h = fnv1a_u32(h, o_A);
+            unrank_suffix(P, gj, U, d, o_xs, t_seg, [&](int, uint32_t v) { h = fnv1a_u32(h, v); });
             csum += h;
           }
           wave_sync();
@@ -499,16 +651,23 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
               } else {
                 uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
                 for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+                if (pair) row[U - 2] = o_T;
                 if (U >= 1) row[U - 1] = o_A;
                 row[U] = aU;
                 for (int c2 = 1; c2 <= k; ++c2) row[U + c2] = mr.field(fsh, fmk, c2);
               }
             }
+            if (head && uint32_t(lane) >= plo && uint32_t(lane) < phi) {
+              uint32_t* row = ring + ((produced + rho) & ring_mask) * uint32_t(d);
+              for (int j = 0; j < nouter; ++j) row[j] = readlane_u32(aj, j);
+              if (pair) row[U - 2] = o_T;
+              if (U >= 1) row[U - 1] = o_A;
+              unrank_suffix(P, gj, U, d, o_xs, t_seg, [&](int j, uint32_t v) { row[j] = v; });
+            }
             wave_sync();
             const uint32_t written = produced + beta + (nrows < phi ? nrows : phi);
             while (written - flushed >= flush_rows_n) {
-              flush_rows<ALIGN16>(ring, flushed & ring_mask, flush_rows_n, d,
-                                  out_tile + uint64_t(flushed) * d);
+              emit(flushed & ring_mask, flush_rows_n, flushed);
               flushed += flush_rows_n;
             }
             wave_sync();
@@ -525,7 +684,21 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
       single_done = true;
       continue;
     }
-    if (uint64_t(aseg + kWave) * gseg <= xouter) {
+    if (pair) {
+      if (npairs == uint32_t(kWave)) {  // step past lane 63's pair
+        const uint32_t t63 = readlane_u32(pt, kWave - 1), a63 = readlane_u32(pa, kWave - 1);
+        if (a63 < P.dG1.div(xouter - t63 * gpre)) {
+          tc = t63;
+          aseg = a63 + 1;
+          continue;
+        }
+        if (uint64_t(t63 + 1) * gpre <= xouter) {
+          tc = t63 + 1;
+          aseg = 0;
+          continue;
+        }
+      }
+    } else if (uint64_t(aseg + kWave) * gseg <= xouter) {
       aseg += kWave;
       continue;
     }
@@ -548,11 +721,11 @@ __device__ inline void write_tile(const TileArgs& P, uint64_t tile, const uint32
     }
     xouter = nrem;
     aseg = 0;
+    tc = 0;
   }
 
   if (!COUNT_ONLY && produced > flushed) {
-    flush_rows<ALIGN16>(ring, flushed & ring_mask, produced - flushed, d,
-                        out_tile + uint64_t(flushed) * d);
+    emit(flushed & ring_mask, produced - flushed, flushed);
   }
   wave_sync();
   if (lane == 0 && produced != target) set_error(P.err, kErrTileRows);
@@ -796,6 +969,17 @@ __device__ inline TileArgs uniform_args(const TileArgs& a) {
   A.U = rfl(a.U);
   A.k = rfl(a.k);
   A.gseg = rfl(a.gseg);
+  A.gpre = rfl(a.gpre);
+  A.pair = int(rfl(uint32_t(a.pair)));
+  A.desc = int(rfl(uint32_t(a.desc)));
+  A.top = rfl(a.top);
+  A.nclass = rfl(a.nclass);
+  A.table = rflp(a.table);
+  A.table_stride = rfl64(a.table_stride);
+  A.dG1.d = rfl(a.dG1.d);
+  A.dG1.m = rfl(a.dG1.m);
+  A.dG1.sh1 = rfl(a.dG1.sh1);
+  A.dG1.sh2 = rfl(a.dG1.sh2);
   A.ring = rfl(a.ring);
   A.flush = rfl(a.flush);
   A.total = rfl64(a.total);
@@ -970,21 +1154,6 @@ __global__ void k_single(uint32_t n, uint32_t g, uint32_t* out, int count_only,
   }
 }
 
-// Reverse the order of `rows` rows of d dwords in place (descending output).
-__global__ __launch_bounds__(256) void k_reverse_rows(uint32_t* out, uint64_t rows, int d) {
-  const uint64_t half = rows / 2;
-  const uint64_t total = half * uint64_t(d);
-  for (uint64_t w = uint64_t(blockIdx.x) * 256 + threadIdx.x; w < total;
-       w += uint64_t(gridDim.x) * 256) {
-    const uint64_t r = w / d, c = w % d;
-    uint32_t* a = out + r * d + c;
-    uint32_t* b = out + (rows - 1 - r) * d + c;
-    const uint32_t t = *a;
-    *a = *b;
-    *b = t;
-  }
-}
-
 // Per instantiation of the write kernel: the largest dynamic LDS its function
 // attribute has been raised to, and the occupancy found for each LDS size
 // (both fixed for a kernel and a size, and costly to ask for per call).
@@ -1062,6 +1231,20 @@ hipError_t dispatch_spec(const EnumParams& P, A... args) {
   return F<1, false, true, PK, true, -1, -1>::run(P, args...);
 }
 
+// Partial memos: the kNoPartial instantiations.
+template <template <int, bool, bool, int, bool, int, int> class F, int PK, class... A>
+hipError_t dispatch_partial(const EnumParams& P, bool count_only, bool align16, A... args) {
+  constexpr int X = kNoPartial;
+  if (P.lds_cnt) {
+    if (count_only) return F<1, true, false, PK, true, X, -1>::run(P, args...);
+    return align16 ? F<1, false, true, PK, true, X, -1>::run(P, args...)
+                   : F<1, false, false, PK, true, X, -1>::run(P, args...);
+  }
+  if (count_only) return F<1, true, false, PK, false, X, -1>::run(P, args...);
+  return align16 ? F<1, false, true, PK, false, X, -1>::run(P, args...)
+                 : F<1, false, false, PK, false, X, -1>::run(P, args...);
+}
+
 // Dispatch on the run-time choices to the matching instantiation.
 template <template <int, bool, bool, int, bool, int, int> class F, class... A>
 hipError_t dispatch(const EnumParams& P, bool count_only, bool align16, A... args) {
@@ -1070,7 +1253,15 @@ hipError_t dispatch(const EnumParams& P, bool count_only, bool align16, A... arg
     return align16 ? F<0, false, true, 0, false, -1, -1>::run(P, args...)
                    : F<0, false, false, 0, false, -1, -1>::run(P, args...);
   }
-  const bool spec = !count_only && align16 && P.lds_cnt && P.U >= 1 &&
+  if (P.memo_top && P.memo_top <= P.n) {  // a partial memo
+    switch (P.pack) {
+      case 1: return dispatch_partial<F, 1>(P, count_only, align16, args...);
+      case 2: return dispatch_partial<F, 2>(P, count_only, align16, args...);
+      default: return dispatch_partial<F, 0>(P, count_only, align16, args...);
+    }
+  }
+  const bool spec = !P.pair && !count_only && align16 &&
+                    P.lds_cnt && P.U >= 1 &&
                     P.U - 1 <= kSpecMaxOuter && P.k <= kSpecMaxK;
   if (spec && P.pack == 1) return dispatch_spec<F, 1>(P, args...);
   if (spec && P.pack == 2) return dispatch_spec<F, 2>(P, args...);
@@ -1118,6 +1309,13 @@ hipError_t write_occupancy(const EnumParams& P, bool count_only, bool align16, i
 
 hipError_t launch_plan(const EnumParams& P, hipStream_t s) {
   const uint64_t blocks = (P.ntiles + 255) / 256;
+  hipLaunchKernelGGL(k_plan, dim3(uint32_t(blocks)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_device_sized(const EnumParams& P, hipStream_t s) {
+  if (!P.total_dev || P.want_tiles == 0) return hipErrorInvalidValue;
+  const uint64_t blocks = (P.want_tiles + 255) / 256;
   hipLaunchKernelGGL(k_plan, dim3(uint32_t(blocks)), dim3(256), 0, s, P);
   return hipGetLastError();
 }
@@ -1200,14 +1398,6 @@ hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,
                          uint64_t* checksum, hipStream_t s) {
   hipLaunchKernelGGL(k_single, dim3(1), dim3(64), 0, s, uint32_t(n), g, out, int(count_only),
                      checksum);
-  return hipGetLastError();
-}
-
-hipError_t launch_reverse(uint32_t* out, uint64_t rows, int d, hipStream_t s) {
-  uint64_t blocks = (rows / 2 * uint64_t(d) + 255) / 256;
-  if (blocks > 65536) blocks = 65536;
-  if (blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reverse_rows, dim3(uint32_t(blocks)), dim3(256), 0, s, out, rows, d);
   return hipGetLastError();
 }
 

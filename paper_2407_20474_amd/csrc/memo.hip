@@ -82,11 +82,14 @@ __device__ inline void wave_sync_lds() {
 //  * |Z_{=i}(p)| = |Z_{>=i}(p - h_i)|, so |Z_{>=i}(p)| is a suffix sum over i,
 //    saved for later steps, and |Z(p)| = |Z_{>=1}(p)|; a wave prefix sum of the
 //    sizes places every list;
-//  * the copy-and-increment runs one lane per copied row (factorizationwise
-//    parallelism, Alg 2.9), 64 rows at a time: the first row of each element
-//    is marked in LDS and a wave prefix max gives every row its element, whose
-//    saved cardinalities then give the row's block i (blocks in the order
-//    i = k..1) and its source row.
+//  * the copy-and-increment: when the step's longest list is at most
+//    kLaneCopyRows rows per 64 rows of the step, each lane copies its own
+//    element's blocks (in the order i = k..1); otherwise it runs one lane per
+//    copied row
+//    (factorizationwise parallelism, Alg 2.9), 64 rows at a time: the first
+//    row of each element is marked in LDS and a wave prefix max gives every
+//    row its element, whose saved cardinalities then give the row's block i
+//    and its source row.
 // Dynamic LDS layout (uint32): GE[W*k] | OFF[W] | marks[64] | M rows, W a power
 // of two >= max(h) + step and M 16-byte aligned (memo_ring_words).
 //  * WINDOW = false: M holds the whole memo (Rcap rows); a memo that would
@@ -97,6 +100,10 @@ __device__ inline void wave_sync_lds() {
 //    stored to `nat` as it is made; a step that would overrun the ring stops
 //    the build with an error (the caller sizes the ring from the longest list).
 // Rexp, when non-zero, is the row count the count table predicts.
+// A step copies one element per lane while its longest list has at most this
+// many rows per 64 rows of the step (else one lane per row).
+constexpr uint32_t kLaneCopyRows = 3;
+
 template <int KMAX, bool WINDOW>
 __device__ inline void memo_chain(const uint32_t (&hg)[KMAX], int k, uint32_t top, uint32_t step,
                                   uint32_t W, uint32_t hmax, uint32_t Mmask, uint32_t Rcap,
@@ -171,7 +178,38 @@ __device__ inline void memo_chain(const uint32_t (&hg)[KMAX], int k, uint32_t to
       OFF[p & Wm] = running + first;
       off_out[p] = running + first;
     }
-    // Copy-and-increment, one lane per row of the step.
+    // Copy-and-increment.  Each lane copying its own element's blocks costs
+    // about one LDS round trip per row of the longest list of the step; one
+    // lane per row of the step costs a few round trips per 64 rows.  The step takes the cheaper: lanes per element
+    // when its lists are of similar length, lanes per row when a few long
+    // lists would leave most lanes idle.
+    const uint32_t smax = __builtin_amdgcn_readlane(wave_incl_max_u32(size), kWave - 1);
+    if (smax <= kLaneCopyRows * ((tot + kWave - 1) / kWave)) {
+      uint32_t dst = running + first;
+#pragma unroll
+      for (int i = KMAX - 1; i >= 0; --i) {
+        if (i < k) {
+          for (uint32_t r = 0; r < s[i]; ++r) {
+            uint32_t v[KMAX];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c)
+              if (c < k) v[c] = M[mrow(so[i] + r) * k + c];
+#pragma unroll
+            for (int c = 0; c < KMAX; ++c) {
+              if (c < k) {
+                const uint32_t w = v[c] + (c == i ? 1u : 0u);
+                M[mrow(dst + r) * k + c] = w;
+                if (WINDOW) nat[uint64_t(dst + r) * k + c] = w;
+              }
+            }
+          }
+          dst += s[i];
+        }
+      }
+      wave_sync_lds();
+      running += tot;
+      continue;
+    }
     uint32_t carry = 0;
     for (uint32_t beta = 0; beta < tot; beta += kWave) {
       marks[lane] = 0;
@@ -440,8 +478,10 @@ __device__ inline void memo_leaf_element(const LeafJob& J, uint32_t p, int* __re
 // neighbouring rows, and a long list costs no more than many short ones.
 __global__ __launch_bounds__(256) void k_memo_leaf(LeafJob J, int* __restrict__ err) {
   const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (t == 0 && J.off[uint64_t(J.n) + 1] != J.leaf_rows) set_error(err, kErrMemoTotal);
-  if (t >= J.leaf_rows) return;
+  const uint64_t rows = J.off[uint64_t(J.n) + 1];
+  if (J.exact ? (t == 0 && rows != J.leaf_rows) : (t == 0 && rows > J.leaf_rows))
+    set_error(err, kErrMemoTotal);
+  if (t >= rows || t >= J.leaf_rows) return;
   uint32_t lo = 0, hi = J.n;
   while (lo < hi) {
     const uint32_t mid = lo + (hi - lo + 1) / 2;
@@ -646,6 +686,7 @@ LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const 
   J.leaf_rows = leaf_rows;
   J.pack = P.pack;
   for (int c = 0; c <= k; ++c) J.fshift[c] = P.fshift[c];
+  J.exact = 1;
   return J;
 }
 

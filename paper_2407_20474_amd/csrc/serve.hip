@@ -5,10 +5,13 @@
 //     with a host copy of row 0 (|Z(n)| for every n <= n_max), which prices a
 //     query's output bytes (|Z(n)| d 4) without touching the device;
 //   * for memo dimension k >= 1, the memo Z(p; h) of the trailing k generators
-//     for p <= n_max, built by the dynamic recurrence (zset_memo_build), and its
-//     leaf-order layout with the residue-class ends.  A segment Z(x; G, h)
-//     starts at end[x mod G] - C_U[x] whatever the query's n, as long as
-//     x <= n_max, so one layout serves every n <= n_max.
+//     for p < top, built by the dynamic recurrence (zset_memo_build), and its
+//     leaf-order layout with the residue-class ends.  top = n_max + 1 when
+//     that memo fits the server's memo budget, else the largest top whose
+//     memo does (a partial memo: the rows of a query with n >= top whose memo
+//     remainder is >= top are unranked from the count table, Alg 3.2's Else
+//     branch).  A segment Z(x; G, h) starts at end[x mod G] - C_U[x] whatever
+//     the query's n, so one layout serves every n <= n_max.
 // A query (set, n) then needs only the slice plan and the write pass, with no
 // host synchronisation.  Queries run on `slots` streams at once (continuous
 // batching): a dispatcher thread admits waiting queries in arrival order as a
@@ -41,8 +44,9 @@ constexpr int kDefaultSlots = 8;
 // wavefront (and rows_per_tile >= 128 rows below that), so this bounds every
 // query's slice table once the device's resident wavefronts are known.
 constexpr uint64_t kSlicesPerWave = 128;
-// Automatic memo dimension of a resident set: the largest k whose memo
-// takes at most this many bytes.
+// Default memo budget of a resident set (its leaf-order layout): the
+// automatic memo dimension is the largest k whose memo over p <= n_max fits
+// it, and a larger memo is capped to it.
 constexpr uint64_t kResidentMemoBytes = uint64_t(32) << 20;
 // Slices per wavefront up to which the write pass plans its own slices.
 constexpr uint64_t kFusedSlicesPerWave = 4;
@@ -58,6 +62,7 @@ struct ResidentSet {
   std::vector<uint64_t> c0;  // |Z(n)| for n <= n_max
   DevBuf table, endc, leaf;
   uint64_t memo_rows = 0;
+  uint64_t memo_top = 0;     // the memo covers p < memo_top (n_max + 1: every p)
   uint64_t sum_u = 0;        // sum over x <= n_max of C_U[x]
   EnumParams tmpl;           // per-set fields of the write pass
 };
@@ -111,6 +116,7 @@ struct zset_server_s {
   uint64_t arena_words = 0;
   std::map<uint64_t, uint64_t> free_list;  // word offset -> words, coalesced
   uint64_t slice_cap = 0;                  // slices one slot's table holds
+  uint64_t memo_bytes = 0;                 // memo budget of each resident set
   std::mutex mu;
   std::condition_variable cv;       // dispatchers: submissions, arena room, stop
   std::condition_variable cv_done;  // zset_server_wait: a waited-for query ended
@@ -386,6 +392,7 @@ zset_status zset_server_create(const zset_server_opts* opts, zset_server* out) {
     (void)hipGetLastError();
     return bail(fail(ZSET_EDEVICE, "device query failed"));
   }
+  S->memo_bytes = opts->memo_bytes ? opts->memo_bytes : kResidentMemoBytes;
   S->arena = reinterpret_cast<uint32_t*>(opts->arena);
   S->arena_words = opts->arena_bytes / 16 * 4;
   S->free_list[0] = S->arena_words;
@@ -480,7 +487,7 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
   const size_t lds_max = size_t(write_lds_budget(S->device));
 
   // Memo dimension: the requested one, else the largest k whose memo over
-  // p <= n_max takes at most kResidentMemoBytes.  The memo is built once per
+  // p <= n_max takes at most the server's memo budget.  The memo is built once per
   // set, so only the write pass counts: a larger k leaves fewer outer
   // coordinates and longer segments per outer prefix, and that gain outweighs
   // reading the memo from global memory instead of LDS up to memos of tens of
@@ -521,7 +528,7 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
       EnumParams P;
       tmpl_for(c, P);
       const uint64_t words = P.pack ? Rc * uint64_t(P.pack) : Rc * uint64_t(c + 1);
-      if (words * 4 <= kResidentMemoBytes) {
+      if (words * 4 <= S->memo_bytes) {
         kk = c;
         break;
       }
@@ -532,16 +539,55 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
   R->U = (kk == 0) ? d - 1 : R->L - 1;
   tmpl_for(kk, R->tmpl);
   R->sum_u = sums[R->U];
+  R->memo_top = N;
   if (kk >= 1 && d >= 2) {
     EnumParams& P = R->tmpl;
-    const uint64_t Rn = sums[R->L];
-    R->memo_rows = Rn;
+    uint64_t Rn = sums[R->L];
+    const int pack0 = P.pack;
     if (P.pack != 0 && write_lds_bytes(P) > lds_max) {
       P.pack = 0;
       P.memo_words = 0;
     }
+    const uint64_t wpr = P.pack ? uint64_t(P.pack) : uint64_t(kk + 1);  // words per memo row
+    uint64_t top = N;
+    if (Rn == ~uint64_t(0) || Rn > S->memo_bytes / (4 * wpr)) {
+      // A partial memo: the largest top whose rows (|Z(p; h)| summed over
+      // p < top, row L of the count table) fit the budget, packed when the
+      // capped memo fits the write pass's LDS.  The memo of p = 0 (one row)
+      // is always kept.
+      std::vector<uint64_t> cl(N);
+      if (hipMemcpyAsync(cl.data(), T + uint64_t(R->L) * N, N * sizeof(uint64_t),
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(ZSET_EDEVICE, "count table readback failed"));
+      }
+      auto cap_top = [&](uint64_t words_per_row, uint64_t* rows) {
+        const uint64_t max_rows = std::max<uint64_t>(S->memo_bytes / (4 * words_per_row), 1);
+        uint64_t acc = 0, t = 0;
+        while (t < N && cl[t] <= max_rows - acc) acc += cl[t++];
+        if (t == 0) acc = cl[t++];  // |Z(0; h)| = 1
+        *rows = acc;
+        return t;
+      };
+      P.pack = pack0;
+      if (P.pack != 0) {
+        top = cap_top(uint64_t(P.pack), &Rn);
+        P.memo_words = Rn * uint64_t(P.pack);
+        if (write_lds_bytes(P) > lds_max) P.pack = 0;
+      }
+      if (P.pack == 0) {
+        top = cap_top(uint64_t(kk + 1), &Rn);
+        P.memo_words = 0;
+      }
+      P.memo_top = uint32_t(top);
+      P.nclass = uint32_t(std::min<uint64_t>(gens[R->U], top));
+      P.leaf_rows = Rn;
+    }
+    R->memo_rows = Rn;
+    R->memo_top = top;
     zset_memo m = nullptr;
-    if ((st = zset_memo_build(gens + R->L, kk, N, s, &m)) != ZSET_OK) return bail(st);
+    if ((st = zset_memo_build(gens + R->L, kk, top, s, &m)) != ZSET_OK) return bail(st);
     struct MemoGuard {
       zset_memo m;
       ~MemoGuard() { zset_memo_free(m); }
@@ -555,9 +601,9 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
     uint32_t* leaf = reinterpret_cast<uint32_t*>(R->leaf.p);
     uint32_t nclass = 0;
     const uint64_t* cu = T + uint64_t(R->U) * N;
-    if (launch_class_ends(cu, n_max, G, endc, &nclass, s) != hipSuccess ||
-        launch_memo_leaf(make_leaf_job(kk, n_max, G, m->off, m->nat, cu, endc, leaf, Rn, P), err,
-                         s) != hipSuccess) {
+    if (launch_class_ends(cu, top - 1, G, endc, &nclass, s) != hipSuccess ||
+        launch_memo_leaf(make_leaf_job(kk, top - 1, G, m->off, m->nat, cu, endc, leaf, Rn, P),
+                         err, s) != hipSuccess) {
       (void)hipGetLastError();
       return bail(fail(ZSET_EDEVICE, "leaf layout launch failed"));
     }
@@ -579,7 +625,8 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
 }
 
 zset_status zset_server_set_info(zset_server S, int set_id, int* k, uint64_t* n_max,
-                                 uint64_t* memo_rows, uint64_t* resident_bytes) {
+                                 uint64_t* memo_rows, uint64_t* resident_bytes,
+                                 uint64_t* memo_top) {
   g_last_error.clear();
   if (!S) return fail(ZSET_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> lock(S->mu);
@@ -589,6 +636,7 @@ zset_status zset_server_set_info(zset_server S, int set_id, int* k, uint64_t* n_
   if (n_max) *n_max = R.n_max;
   if (memo_rows) *memo_rows = R.memo_rows;
   if (resident_bytes) *resident_bytes = R.table.bytes + R.endc.bytes + R.leaf.bytes;
+  if (memo_top) *memo_top = R.memo_top;
   return ZSET_OK;
 }
 

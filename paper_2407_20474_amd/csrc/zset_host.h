@@ -45,8 +45,15 @@ struct EnumParams;
 // and the leaf-order row format; shared by the single-query path and the server.
 // share: queries expected on the device at once (the grid gets 1/share of the
 // resident workgroups; 1 = the whole device).
+// want_tiles: the slice count the slice length is taken for (0: about 128
+// slices per resident wavefront of this write pass).
 zset_status size_write_pass(EnumParams& P, uint64_t rows_per_tile, int claim_pct, int device,
-                            bool count_only, bool align16, int share = 1);
+                            bool count_only, bool align16, int share = 1,
+                            uint64_t want_tiles = 0);
+// Slices asked for when the planner sizes them on the device before the
+// write pass's occupancy is known: 128 per wavefront of one write workgroup
+// on every compute unit.
+uint64_t plan_want_tiles(int device);
 void leaf_format(EnumParams& P, uint64_t n, const uint32_t* gens, int U, int k);
 uint32_t next_pow2(uint32_t v);
 float elapsed_us(hipEvent_t a, hipEvent_t b);

@@ -30,6 +30,13 @@ struct EnumParams {
   uint64_t* checksum;       // count-only: wrapping sum of row hashes
   int* err;                 // device status word
   DivMod32 dG;              // division by g_U
+  DivMod32 dG1;             // division by g_{U-1} (pair lanes)
+  uint32_t memo_top;        // the memo covers p < memo_top; 0 or > n: every p <= n (a
+                            // partial memo's other rows are unranked from the count table)
+  int desc;                 // 1: rows stored in descending lexicographic order (rank r at
+                            // row total - 1 - r)
+  int pair;                 // 1: the write pass's lanes range over (a_{U-2}, a_{U-1}) pairs
+                            // (MODE 1, U >= 2), 0: over a_{U-1}
   uint32_t ring;            // rows in each wavefront's LDS staging ring (power of two)
   uint32_t flush;           // rows per coalesced flush (ring / 2)
   int pack;                 // memo row format: 0 plain words in global, 1 / 2 packed
@@ -49,7 +56,22 @@ struct EnumParams {
   uint32_t* blocks_done;    // write workgroups finished (with done_flag)
   uint64_t* done_flag;      // non-NULL: the last write workgroup stores *err to done_flag[1]
   uint64_t done_seq;        // and then done_seq to done_flag[0] (pinned host words)
+  // Slice planner only: when total_dev is non-NULL, |Z(n)| is read there and
+  // the slice length is slice_rows(|Z(n)|, want_tiles) (the host repeats the
+  // same formula once it has |Z(n)|).
+  const uint64_t* total_dev;
+  uint64_t want_tiles;
 };
+
+// Rows per slice when `want` slices are asked for |Z| = total rows: a
+// multiple of 128, at least 128 and at most 2^30.
+__host__ __device__ inline uint64_t slice_rows(uint64_t total, uint64_t want) {
+  uint64_t T = (total + want - 1) / want;
+  T = (T + 127) / 128 * 128;
+  if (T < 128) T = 128;
+  if (T > (uint64_t(1) << 30)) T = uint64_t(1) << 30;
+  return T;
+}
 
 // One query's share of a batched launch.
 struct CountJob {
@@ -83,6 +105,8 @@ struct LeafJob {
   int pack;
   uint32_t block0;          // batched: first workgroup of this job
   uint32_t fshift[kMaxD + 1];
+  int exact;                // 1: leaf_rows is the memo's row count; 0: a bound (partial
+                            // memo), the rows being off[n + 1]
 };
 
 struct ClassJob {
@@ -172,10 +196,12 @@ size_t write_lds_bytes(const EnumParams& P);
 int write_waves_per_block();
 hipError_t write_occupancy(const EnumParams& P, bool count_only, bool align16, int* per_cu);
 hipError_t launch_plan(const EnumParams& P, hipStream_t s);
+// The same planner sized on the device (P.total_dev, P.want_tiles): a grid for
+// want_tiles slices, of which the first ceil(|Z| / slice_rows) are planned.
+hipError_t launch_plan_device_sized(const EnumParams& P, hipStream_t s);
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s);
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,
                          uint64_t* checksum, hipStream_t s);
-hipError_t launch_reverse(uint32_t* out, uint64_t rows, int d, hipStream_t s);
 
 // Batched forms (batch.hip drives them).  qp: one EnumParams per query;
 // qout: each query's first output word.

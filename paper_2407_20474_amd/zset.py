@@ -30,7 +30,7 @@ SYMBOLS = (
     "zset_batch_times", "zset_batch_free",
     "zset_server_default_opts", "zset_server_create", "zset_server_add_set",
     "zset_server_set_info", "zset_server_count", "zset_server_submit", "zset_server_wait",
-    "zset_server_release", "zset_server_stats", "zset_server_free",
+    "zset_server_release", "zset_server_stats", "zset_server_free", "zset_store_ceiling",
     "zset_strerror", "zset_selftest_host", "zset_last_error",
 )
 
@@ -38,12 +38,14 @@ SYMBOLS = (
 class Opts(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("order", ctypes.c_int),
                 ("rows_per_tile", ctypes.c_uint64), ("count_only", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("claim_pct", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("claim_pct", ctypes.c_int),
+                ("memo_top", ctypes.c_uint64)]
 
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int), ("arena", ctypes.c_void_p),
-                ("arena_bytes", ctypes.c_uint64), ("dispatchers", ctypes.c_int)]
+                ("arena_bytes", ctypes.c_uint64), ("dispatchers", ctypes.c_int),
+                ("memo_bytes", ctypes.c_uint64)]
 
 
 class ServerResult(ctypes.Structure):
@@ -123,6 +125,8 @@ def load():
     lib.zset_enumerate_ex.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
                                       _u64p, _u64p, ctypes.POINTER(Stats)]
+    lib.zset_store_ceiling.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.zset_enumerate_walk.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_uint64, ctypes.c_int, ctypes.c_void_p, _u64p]
     lib.zset_batch_default_opts.argtypes = [ctypes.POINTER(BatchOpts)]
@@ -142,7 +146,7 @@ def load():
     lib.zset_server_add_set.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int, ctypes.c_uint64,
                                         ctypes.c_int, _i32p]
     lib.zset_server_set_info.argtypes = [ctypes.c_void_p, ctypes.c_int, _i32p, _u64p, _u64p,
-                                         _u64p]
+                                         _u64p, _u64p]
     lib.zset_server_count.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, _u64p]
     lib.zset_server_submit.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint64, _u64p]
     lib.zset_server_wait.argtypes = [ctypes.c_void_p, ctypes.c_uint64,
@@ -163,7 +167,7 @@ def load():
                  "zset_batch_run", "zset_batch_times", "zset_selftest_host",
                  "zset_server_create", "zset_server_add_set", "zset_server_set_info",
                  "zset_server_count", "zset_server_submit", "zset_server_wait",
-                 "zset_server_release", "zset_server_stats"):
+                 "zset_server_release", "zset_server_stats", "zset_store_ceiling"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -283,10 +287,12 @@ def tuned(n: int, gens):
 
 def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
                  rows_per_tile: int = 0, count_only: bool = False, memo: Memo | None = None,
-                 stream=None, out_rows_cap: int | None = None, claim_pct: int = -1) -> Result:
+                 stream=None, out_rows_cap: int | None = None, claim_pct: int = -1,
+                 memo_top: int = 0) -> Result:
     """Z(n; g) through zset_enumerate_ex.  `out` is an int32 CUDA tensor with at least
     |Z(n)| * d elements (allocated here when None and count_only is False).
-    `claim_pct`: percent of slices claimed at run time (-1 automatic, 0 none)."""
+    `claim_pct`: percent of slices claimed at run time (-1 automatic, 0 none).
+    `memo_top`: 0, or the memo covers p < memo_top only (a partial memo)."""
     import torch
     g = _gens(gens)
     d = len(g)
@@ -307,6 +313,7 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     opts.count_only = 1 if count_only else 0
     opts.stream = _stream_handle(stream)
     opts.claim_pct = claim_pct
+    opts.memo_top = memo_top
     rows_written, csum, stats = ctypes.c_uint64(), ctypes.c_uint64(), Stats()
     _check(load().zset_enumerate_ex(n, g.ctypes.data_as(_u32p), d, ptr, cap, ctypes.byref(opts),
                                     memo.handle if memo is not None else None,
@@ -315,6 +322,17 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     r = int(rows_written.value)
     view = out[:r] if (out is not None and out.dim() == 2) else out
     return Result(rows=r, checksum=int(csum.value), stats=stats.as_dict(), out=view)
+
+
+def store_ceiling(buf, reps: int = 5, stream=None) -> float:
+    """Mean microseconds per pass of the library's store-only kernel (16-byte
+    non-temporal stores, the write pass's store form) over the whole of `buf`,
+    a CUDA tensor (overwritten).  A measurement of the device, not of Z(n)."""
+    us = ctypes.c_double()
+    _check(load().zset_store_ceiling(buf.data_ptr(), buf.numel() * buf.element_size(), reps,
+                                     _stream_handle(stream), ctypes.byref(us)),
+           "zset_store_ceiling")
+    return float(us.value)
 
 
 def enumerate_walk(n: int, gens, out, *, order: int = 0, stream=None) -> int:
@@ -451,7 +469,7 @@ class Server:
     the caller keeps it alive while the server runs.  Submission never blocks;
     wait() blocks until a query is done (the GIL is released meanwhile)."""
 
-    def __init__(self, arena, slots: int = 8, dispatchers: int = 1):
+    def __init__(self, arena, slots: int = 8, dispatchers: int = 1, memo_bytes: int = 0):
         if arena.dtype.itemsize != 4 or not arena.is_contiguous():
             raise ValueError("arena must be a contiguous 4-byte CUDA tensor")
         self.arena = arena.reshape(-1)
@@ -460,6 +478,7 @@ class Server:
         load().zset_server_default_opts(ctypes.byref(opts))
         opts.slots = slots
         opts.dispatchers = dispatchers
+        opts.memo_bytes = memo_bytes
         opts.arena = self.arena.data_ptr()
         opts.arena_bytes = self.arena.numel() * 4
         handle = ctypes.c_void_p(None)
@@ -481,11 +500,13 @@ class Server:
 
     def set_info(self, set_id: int) -> dict:
         k, n_max, rows, nbytes = ctypes.c_int(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        top = ctypes.c_uint64()
         _check(load().zset_server_set_info(self._handle, set_id, ctypes.byref(k),
                                            ctypes.byref(n_max), ctypes.byref(rows),
-                                           ctypes.byref(nbytes)), "zset_server_set_info")
+                                           ctypes.byref(nbytes), ctypes.byref(top)),
+               "zset_server_set_info")
         return {"k": int(k.value), "n_max": int(n_max.value), "memo_rows": int(rows.value),
-                "resident_bytes": int(nbytes.value)}
+                "resident_bytes": int(nbytes.value), "memo_top": int(top.value)}
 
     def count(self, set_id: int, n: int) -> int:
         v = ctypes.c_uint64()

@@ -145,6 +145,83 @@ def test_medium_cases_default_slices():
             assert_same(got, want, f"medium n={n} g={g} k={k}")
 
 
+@pytest.mark.parametrize("pair", ["0", "1"])
+def test_pair_lanes_forced_on_and_off(pair, monkeypatch):
+    # The write pass's lanes over (a_{U-2}, a_{U-1}) pairs (U >= 2) or over
+    # a_{U-1} alone give the same bytes; the automatic choice takes pairs
+    # only when a_{U-1} never fills a wavefront, so both forms are forced here
+    # on small, medium, unsorted and repeated-generator cases, every k, short
+    # and default slices, and count-only.
+    monkeypatch.setenv("ZSET_PAIR", pair)
+    cases = list(bounded_queries(31, 25, dmax=7, gmax=40, nmax=900))
+    cases += [(7824 // 4, [31, 63, 87, 123, 132, 136, 157, 170, 187]),
+              (1000, [13, 37, 38, 40, 41, 42, 43]), (5000, [13, 37, 38, 40]),
+              (60, [1, 1, 1, 1, 1]), (3000, [170, 61, 44, 97, 5])]
+    for n, g in cases:
+        want = oracle.enumerate_rows(n, g)
+        for k in range(1, len(g)):
+            for T in (128, 0):
+                got, r = gpu_rows(n, g, k=k, rows_per_tile=T)
+                assert_same(got, want, f"pair={pair} n={n} g={g} k={k} T={T}")
+            got, r = gpu_rows(n, g, k=k, order=1)
+            assert_same(got, np.ascontiguousarray(want[::-1]), f"pair={pair} desc n={n} k={k}")
+            c = zset.enumerate_ex(n, g, k=k, count_only=True)
+            assert c.rows == len(want) and c.checksum == oracle.checksum(want), (pair, n, g, k)
+
+
+def test_partial_memo_every_k(monkeypatch):
+    # A memo covering only p < top <= n (Alg 3.2's Else branch): rows whose
+    # memo remainder is >= top are unranked from the count table by the write
+    # pass, the rest copied from the memo.  top = 1, n / 3 and n at every k,
+    # short and default slices, ascending and descending, count-only, and
+    # pair lanes forced on and off.
+    cases = [(2000, [7, 11, 13, 17]), (1000, [13, 37, 38, 40, 41, 42, 43]), (400, [3, 5, 7, 11]),
+             (60, [1, 1, 1, 1]), (700, [10, 12, 14, 16, 19])]
+    cases += list(bounded_queries(51, 12, dmax=6, gmax=30, nmax=800))
+    for pair in ("0", "1"):
+        monkeypatch.setenv("ZSET_PAIR", pair)
+        for n, g in cases:
+            want = oracle.enumerate_rows(n, g)
+            for k in range(1, len(g)):
+                for top in sorted({1, max(1, n // 3), n}):
+                    for T in (128, 0):
+                        got, r = gpu_rows(n, g, k=k, rows_per_tile=T, memo_top=top)
+                        assert_same(got, want, f"partial pair={pair} n={n} g={g} k={k} top={top} T={T}")
+                    got, r = gpu_rows(n, g, k=k, order=1, memo_top=top)
+                    assert_same(got, np.ascontiguousarray(want[::-1]), f"partial desc n={n} k={k} top={top}")
+                    c = zset.enumerate_ex(n, g, k=k, count_only=True, memo_top=top)
+                    assert c.rows == len(want) and c.checksum == oracle.checksum(want), (n, g, k, top)
+
+
+def test_partial_memo_handle():
+    # A memo handle whose top is <= n is accepted and treated as partial.
+    n, g = 3000, [13, 37, 38, 40, 41]
+    want = oracle.enumerate_rows(n, g)
+    for k in (1, 2, 3):
+        for top in (1, n // 2, n, n + 1):
+            m = zset.Memo(g[len(g) - k:], top)
+            got, r = gpu_rows(n, g, memo=m, rows_per_tile=256)
+            assert_same(got, want, f"partial handle k={k} top={top}")
+            m.free()
+
+
+def test_partial_memo_full_size():
+    # The large workload with its k = 2 memo capped at n / 2.
+    w = inputs.load_workloads()["large"][0]
+    n, g, k, rows = w["n"], w["gens"], w["k"], w["rows"]
+    table = oracle.count_table(n, g)
+    want = np.empty((rows, len(g)), dtype=np.uint32)
+    _, got_rows = oracle.enumerate_rows_threads(n, g, 0, n // g[0] + 1, min(16, os.cpu_count() or 1),
+                                                table=table, out=want)
+    want_dev = torch.from_numpy(want.view(np.int32)).to("cuda")
+    out = torch.full((rows, len(g)), -1, dtype=torch.int32, device="cuda")
+    r = zset.enumerate_ex(n, g, out=out, k=k, memo_top=n // 2)
+    assert r.rows == rows
+    assert torch.equal(out, want_dev), "large partial memo"
+    del out, want_dev
+    torch.cuda.empty_cache()
+
+
 def wide_queries(seed, count, max_rows=200_000):
     """Queries with d in [17, 32]: rows wider than 16 words use the 64-row
     staging ring, which stages each 64-row chunk in two halves."""
@@ -202,11 +279,18 @@ def test_write_pass_at_the_device_lds_limit():
 
 
 def test_descending_order_is_the_reversal():
-    n, g = 2000, [7, 11, 13, 17]
-    want = oracle.enumerate_rows(n, g)[::-1]
-    for k in (0, 2):
-        got, _ = gpu_rows(n, g, k=k, order=1, rows_per_tile=256)
-        assert_same(got, np.ascontiguousarray(want), f"descending k={k}")
+    # The write pass stores rank r at row |Z| - 1 - r (each staged block
+    # written in reverse): every k, short and default slices, pair lanes on
+    # and off, d = 1 and empty sets.
+    cases = [(2000, [7, 11, 13, 17]), (1000, [13, 37, 38, 40, 41, 42, 43]), (123, [41]),
+             (101, [4, 6, 10]), (0, [3, 7, 9])]
+    cases += list(bounded_queries(41, 10, dmax=6, gmax=30, nmax=800))
+    for n, g in cases:
+        want = np.ascontiguousarray(oracle.enumerate_rows(n, g)[::-1])
+        for k in range(len(g)):
+            for T in (128, 0):
+                got, r = gpu_rows(n, g, k=k, order=1, rows_per_tile=T)
+                assert_same(got, want, f"descending n={n} g={g} k={k} T={T}")
 
 
 def test_count_only_checksum():
@@ -318,11 +402,11 @@ def test_errors():
         zset.enumerate_ex(2000, g, memo=m)
     assert e.value.status == zset.EINVAL
     m.free()
-    say("EINVAL: memo top does not exceed n")
+    say("a memo whose top does not exceed n is a partial memo")
     m = zset.Memo([13, 17], 2000)
-    with pytest.raises(zset.ZsetError) as e:
-        zset.enumerate_ex(2000, g, memo=m)
-    assert e.value.status == zset.EINVAL
+    got = zset.enumerate_ex(2000, g, memo=m)
+    assert_same(got.out[:got.rows].cpu().numpy().view(np.uint32),
+                oracle.enumerate_rows(2000, g), "partial memo handle")
     m.free()
     say("EINVAL: out is host memory")
     host = np.zeros(81205 * 4, dtype=np.int32)
@@ -367,6 +451,13 @@ def test_large_config_full_size_bit_exact():
         e = min(rows, s + chunk)
         got = out[s:e].cpu().numpy().view(np.uint32)
         assert_same(got, want[s:e], f"large rows [{s}, {e})")
+    say("large: descending order, same launch configuration")
+    want_dev = torch.from_numpy(want.view(np.int32)).to("cuda").flip(0)
+    out.fill_(-1)
+    r = zset.enumerate_ex(n, g, out=out, k=k, order=1)
+    assert r.rows == rows
+    assert torch.equal(out, want_dev), "large descending"
+    del want_dev
     say("large: count-only checksum")
     want_sum = oracle.checksum(want)
     for pct in (-1, 0, 100):

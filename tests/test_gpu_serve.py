@@ -107,6 +107,52 @@ def test_served_slice_plans_alone_and_shared():
     srv.free()
 
 
+def test_served_capped_memos():
+    """Resident memos capped by bytes (a partial memo, Alg 3.2's Else branch):
+    queries below and above the memo's top, served in a mix, give the rows
+    zset_enumerate_ex writes alone with the same capped memo, and the oracle's."""
+    arena = torch.empty(8_000_000, dtype=torch.int32, device="cuda")
+    srv = zset.Server(arena, slots=6, memo_bytes=4096)
+    sets = [([7, 11, 13, 17], 3000, 2), ([13, 34, 37, 54, 65, 83], 1500, 3),
+            ([3, 5, 7, 11, 13], 300, 3), ([9, 4, 6, 7], 700, 1), ([12, 18, 30], 500, -1)]
+    ids, tops = [], []
+    for g, n_max, k in sets:
+        sid = srv.add_set(g, n_max, k)
+        info = srv.set_info(sid)
+        say(f"capped set {sid}: g={g} n_max={n_max} {info}")
+        h = g[len(g) - info["k"]:]
+        assert 1 <= info["memo_top"] <= n_max + 1
+        assert info["memo_rows"] == sum(oracle.count(p, h) for p in range(info["memo_top"]))
+        if info["memo_top"] <= n_max:  # capped: the next element's memo would not fit
+            assert info["memo_rows"] * 4 <= 4096 * (info["k"] + 1)
+        ids.append(sid)
+        tops.append(info["memo_top"])
+    assert min(t - 1 - s[1] for t, s in zip(tops, sets)) < 0  # at least one memo is capped
+    rng = np.random.default_rng(91)
+    queries = []
+    for i, (g, n_max, k) in enumerate(sets):
+        for n in {0, 1, tops[i] - 1, tops[i], min(n_max, tops[i] + 1), n_max}:
+            if 0 <= n <= n_max:
+                queries.append((i, n))
+        queries += [(i, int(rng.integers(0, n_max + 1))) for _ in range(12)]
+    rng.shuffle(queries)
+    tickets = [srv.submit(ids[i], n) for i, n in queries]
+    for (i, n), t in zip(queries, tickets):
+        res = srv.wait(t)
+        g = sets[i][0]
+        info = srv.set_info(ids[i])
+        want = oracle.enumerate_rows(n, g)
+        assert res["rows"] == len(want)
+        got = srv.rows_of(ids[i], res).cpu().numpy().view(np.uint32) if res["rows"] else \
+            np.zeros((0, len(g)), np.uint32)
+        assert np.array_equal(got, want), (i, n, info)
+        if res["rows"]:
+            alone_rows = zset.enumerate_ex(n, g, k=info["k"], memo_top=info["memo_top"])
+            assert torch.equal(srv.rows_of(ids[i], res), alone_rows.out[: res["rows"]]), (i, n)
+        srv.release(t)
+    srv.free()
+
+
 def test_server_errors():
     arena = torch.empty(1 << 16, dtype=torch.int32, device="cuda")
     srv = zset.Server(arena, slots=2)
