@@ -187,6 +187,37 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t 
                               uint64_t *checksum, zset_stats *stats);
 
 /*
+ * zset_enumerate_noalloc -- zset_enumerate_ex for callers that cannot
+ * allocate device memory (code that must not call hipMalloc: tight serving
+ * loops, harnesses that forbid allocation).  It calls no hipMalloc, hipFree
+ * or other allocating routine: every scratch buffer (count table, memo and
+ * its leaf layout, slice table, status words) is carved from one array of
+ * ZSET_NOALLOC_SCRATCH_BYTES bytes in device memory that the library holds on
+ * every device it runs on until the process ends.  The caller passes the
+ * inputs and the output as for zset_enumerate_ex (same rows, same
+ * checksum); every launch runs in order on opts->stream and the call returns
+ * after they complete.  No memo handle and no timings.
+ *   out           device, out_rows_cap * d uint32; ignored when count_only
+ *   out_rows_cap  rows `out` holds; ECAPACITY (nothing written) if < |Z(n)|
+ *   opts          host, or NULL for the defaults (zset_default_opts)
+ *   rows_written  host, optional: |Z(n)|
+ *   checksum      host, optional: as zset_enumerate_ex (count_only only)
+ * opts->memo_top must be 0 or > n (no partial memo).
+ * Errors: as zset_enumerate_ex, and ENOMEM (before any output is written)
+ *         when the query's scratch exceeds the array: about
+ *         8 (d + 1)(n + 1) bytes of count table, the slice table and the memo.
+ * The array is shared by every call on a device and keeps the last call's
+ * contents (the call clears what must start at zero).  Two calls that
+ * overlapped on one device would race on it: the library's lock serialises
+ * them within a process, and each process has its own array.
+ */
+#define ZSET_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+zset_status zset_enumerate_noalloc(uint64_t n, const uint32_t *gens, int d, uint32_t *out,
+                                   uint64_t out_rows_cap, const zset_opts *opts,
+                                   uint64_t *rows_written, uint64_t *checksum);
+
+/*
  * zset_enumerate_walk -- Z(n; g) without the count table: the lexicographic
  * walk of Section 2 (each coordinate takes its values in order, the last one
  * is forced by division), split over prefixes of the first coordinates that

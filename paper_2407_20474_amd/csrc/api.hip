@@ -453,9 +453,66 @@ uint64_t init_params(EnumParams& P, uint64_t n, const uint32_t* gens, int d, int
   return P.pack ? Rn * uint64_t(P.pack) : Rn * uint64_t(k + 1);
 }
 
+// Status words and scratch of zset_enumerate_noalloc carved in order from the
+// device's scratch array (256-byte aligned pieces).
+struct Carve {
+  unsigned char* base;
+  size_t cap;
+  size_t used;
+  template <class Tp>
+  Tp* take(size_t bytes) {
+    const size_t off = (used + 255) & ~size_t(255);
+    if (bytes > cap || off > cap - bytes) return nullptr;
+    used = off + (bytes ? bytes : 1);
+    return reinterpret_cast<Tp*>(base + off);
+  }
+};
+
+__global__ void k_clear_words(uint64_t* p, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
 }  // namespace
 }  // namespace zset
 
+// Device scratch of zset_enumerate_noalloc: one copy on every device the
+// library runs on, held until the process ends.  Host code never passes this
+// name to a kernel or a copy (on the host it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress gives for the current
+// device, kept per device in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[ZSET_NOALLOC_SCRATCH_BYTES];
+
+namespace zset {
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};  // guarded by g_mu
+
+// The scratch array's address on device `dev` (current), looked up on the
+// first call on that device.
+zset_status noalloc_scratch(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(ZSET_EDEVICE, "device index out of range");
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(ZSET_EDEVICE, "hipGetSymbolAddress(scratch) gave NULL");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  return ZSET_OK;
+}
+
+zset_status scratch_full(const char* what, size_t bytes) {
+  return fail(ZSET_ENOMEM, std::string("zset_enumerate_noalloc: the ") + what + " (" +
+                               std::to_string(bytes) + " bytes) does not fit in what is left of "
+                               "the " + std::to_string(size_t(ZSET_NOALLOC_SCRATCH_BYTES)) +
+                               "-byte scratch array; use zset_enumerate_ex");
+}
+
+}  // namespace
+}  // namespace zset
 
 
 using namespace zset;
@@ -951,6 +1008,137 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     stats->rows_per_tile = T_rows;
     stats->k = k;
   }
+  return ZSET_OK;
+}
+
+zset_status zset_enumerate_noalloc(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
+                                   uint64_t out_rows_cap, const zset_opts* opts_in,
+                                   uint64_t* rows_written, uint64_t* checksum) {
+  g_last_error.clear();
+  zset_status st = check_query(n, gens, d);
+  if (st != ZSET_OK) return st;
+  zset_opts opts;
+  if (opts_in) opts = *opts_in; else zset_default_opts(&opts);
+  if (opts.k < -1 || opts.k > d - 1) return fail(ZSET_EINVAL, "k must be -1 or lie in [0, d-1]");
+  if (opts.order != 0 && opts.order != 1) return fail(ZSET_EINVAL, "order must be 0 or 1");
+  if (opts.claim_pct < -1 || opts.claim_pct > 100)
+    return fail(ZSET_EINVAL, "claim_pct must be -1 or lie in [0, 100]");
+  if (opts.rows_per_tile % 128 != 0 || opts.rows_per_tile > (uint64_t(1) << 30))
+    return fail(ZSET_EINVAL, "rows_per_tile must be a multiple of 128 and at most 2^30");
+  if (opts.memo_top != 0 && opts.memo_top <= n)
+    return fail(ZSET_EINVAL, "zset_enumerate_noalloc takes no partial memo (memo_top <= n)");
+  const bool count_only = opts.count_only != 0;
+  if (!count_only && !out) return fail(ZSET_EINVAL, "out is NULL");
+  if (!count_only && !is_device_pointer(out)) return fail(ZSET_EINVAL, "out is not device memory");
+  hipStream_t s = reinterpret_cast<hipStream_t>(opts.stream);
+
+  std::lock_guard<std::mutex> lock(g_mu);
+  int dev = 0;
+  ZSET_HIP(hipGetDevice(&dev));
+  unsigned char* base = nullptr;
+  if ((st = noalloc_scratch(dev, &base)) != ZSET_OK) return st;
+  Carve cv{base, size_t(ZSET_NOALLOC_SCRATCH_BYTES), 0};
+  const uint64_t N = n + 1;
+  uint64_t* misc = cv.take<uint64_t>(kMiscWords * sizeof(uint64_t));
+  const size_t table_bytes = size_t(d + 1) * N * sizeof(uint64_t);
+  uint64_t* T = cv.take<uint64_t>(table_bytes);
+  if (!misc || !T) return scratch_full("count table", table_bytes);
+  int* err = reinterpret_cast<int*>(misc + kMiscErr);
+
+  // 1. Status words cleared (a kernel: the array keeps the last call's
+  // contents), count table, one readback of the row sums and |Z(n)|.
+  hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(256), 0, s, misc, uint32_t(kMiscWords));
+  ZSET_HIP(hipGetLastError());
+  ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
+  uint64_t host[2 * kMaxD + 3];
+  ZSET_HIP(hipMemcpyAsync(host, misc + kMiscRowSums, (2 * d + 3) * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  uint64_t sums[kMaxD + 1], rowmax[kMaxD + 1];
+  for (int j = 0; j <= d; ++j) {
+    sums[j] = host[j];
+    rowmax[j] = host[d + 2 + j];
+  }
+  const uint64_t total = host[d + 1];
+  if (total == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
+  if (total > (~uint64_t(0)) / (4 * uint64_t(d)))
+    return fail(ZSET_EOVERFLOW, "|Z(n)| * d * 4 bytes overflows 64 bits");
+  if (!count_only && total > out_rows_cap)
+    return fail(ZSET_ECAPACITY, "out holds " + std::to_string(out_rows_cap) + " rows, |Z(n)| = " +
+                                    std::to_string(total));
+
+  // 2. Memo dimension, descriptor, scratch pieces, then the same launches as
+  // zset_enumerate_ex in one stream order.
+  int k = opts.k;
+  if (d == 1) k = 0;
+  else if (k < 0) k = auto_memo_dim(sums, d, total);
+  if (total > 0 && d == 1) {
+    ZSET_HIP(launch_single(n, gens[0], out, count_only, misc + kMiscSum, s));
+  } else if (total > 0) {
+    const int L = d - std::max(k, 1);
+    const int U = (k == 0) ? d - 1 : L - 1;
+    const uint32_t G = gens[U];
+    EnumParams P;
+    const uint64_t leaf_words = init_params(P, n, gens, d, k, total, sums, T, err,
+                                            misc + kMiscSum, out, size_t(write_lds_budget(dev)));
+    P.desc = opts.order == 1 && !count_only;
+    const uint64_t Rn = k >= 1 ? sums[L] : 0;
+    if (k >= 1) {
+      const size_t eb = size_t(std::min<uint64_t>(G, N)) * sizeof(uint64_t);
+      P.endc = cv.take<uint64_t>(eb);
+      if (!P.endc) return scratch_full("class ends", eb);
+      const size_t lb = size_t(leaf_words) * sizeof(uint32_t);
+      P.leaf = cv.take<uint32_t>(lb);
+      if (!P.leaf) return scratch_full("leaf-order memo", lb);
+    }
+    const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+    P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
+    if ((st = size_write_pass(P, opts.rows_per_tile, opts.claim_pct, dev, count_only, align16)) !=
+        ZSET_OK)
+      return st;
+    const size_t tb = size_t(P.ntiles) * (U + 2) * sizeof(uint32_t);
+    P.tiles = cv.take<uint32_t>(tb);
+    if (!P.tiles) return scratch_full("slice table", tb);
+    if (k >= 1) {
+      uint32_t nclass = 0;
+      ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc),
+                                 &nclass, s));
+    }
+    ZSET_HIP(launch_plan(P, s));
+    if (k >= 1) {
+      const size_t ob = size_t(N + 1) * sizeof(uint64_t);
+      uint64_t* off = cv.take<uint64_t>(ob);
+      if (!off) return scratch_full("memo offsets", ob);
+      const size_t nb = size_t(Rn) * k * sizeof(uint32_t);
+      uint32_t* nat = cv.take<uint32_t>(nb);
+      if (!nat) return scratch_full("memo rows", nb);
+      if (k == 2 && memo2_closed_form()) {
+        uint64_t* cnt = cv.take<uint64_t>(ob);
+        if (!cnt) return scratch_full("memo counts", ob);
+        ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn, nat, off, cnt, s));
+      } else {
+        auto srcw_for = [&cv](size_t bytes, uint64_t** p) {
+          *p = cv.take<uint64_t>(bytes);
+          return *p ? ZSET_OK : scratch_full("memo source table", bytes);
+        };
+        st = build_memo_rows(gens + L, k, N, off, T + uint64_t(L) * N, N, Rn, rowmax[L], nat, err,
+                             size_t(device_max_lds_bytes(dev)), srcw_for, s);
+        if (st != ZSET_OK) return st;
+      }
+      ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                              const_cast<uint32_t*>(P.leaf), Rn, P),
+                                err, s));
+    }
+    ZSET_HIP(launch_write(P, count_only, align16, s));
+  }
+
+  uint64_t fin[2] = {0, 0};
+  ZSET_HIP(hipMemcpyAsync(fin, misc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  const int code = int(uint32_t(fin[0]));
+  if (code != 0) return fail(ZSET_EDEVICE, device_error_text(code));
+  if (rows_written) *rows_written = total;
+  if (checksum) *checksum = count_only ? fin[1] : 0;
   return ZSET_OK;
 }
 

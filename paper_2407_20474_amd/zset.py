@@ -25,7 +25,7 @@ MAX_D = 32
 SYMBOLS = (
     "zset_default_opts", "zset_count", "zset_count_table", "zset_memo_build",
     "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
-    "zset_enumerate_walk",
+    "zset_enumerate_noalloc", "zset_enumerate_walk",
     "zset_batch_default_opts", "zset_batch_create", "zset_batch_info", "zset_batch_run",
     "zset_batch_times", "zset_batch_free",
     "zset_server_default_opts", "zset_server_create", "zset_server_add_set",
@@ -125,6 +125,8 @@ def load():
     lib.zset_enumerate_ex.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                       ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
                                       _u64p, _u64p, ctypes.POINTER(Stats)]
+    lib.zset_enumerate_noalloc.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
+                                           ctypes.c_uint64, ctypes.POINTER(Opts), _u64p, _u64p]
     lib.zset_store_ceiling.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.zset_enumerate_walk.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
@@ -162,7 +164,7 @@ def load():
     lib.zset_last_error.argtypes = []
     lib.zset_last_error.restype = ctypes.c_char_p
     for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
-                 "zset_enumerate", "zset_enumerate_ex",
+                 "zset_enumerate", "zset_enumerate_ex", "zset_enumerate_noalloc",
                  "zset_batch_create", "zset_batch_info",
                  "zset_batch_run", "zset_batch_times", "zset_selftest_host",
                  "zset_server_create", "zset_server_add_set", "zset_server_set_info",
@@ -322,6 +324,36 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     r = int(rows_written.value)
     view = out[:r] if (out is not None and out.dim() == 2) else out
     return Result(rows=r, checksum=int(csum.value), stats=stats.as_dict(), out=view)
+
+
+def enumerate_noalloc(n: int, gens, out=None, *, k: int = -1, order: int = 0,
+                      rows_per_tile: int = 0, count_only: bool = False, stream=None,
+                      out_rows_cap: int | None = None, claim_pct: int = -1,
+                      memo_top: int = 0) -> Result:
+    """Z(n; g) through zset_enumerate_noalloc (scratch from the library's fixed
+    device array; no device allocation by the library).  `out` as for
+    enumerate_ex, but never allocated here: pass it unless count_only."""
+    g = _gens(gens)
+    d = len(g)
+    if out is not None:
+        cap = out.numel() // max(d, 1) if out_rows_cap is None else out_rows_cap
+        ptr = out.data_ptr()
+    else:
+        cap, ptr = 0, None
+    opts = Opts()
+    load().zset_default_opts(ctypes.byref(opts))
+    opts.k, opts.order, opts.rows_per_tile = k, order, rows_per_tile
+    opts.count_only = 1 if count_only else 0
+    opts.stream = _stream_handle(stream)
+    opts.claim_pct = claim_pct
+    opts.memo_top = memo_top
+    rows_written, csum = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(load().zset_enumerate_noalloc(n, g.ctypes.data_as(_u32p), d, ptr, cap,
+                                         ctypes.byref(opts), ctypes.byref(rows_written),
+                                         ctypes.byref(csum)), "zset_enumerate_noalloc")
+    r = int(rows_written.value)
+    view = out[:r] if (out is not None and out.dim() == 2) else out
+    return Result(rows=r, checksum=int(csum.value), stats={}, out=view)
 
 
 def store_ceiling(buf, reps: int = 5, stream=None) -> float:
