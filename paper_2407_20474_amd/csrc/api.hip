@@ -118,7 +118,7 @@ zset_status get_ctx(Ctx** out) {
       return fail(ZSET_EDEVICE, "hipEventCreate failed");
     }
   }
-  if (hipEventCreateWithFlags(&c->fork, hipEventDisableTiming) != hipSuccess ||
+  if (hipEventCreate(&c->fork) != hipSuccess ||
       hipEventCreate(&c->memo0) != hipSuccess || hipEventCreate(&c->memo1) != hipSuccess ||
       hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
       hipEventCreateWithFlags(&c->counted, hipEventDisableTiming) != hipSuccess ||
@@ -293,6 +293,9 @@ const char* device_error_text(int code) {
     case kErrTileRows: return "a slice wrote a different number of rows than planned";
     case kErrMemoTotal: return "the memo build produced a different row total than counted";
     case kErrUnrank: return "a slice start could not be unranked";
+    case kErrCapacity: return "|Z(n)| exceeds the output's rows";
+    case kErrOverflow: return "|Z(n)| or its bytes overflow 64 bits";
+    case kErrSlices: return "|Z(n)| needs more slices of at most 2^30 rows than were planned";
     default: return "unknown kernel check";
   }
 }
@@ -356,7 +359,7 @@ zset_status build_memo_rows(const uint32_t* h, int k, uint64_t top, uint64_t* of
   uint64_t* srcw = nullptr;
   zset_status st = srcw_for(size_t(R) * sizeof(uint64_t), &srcw);
   if (st != ZSET_OK) return st;
-  ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride, srcw, nat, err, s));
+  ZSET_HIP(launch_memo_global(h, k, top, b, off, ge, ge_stride, srcw, nat, err, s, R));
   return ZSET_OK;
 }
 
@@ -672,6 +675,180 @@ zset_status zset_enumerate(uint64_t n, const uint32_t* gens, int d, uint32_t* ou
                            nullptr);
 }
 
+namespace zset {
+namespace {
+
+// Rows of the memo Z(p; h) over p <= n for k = 1 and k = 2 trailing
+// generators, counted on the host: the number of m >= 0 with
+// m_1 h_1 (+ m_2 h_2) <= n.  For k = 2 the sum runs over multiples of the
+// larger generator.  Returns false when that takes more than kHostCountSteps
+// steps.
+constexpr uint64_t kHostCountSteps = 1 << 16;
+bool host_memo_rows(uint64_t n, const uint32_t* h, int k, uint64_t* rows) {
+  if (k == 1) {
+    *rows = n / h[0] + 1;
+    return true;
+  }
+  const uint64_t big = std::max(h[0], h[1]), small = std::min(h[0], h[1]);
+  if (n / big + 1 > kHostCountSteps) return false;
+  uint64_t r = 0;
+  for (uint64_t x = 0; x <= n; x += big) r += (n - x) / small + 1;
+  *rows = r;
+  return true;
+}
+
+// zset_enumerate_ex with the memo dimension fixed at 1 or 2 by the caller:
+// every launch is enqueued at once, with no readback of |Z(n)| in the middle.
+// The memo's size comes from host_memo_rows; the slice planner and the write
+// pass read |Z(n)| from device memory (EnumParams::total_dev) and size the
+// slices from it, and a query that overflows or exceeds out_rows_cap is
+// refused on the device (no slices: nothing written) and reported at the end.
+// *taken = false (and nothing enqueued) when the call needs the general path.
+zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, uint32_t* out,
+                              uint64_t out_rows_cap, const zset_opts& opts,
+                              uint64_t* rows_written, uint64_t* checksum, zset_stats* stats,
+                              hipStream_t s, bool* taken) {
+  *taken = false;
+  const int k = opts.k;
+  const bool count_only = opts.count_only != 0;
+  if (k < 1 || k > 2 || d < 2 || k > d - 1 || opts.rows_per_tile != 0 ||
+      (opts.claim_pct != -1 && opts.claim_pct != 100) ||
+      (opts.memo_top != 0 && opts.memo_top <= n) || std::getenv("ZSET_MEMO_PATH") ||
+      std::getenv("ZSET_FIXED_K_READBACK"))
+    return ZSET_OK;
+  const uint64_t N = n + 1;
+  const int L = d - k, U = L - 1;
+  const uint32_t G = gens[U];
+  uint64_t Rn = 0;
+  if (!host_memo_rows(n, gens + L, k, &Rn) || Rn >= (uint64_t(1) << 32)) return ZSET_OK;
+  // The row sums the write pass's format needs: the memo's rows, and a bound
+  // on the sum of C_U[x] over x <= n (each x contributes at most
+  // (x / G + 1) memo lists), which decides whether segment counts and class
+  // ends fit 32 bits.
+  uint64_t sums[kMaxD + 1] = {};
+  sums[L] = Rn;
+  const uint64_t qmax = n / G + 1;
+  sums[U] = Rn > ~uint64_t(0) / qmax ? ~uint64_t(0) : Rn * qmax;
+  uint64_t* misc = reinterpret_cast<uint64_t*>(c->misc.p);
+  int* err = reinterpret_cast<int*>(misc + kMiscErr);
+  zset_status st;
+  if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
+  uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
+  EnumParams P;
+  const uint64_t leaf_words = init_params(P, n, gens, d, k, 0, sums, T, err, misc + kMiscSum, out,
+                                          size_t(write_lds_budget(c->device)));
+  P.desc = opts.order == 1 && !count_only;
+  const uint64_t want = plan_want_tiles(c->device);
+  const bool align16 = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+  P.pool = reinterpret_cast<uint32_t*>(misc + kMiscPool);
+  // Grid and slice-state room as for want_tiles slices of 128 rows (every
+  // slice claimed): the write pass then takes the real slices from the plan.
+  P.total = want * 128;
+  if ((st = size_write_pass(P, 0, 100, c->device, count_only, align16, 1, want)) != ZSET_OK)
+    return st;
+  if (P.chunk == 0 || P.static_tiles != 0) return ZSET_OK;  // claims do not fit: general path
+  P.total = 0;
+  P.rows_per_tile = 0;
+  P.ntiles = 0;
+  P.total_dev = misc + kMiscRowSums + d + 1;
+  P.want_tiles = want;
+  P.out_rows_cap = count_only ? 0 : out_rows_cap;
+  P.dyn = 1;
+  *taken = true;
+
+  if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+  if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
+  if ((st = ensure(c->endc, size_t(std::min<uint64_t>(G, N)) * sizeof(uint64_t))) != ZSET_OK)
+    return st;
+  if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
+  if ((st = ensure(c->tiles, size_t(want) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
+  if (k == 2 && (st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+  P.endc = reinterpret_cast<uint64_t*>(c->endc.p);
+  P.leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
+  P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
+  uint64_t* off = reinterpret_cast<uint64_t*>(c->off.p);
+  uint32_t* nat = reinterpret_cast<uint32_t*>(c->nat.p);
+
+  // Enqueued in the order of the critical path: status words clear, count
+  // table, class ends and slice plan on the call's stream; then the memo
+  // (closed form) on the side stream, which needs only the status reset and
+  // runs beside them; then the leaf layout (after the memo) and the write
+  // pass.  The host's enqueue time would otherwise delay the count table.
+  ZSET_HIP(hipEventRecord(c->ev[0], s));
+  ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
+  ZSET_HIP(hipEventRecord(c->fork, s));
+  ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
+  ZSET_HIP(hipEventRecord(c->ev[1], s));
+  uint32_t nclass = 0;
+  ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc), &nclass,
+                             s));
+  ZSET_HIP(launch_plan_device_sized(P, s));
+  ZSET_HIP(hipEventRecord(c->ev[3], s));
+  struct SideJoin {
+    Ctx* c = nullptr;
+    ~SideJoin() {
+      if (c) (void)hipStreamSynchronize(c->side);
+    }
+  } side_join;
+  ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
+  side_join.c = c;
+  ZSET_HIP(hipEventRecord(c->memo0, c->side));
+  if (k == 2)
+    ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn, nat, off,
+                            reinterpret_cast<uint64_t*>(c->cnt2.p), c->side));
+  else
+    ZSET_HIP(launch_memo_k1(gens[L], N, Rn, nat, off, c->side));
+  ZSET_HIP(hipEventRecord(c->memo1, c->side));
+  ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
+  ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                          const_cast<uint32_t*>(P.leaf), Rn, P),
+                            err, s));
+  ZSET_HIP(hipEventRecord(c->ev[4], s));
+  ZSET_HIP(launch_write(P, count_only, align16, s));
+  ZSET_HIP(hipEventRecord(c->ev[5], s));
+  // Status, checksum and |Z(n)| in one readback.
+  static_assert(kMiscErr == 0 && kMiscSum == 1 && kMiscRowSums == 2, "misc layout");
+  ZSET_HIP(hipMemcpyAsync(c->pinned, misc, (kMiscRowSums + d + 2) * sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, s));
+  ZSET_HIP(hipStreamSynchronize(s));
+  side_join.c = nullptr;  // the call's stream waited for the side stream
+  const int code = *reinterpret_cast<int*>(c->pinned);
+  const uint64_t total = c->pinned[kMiscRowSums + d + 1];
+  if (code == kErrOverflow) {
+    if (total == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
+    return fail(ZSET_EOVERFLOW, "|Z(n)| * d * 4 bytes overflows 64 bits");
+  }
+  if (code == kErrCapacity)
+    return fail(ZSET_ECAPACITY, "out holds " + std::to_string(out_rows_cap) + " rows, |Z(n)| = " +
+                                    std::to_string(total));
+  if (code == kErrSlices) return fail(ZSET_EINVAL, "too many slices: raise rows_per_tile");
+  if (code != 0) return fail(ZSET_EDEVICE, device_error_text(code));
+  if (rows_written) *rows_written = total;
+  if (checksum) *checksum = count_only ? c->pinned[kMiscSum] : 0;
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    const uint64_t T_rows = slice_rows(total, want);
+    // count: the status reset and the count table; plan: class ends and
+    // slice plan; memo: the closed form on the side stream and the leaf
+    // layout (from the plan's end).
+    stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
+    stats->plan_us = elapsed_us(c->ev[1], c->ev[3]);
+    stats->memo_us = elapsed_us(c->memo0, c->memo1) + elapsed_us(c->ev[3], c->ev[4]);
+    stats->write_us = elapsed_us(c->ev[4], c->ev[5]);
+    stats->total_us = elapsed_us(c->ev[0], c->ev[5]);
+    stats->rows = total;
+    stats->memo_rows = Rn;
+    stats->memo_bytes = leaf_words * 4;
+    stats->tiles = (total + T_rows - 1) / T_rows;
+    stats->rows_per_tile = T_rows;
+    stats->k = k;
+  }
+  return ZSET_OK;
+}
+
+}  // namespace
+}  // namespace zset
+
 zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
                               uint64_t out_rows_cap, const zset_opts* opts_in, zset_memo memo,
                               uint64_t* rows_written, uint64_t* checksum, zset_stats* stats) {
@@ -706,6 +883,12 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   if ((st = get_ctx(&c)) != ZSET_OK) return st;
   if (memo && memo->device != c->device)
     return fail(ZSET_EINVAL, "memo lives on another device");
+  if (!memo) {
+    bool taken = false;
+    st = enumerate_fixed_k(c, n, gens, d, out, out_rows_cap, opts, rows_written, checksum, stats,
+                           s, &taken);
+    if (taken || st != ZSET_OK) return st;
+  }
 
   const uint64_t N = n + 1;
   uint64_t* misc = reinterpret_cast<uint64_t*>(c->misc.p);

@@ -170,9 +170,10 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   }
   uint64_t T = P.rows_per_tile, ntiles = P.ntiles;
   if (P.total_dev) {  // sized on the device from |Z(n)|
-    const uint64_t total = *P.total_dev;
-    T = slice_rows(total, P.want_tiles);
-    ntiles = (total + T - 1) / T;
+    const DynSize z = dyn_size(P);
+    T = z.T;
+    ntiles = z.ntiles;
+    if (tile == 0 && z.err) set_error(P.err, z.err);
   }
   if (tile >= ntiles) return;
   plan_tile(P, tile, T);
@@ -743,8 +744,17 @@ __device__ inline void publish_flag(uint32_t* f, uint32_t v, int lane) {
   if (lane == 0) __hip_atomic_store(f, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Memo rows read from global memory (PACK 0, generic row assembly): such a
+// load waits for every store the wavefront has issued before it (one counter
+// for both), so these kernels are held to 64 VGPRs for 8 wavefronts per SIMD:
+// two workgroups per compute unit when LDS allows, twice the wavefronts to
+// cover the waits.
+template <int MODE, int PACK, int NO>
+constexpr int write_waves_per_simd() { return (PACK == 0 && NO == -1) ? 8 : 1; }
+
 template <int MODE, bool COUNT_ONLY, bool ALIGN16, int PACK, bool LDSCNT, int NO, int KF>
-__global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
+__global__ __launch_bounds__(kWriteWaves * kWave, (write_waves_per_simd<MODE, PACK, NO>()))
+void k_write(EnumParams P) {
   extern __shared__ __align__(16) uint32_t lds[];
   const int lane = lane_id();
   const int wave = int(threadIdx.x / kWave);
@@ -790,6 +800,15 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   __shared__ uint32_t next_slot, first_chunk;
   const uint64_t B = blockIdx.x, NB = gridDim.x;
   const uint64_t nstatic = P.static_tiles;
+  // Slices sized on the device (P.dyn): |Z(n)|, the slice length and count
+  // as the planner took them; every slice is claimed (nstatic = 0).
+  uint64_t ntiles = P.ntiles, dyn_total = P.total, dyn_T = P.rows_per_tile;
+  if (P.dyn) {
+    const DynSize z = dyn_size(P);
+    ntiles = z.ntiles;
+    dyn_total = z.total;
+    dyn_T = z.T;
+  }
   uint32_t my_tiles = B < nstatic ? uint32_t((nstatic - B + NB - 1) / NB) : 0;
   if (my_tiles > P.max_tiles) {  // the host sizes the grid so that this cannot happen
     if (threadIdx.x == 0) set_error(P.err, kErrTileRows);
@@ -822,7 +841,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   // lands about CH slices ahead of use.
   const uint32_t CH = P.chunk;
   constexpr uint32_t R = kChunkSlots;
-  const uint32_t nchunks = CH ? uint32_t((P.ntiles - nstatic + CH - 1) / CH) : 0;
+  const uint32_t nchunks = CH ? uint32_t((ntiles - nstatic + CH - 1) / CH) : 0;
   uint32_t* cflag = tstates + align4(uint64_t(P.max_tiles) * S);
   uint32_t* cgid = cflag + R;
   uint32_t* cdone = cgid + R;
@@ -833,7 +852,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     __syncthreads();
     const uint32_t gc = min(first_chunk, nchunks);
     if (gc < nchunks) {
-      const uint64_t hi = P.ntiles - uint64_t(gc) * CH;
+      const uint64_t hi = ntiles - uint64_t(gc) * CH;
       const uint32_t cnt = uint32_t(min<uint64_t>(CH, hi - nstatic));
       const uint64_t t0 = hi - cnt;
       for (uint32_t i = threadIdx.x; i < cnt * S; i += blockDim.x) cstate[i] = P.tiles[t0 * S + i];
@@ -848,7 +867,9 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
   const uint32_t gj = lane < d ? P.g.g[lane] : 0;
   const uint32_t fsh = lane <= k ? P.fshift[lane] : 0;
   const uint32_t fmk = lane <= k ? P.fmask[lane] : 0;
-  const TileArgs A = tile_args(P);
+  TileArgs A = tile_args(P);
+  A.total = dyn_total;
+  A.rows_per_tile = dyn_T;
   __syncthreads();
 
   uint64_t csum = 0;
@@ -872,7 +893,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
     // wait ends.
     wait_word(cflag + r, c + 1);
     const uint32_t gc = cgid[r];
-    const uint64_t hi = gc < nchunks ? P.ntiles - uint64_t(gc) * CH : nstatic;
+    const uint64_t hi = gc < nchunks ? ntiles - uint64_t(gc) * CH : nstatic;
     const uint32_t cnt = uint32_t(min<uint64_t>(CH, hi - nstatic));
     const bool live = e < cnt;  // the chunk claimed last may be short
     const uint64_t tile = hi - 1 - e;
@@ -893,7 +914,7 @@ __global__ __launch_bounds__(kWriteWaves * kWave) void k_write(EnumParams P) {
         gn = min(__builtin_amdgcn_readfirstlane(g_l), nchunks);
       }
       if (gn < nchunks) {
-        const uint64_t hn = P.ntiles - uint64_t(gn) * CH;
+        const uint64_t hn = ntiles - uint64_t(gn) * CH;
         const uint32_t cn = uint32_t(min<uint64_t>(CH, hn - nstatic));
         const uint64_t t0 = hn - cn;
         uint32_t* dst = cstate + rn * CH * S;

@@ -441,6 +441,28 @@ __global__ __launch_bounds__(256) void k_memo_batch(int k, const uint64_t* __res
   }
 }
 
+// Every batch in one workgroup: batch [x0, x0 + b) copies rows
+// [off[x0], off[x0 + b)) and a workgroup barrier separates it from the next,
+// whose sources it may hold.  For memos whose batches hold few rows, where a
+// launch per batch would cost more than its copies.
+__global__ __launch_bounds__(1024) void k_memo_batches_wg(int k, const uint64_t* __restrict__ off,
+                                                          uint32_t top, uint32_t b,
+                                                          const uint64_t* __restrict__ srcw,
+                                                          uint32_t* __restrict__ nat) {
+  for (uint32_t x0 = 1; x0 < top; x0 += b) {
+    const uint32_t x1 = top - x0 > b ? x0 + b : top;
+    const uint64_t lo = off[x0], hi = off[x1];
+    for (uint64_t j = lo + threadIdx.x; j < hi; j += blockDim.x) {
+      const uint64_t w = srcw[j];
+      const uint64_t src = w >> 5;
+      const int i = int(w & 31);
+      if (src >= j) continue;  // sources always precede their copies
+      for (int c = 0; c < k; ++c) nat[j * k + c] = nat[src * k + c] + (c == i ? 1u : 0u);
+    }
+    __syncthreads();
+  }
+}
+
 // Natural order -> leaf order for p in [0, n]: row t of Memo[p] goes to
 // pos(p) + t with pos(p) = end[p mod G] - cu[p]; it is stored as the fields
 // (floor(p / G), m_1..m_k): k+1 plain words (pack 0), or packed into one 32-
@@ -650,9 +672,13 @@ hipError_t launch_memo_k1_batch(const MemoJob* jobs, uint32_t njobs, uint32_t bl
   return hipGetLastError();
 }
 
+// Average rows per batch up to which every batch runs in one workgroup.
+constexpr uint64_t kMemoRowsPerLaunch = 16384;
+
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
-                              uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s) {
+                              uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s,
+                              uint64_t rows) {
   Gens hg{};
   for (int i = 0; i < k; ++i) hg.g[i] = h[i];
   const uint32_t blocks = uint32_t((top + 255) / 256);
@@ -660,6 +686,14 @@ hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b
                      ge_stride, srcw, nat, err);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  // Few rows per batch on average: every batch in one workgroup (a barrier
+  // per batch); else one launch per batch over the whole device.
+  const uint64_t nbatch = top > 1 ? (top - 2) / b + 1 : 0;
+  if (nbatch && rows / nbatch <= kMemoRowsPerLaunch) {
+    hipLaunchKernelGGL(k_memo_batches_wg, dim3(1), dim3(1024), 0, s, k, off, uint32_t(top), b,
+                       srcw, nat);
+    return hipGetLastError();
+  }
   for (uint64_t x0 = 1; x0 < top; x0 += b) {
     const uint64_t x1 = (x0 + b < top) ? x0 + b : top;
     hipLaunchKernelGGL(k_memo_batch, dim3(1024), dim3(256), 0, s, k, off, uint32_t(x0),

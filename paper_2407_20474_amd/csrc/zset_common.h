@@ -17,6 +17,9 @@ enum DeviceError : int {
   kErrTileRows = 2,      // a slice wrote a different number of rows than planned
   kErrMemoTotal = 3,     // memo chain produced a different row total than counted
   kErrUnrank = 4,        // a slice start could not be unranked
+  kErrCapacity = 5,      // |Z(n)| exceeds the output's rows (nothing written)
+  kErrOverflow = 6,      // |Z(n)| or its bytes overflow 64 bits (nothing written)
+  kErrSlices = 7,        // |Z(n)| needs more slices than were planned for (nothing written)
 };
 
 // Generators passed by value in kernel arguments.

@@ -56,11 +56,14 @@ struct EnumParams {
   uint32_t* blocks_done;    // write workgroups finished (with done_flag)
   uint64_t* done_flag;      // non-NULL: the last write workgroup stores *err to done_flag[1]
   uint64_t done_seq;        // and then done_seq to done_flag[0] (pinned host words)
-  // Slice planner only: when total_dev is non-NULL, |Z(n)| is read there and
-  // the slice length is slice_rows(|Z(n)|, want_tiles) (the host repeats the
-  // same formula once it has |Z(n)|).
+  // When total_dev is non-NULL, |Z(n)| is read there (dyn_size below): the
+  // slice planner sizes the slices as slice_rows(|Z(n)|, want_tiles), and the
+  // write pass, given no host-side |Z(n)| (total, rows_per_tile and ntiles
+  // unset, every slice claimed), takes its slices the same way.
   const uint64_t* total_dev;
   uint64_t want_tiles;
+  uint64_t out_rows_cap;    // with total_dev: rows the output holds (0: no check)
+  int dyn;                  // write pass: 1 = total, slice length and count from dyn_size
 };
 
 // Rows per slice when `want` slices are asked for |Z| = total rows: a
@@ -71,6 +74,32 @@ __host__ __device__ inline uint64_t slice_rows(uint64_t total, uint64_t want) {
   if (T < 128) T = 128;
   if (T > (uint64_t(1) << 30)) T = uint64_t(1) << 30;
   return T;
+}
+
+// |Z(n)| read on the device (P.total_dev), with the slice length and count
+// the planner uses for it, and the error that refuses the query: its bytes
+// overflow 64 bits, it exceeds P.out_rows_cap rows, or its slices (at most
+// 2^30 rows each) outnumber the want_tiles planned for.  A refused query gets
+// no slices, so nothing is written.
+struct DynSize {
+  uint64_t total, T, ntiles;
+  int err;
+};
+__device__ inline DynSize dyn_size(const EnumParams& P) {
+  DynSize z;
+  z.total = *P.total_dev;
+  z.err = 0;
+  if (z.total == ~uint64_t(0) || z.total > ~uint64_t(0) / (4 * uint64_t(P.d)))
+    z.err = kErrOverflow;
+  else if (P.out_rows_cap && z.total > P.out_rows_cap)
+    z.err = kErrCapacity;
+  z.T = slice_rows(z.err ? 0 : z.total, P.want_tiles);
+  z.ntiles = z.err ? 0 : (z.total + z.T - 1) / z.T;
+  if (z.ntiles > P.want_tiles) {
+    z.err = kErrSlices;
+    z.ntiles = 0;
+  }
+  return z;
 }
 
 // One query's share of a batched launch.
@@ -169,7 +198,8 @@ hipError_t launch_memo_chain_window(const uint32_t* h, int k, uint64_t top, uint
                                     uint32_t* nat, uint64_t* off_out, int* err, hipStream_t s);
 hipError_t launch_memo_global(const uint32_t* h, int k, uint64_t top, uint32_t b,
                               const uint64_t* off, const uint64_t* ge, uint64_t ge_stride,
-                              uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s);
+                              uint64_t* srcw, uint32_t* nat, int* err, hipStream_t s,
+                              uint64_t rows);
 LeafJob make_leaf_job(int k, uint64_t n, uint32_t G, const uint64_t* off, const uint32_t* nat,
                       const uint64_t* cu, const uint64_t* endc, uint32_t* leaf,
                       uint64_t leaf_rows, const EnumParams& P);

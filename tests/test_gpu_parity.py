@@ -419,6 +419,55 @@ def test_errors():
     assert not host.any()
 
 
+def test_fixed_k_path_matches_the_readback_path(monkeypatch):
+    """k = 1 or 2 fixed by the caller with automatic slices: every launch is
+    enqueued at once and the device sizes the slices from |Z(n)|.  Its bytes,
+    checksums and error statuses equal the path that reads |Z(n)| back first
+    (ZSET_FIXED_K_READBACK=1), and the oracle's rows."""
+    cases = [(2000, [7, 11, 13, 17]), (1000, [13, 37, 38, 40, 41, 42, 43]), (60, [1, 1, 1, 1]),
+             (3, [5, 7, 9]), (700, [10, 12, 14, 16, 19]), (0, [4, 6])]
+    cases += list(bounded_queries(73, 6, dmax=6, gmax=30, nmax=800))
+    for n, g in cases:
+        want = oracle.enumerate_rows(n, g)
+        for k in (1, 2):
+            if k > len(g) - 1:
+                continue
+            for order in (0, 1):
+                monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
+                got, r = gpu_rows(n, g, k=k, order=order)
+                ref = want if order == 0 else np.ascontiguousarray(want[::-1])
+                assert_same(got, ref, f"fixed k={k} order={order} n={n} g={g}")
+                monkeypatch.setenv("ZSET_FIXED_K_READBACK", "1")
+                got2, r2 = gpu_rows(n, g, k=k, order=order)
+                assert_same(got2, got, f"readback path k={k} order={order} n={n} g={g}")
+                assert r.rows == r2.rows == len(want)
+            monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
+            c = zset.enumerate_ex(n, g, k=k, count_only=True)
+            assert c.rows == len(want) and c.checksum == oracle.checksum(want), (n, g, k)
+    monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
+    g = [7, 11, 13, 17]
+    for k in (1, 2):
+        say(f"fixed k={k}: ECAPACITY with one row too few, nothing written")
+        out = torch.full((81204, 4), -1, dtype=torch.int32, device="cuda")
+        with pytest.raises(zset.ZsetError) as e:
+            zset.enumerate_ex(2000, g, out=out, k=k)
+        assert e.value.status == zset.ECAPACITY
+        assert bool((out == -1).all())
+        out = torch.empty((81205, 4), dtype=torch.int32, device="cuda")
+        r = zset.enumerate_ex(2000, g, out=out, k=k)  # the same buffers, exactly enough rows
+        assert_same(out.cpu().numpy().view(np.uint32), oracle.enumerate_rows(2000, g),
+                    f"fixed k={k} after a refused call")
+    say("fixed k=1: EOVERFLOW for 32 generators equal to 1, n = 100000")
+    with pytest.raises(zset.ZsetError) as e:
+        zset.enumerate_ex(100000, [1] * 32, k=1, count_only=True)
+    assert e.value.status == zset.EOVERFLOW
+    out = torch.full((16, 32), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(zset.ZsetError) as e:
+        zset.enumerate_ex(100000, [1] * 32, out=out, k=1)
+    assert e.value.status == zset.EOVERFLOW
+    assert bool((out == -1).all())
+
+
 def test_alloc_fault_is_reported(monkeypatch):
     say("ENOMEM: ZSET_FAULT=alloc on a memo build")
     monkeypatch.setenv("ZSET_FAULT", "alloc")
