@@ -12,9 +12,13 @@
 //           replaced by its children (the prefixes one coordinate longer), in
 //           order, until the work is spread over enough prefixes (the static
 //           counterpart of re-splitting the heaviest remaining range);
-//   pass 1: one thread per prefix walks the rest and counts the rows;
+//   pass 1: one thread per prefix walks the rest and counts the rows (a
+//           progression of the last two coordinates at a time);
 //   scan:   exclusive sum of the counts = each prefix's first output row;
-//   pass 2: the same walk again, writing every row at its place.
+//   pass 2: the same walk again, 64 consecutive prefixes per wavefront (their
+//           rows are one contiguous range): each lane stages a few rows of its
+//           own in LDS, and the wavefront writes the staged words with
+//           consecutive lanes on consecutive words of the output.
 //
 // The walk below a prefix takes coordinates m..d-3 one value at a time.  For
 // the last free coordinate a_{d-1} only values that leave a remainder divisible
@@ -57,91 +61,246 @@ struct WalkArgs {
   uint64_t* cnt;             // pass 1 output
   const uint64_t* off;       // pass 2 input (exclusive sums of cnt)
   uint32_t* out;             // rows, d uint32 each
+  DivMod32 dg[kMaxD];        // division by g_j
+  DivMod32 dh, dstep;        // division by h and by step
+  uint32_t stage_rows;       // pass 2: rows each lane stages in LDS per round
 };
 
-// The walk below one prefix record: a_1..a_m fixed, a_{m+1} in [lo, hi],
-// later coordinates free.  WRITE = false counts the rows, WRITE = true stores
-// them from row `first`.
-template <bool WRITE>
-__device__ uint64_t walk_prefix(const WalkArgs& A, uint64_t i, uint64_t first) {
+// The walk below one prefix record (a_1..a_m fixed, a_{m+1} in [lo, hi],
+// later coordinates free) as a resumable generator: a[0..m) the record's
+// coordinates, a[m..d-3] and r[m..d-3] the current node's coordinates and
+// remainders, and the progression of the last two coordinates below it (pn
+// rows left, pv the next value of a_{d-1}, pR the remainder the two share).
+// next_prog moves to the next node in the walk's order; rows are taken from
+// the progression one at a time.  a[] and r[] live in LDS, one column per
+// thread (entry j at j * kWalkThreads), as do the generators and their
+// divisions: indexed per lane, registers would spill to scratch and kernel
+// arguments would be read from memory, and either load would wait for the
+// wavefront's earlier stores.
+struct WalkState {
+  int m, j;
+  bool done;
+  uint32_t lo, hi;
+  uint32_t* a;  // this thread's columns
+  uint32_t* r;
+  uint32_t pR, pv, pn;
+};
+#define WA(j) S.a[(j) * kWalkThreads]
+#define WR(j) S.r[(j) * kWalkThreads]
+
+struct WalkLds {
+  uint32_t g[kMaxD];
+  DivMod32 dg[kMaxD];
+};
+
+// Rows of the last two coordinates for remainder R with a_{d-1} in
+// [vlo, vhi]: a_{d-1} runs over the progression a0 (mod step), a0 =
+// (R / h) (g_{d-1} / h)^{-1} mod step, when h divides R, up to R / g_{d-1}.
+__device__ inline void prog_setup(const WalkArgs& A, const WalkLds& W, WalkState& S, uint32_t R,
+                                  uint32_t vlo, uint32_t vhi) {
   const int d = A.d;
-  const uint32_t* p = A.pre + i * uint64_t(d + 3);
-  const int m = int(p[0]);
-  const uint32_t lo = p[2], hi = p[3];
-  uint32_t a[kMaxD], r[kMaxD];
-  uint64_t rows = 0;
-  auto emit = [&](uint32_t al, uint32_t last) {  // al = a_{d-1}
-    if (WRITE) {
-      uint32_t* row = A.out + (first + rows) * uint64_t(d);
-      for (int j = 0; j < m; ++j) row[j] = p[4 + j];
-      for (int j = m; j < d - 2; ++j) row[j] = a[j];
-      row[d - 2] = al;
-      row[d - 1] = last;
-    }
-    ++rows;
-  };
-  const uint32_t g2 = A.g.g[d - 2], g1 = A.g.g[d - 1];
-  // Rows of the last two coordinates for remainder R with a_{d-1} in
-  // [vlo, vhi], in order: a_{d-1} runs over a progression of difference step.
-  auto progression = [&](uint32_t R, uint32_t vlo, uint32_t vhi) {
-    if (R % A.h != 0) return;
-    const uint64_t amax = min(uint64_t(R / g2), uint64_t(vhi));
-    const uint64_t a0 = (uint64_t((R / A.h) % A.step) * A.inv) % A.step;
-    const uint64_t v0 = vlo > a0 ? a0 + (uint64_t(vlo) - a0 + A.step - 1) / A.step * A.step : a0;
-    if (v0 > amax) return;
-    const uint64_t nv = (amax - v0) / A.step + 1;
-    for (uint64_t t = 0; t < nv; ++t) {
-      const uint32_t v = uint32_t(A.desc ? v0 + (nv - 1 - t) * A.step : v0 + t * A.step);
-      emit(v, (R - v * g2) / g1);
-    }
-  };
-  if (m == d - 1) {  // only the last coordinate is left: forced
-    if (p[1] % g1 == 0) {
-      if (WRITE) {
-        uint32_t* row = A.out + first * uint64_t(d);
-        for (int j = 0; j < d - 1; ++j) row[j] = p[4 + j];
-        row[d - 1] = p[1] / g1;
-      }
-      ++rows;
-    }
-    return rows;
+  S.pn = 0;
+  S.pR = R;
+  const uint32_t qh = A.dh.div(R);
+  if (A.dh.mod(R, qh) != 0) return;
+  const uint32_t rh = A.dstep.mod(qh, A.dstep.div(qh));
+  uint32_t a0;
+  if (A.step <= 65536u) {
+    const uint32_t t = rh * A.inv;  // both below step: no overflow
+    a0 = A.dstep.mod(t, A.dstep.div(t));
+  } else {
+    a0 = uint32_t((uint64_t(rh) * A.inv) % A.step);
   }
-  if (m == d - 2) {
-    progression(p[1], lo, hi);
-    return rows;
-  }
-  int j = m;
-  r[j] = p[1];
-  a[j] = A.desc ? hi : lo;
-  for (;;) {
-    // Descend to coordinate d - 3 with the first value at each level.
-    while (j < d - 3) {
-      r[j + 1] = r[j] - a[j] * A.g.g[j];
-      ++j;
-      a[j] = A.desc ? r[j] / A.g.g[j] : 0;
-    }
-    progression(r[j] - a[j] * A.g.g[j], 0, 0xffffffffu);
-    // Next value at the deepest level that has one (level m keeps to [lo, hi]).
-    for (; j >= m; --j) {
-      const uint32_t end = A.desc ? (j == m ? lo : 0u) : (j == m ? hi : r[j] / A.g.g[j]);
-      if (a[j] != end) break;
-    }
-    if (j < m) break;
-    a[j] = A.desc ? a[j] - 1 : a[j] + 1;
-  }
-  return rows;
+  const uint32_t qmax = W.dg[d - 2].div(R);  // (an explicit compare: min() of two uint32_t
+  const uint32_t amax = qmax < vhi ? qmax : vhi;  // can resolve to the int overload)
+  uint64_t v0 = a0;
+  if (vlo > a0) v0 = a0 + (uint64_t(vlo) - a0 + A.step - 1) / A.step * A.step;
+  if (v0 > amax) return;
+  S.pn = A.dstep.div(amax - uint32_t(v0)) + 1;
+  S.pv = A.desc ? uint32_t(v0) + (S.pn - 1) * A.step : uint32_t(v0);
 }
 
+// Descend from level j to level d - 3, each coordinate at its first value
+// (the last, in descending order), and set up that node's progression.
+__device__ inline void descend(const WalkArgs& A, const WalkLds& W, WalkState& S) {
+  const int d = A.d;
+  int j = S.j;
+  while (j < d - 3) {
+    WR(j + 1) = WR(j) - WA(j) * W.g[j];
+    ++j;
+    WA(j) = A.desc ? W.dg[j].div(WR(j)) : 0;
+  }
+  S.j = j;
+  prog_setup(A, W, S, WR(j) - WA(j) * W.g[j], 0, 0xffffffffu);
+}
+
+__device__ inline void walk_init(const WalkArgs& A, const WalkLds& W, WalkState& S,
+                                 const uint32_t* p) {
+  const int d = A.d;
+  S.m = int(p[0]);
+  S.lo = p[2];
+  S.hi = p[3];
+  S.done = false;
+  S.pn = 0;
+  for (int j = 0; j < S.m && j < d - 2; ++j) WA(j) = p[4 + j];
+  if (S.m == d - 1) {  // a_1..a_{d-1} fixed: the last coordinate is forced
+    S.done = true;     // a progression of one row (a_{d-1} = p[4 + d - 2]) or none
+    const uint32_t x = p[1];
+    const uint32_t q = W.dg[d - 1].div(x);
+    if (W.dg[d - 1].mod(x, q) == 0) {
+      S.pn = 1;
+      S.pv = p[4 + d - 2];
+      S.pR = x + S.pv * W.g[d - 2];  // so that (pR - pv g_{d-1}) / g_d = x / g_d
+    }
+    return;
+  }
+  if (S.m == d - 2) {  // one progression over a_{d-1} in [lo, hi]
+    S.done = true;
+    prog_setup(A, W, S, p[1], S.lo, S.hi);
+    return;
+  }
+  S.j = S.m;
+  WR(S.m) = p[1];
+  WA(S.m) = A.desc ? S.hi : S.lo;
+  descend(A, W, S);
+}
+
+// The next node at level d - 3 in the walk's order (its progression set
+// up), or done: the deepest level below m whose coordinate can still move,
+// else level m within [lo, hi].
+__device__ inline void next_prog(const WalkArgs& A, const WalkLds& W, WalkState& S) {
+  int j = S.j;
+  while (j > S.m) {
+    const uint32_t last = A.desc ? 0u : W.dg[j].div(WR(j));
+    if (WA(j) != last) break;
+    --j;
+  }
+  if (j == S.m && WA(j) == (A.desc ? S.lo : S.hi)) {
+    S.done = true;
+    return;
+  }
+  WA(j) = A.desc ? WA(j) - 1 : WA(j) + 1;
+  S.j = j;
+  descend(A, W, S);
+}
+
+__device__ inline void walk_lds_init(const WalkArgs& A, WalkLds& W) {
+  if (threadIdx.x < uint32_t(kMaxD)) {
+    W.g[threadIdx.x] = A.g.g[threadIdx.x];
+    W.dg[threadIdx.x] = A.dg[threadIdx.x];
+  }
+  __syncthreads();
+}
+
+// Pass 1: one thread per record counts its rows (a progression at a time).
 __global__ __launch_bounds__(kWalkThreads) void k_walk_count(WalkArgs A) {
+  __shared__ WalkLds W;
+  extern __shared__ uint32_t cols[];  // a[] then r[]: (d - 2) columns each
+  walk_lds_init(A, W);
+  const uint32_t levels = uint32_t(A.d > 2 ? A.d - 2 : 1);
   for (uint64_t i = uint64_t(blockIdx.x) * kWalkThreads + threadIdx.x; i < A.nprefix;
-       i += uint64_t(gridDim.x) * kWalkThreads)
-    A.cnt[i] = walk_prefix<false>(A, i, 0);
+       i += uint64_t(gridDim.x) * kWalkThreads) {
+    WalkState S;
+    S.a = cols + threadIdx.x;
+    S.r = cols + levels * kWalkThreads + threadIdx.x;
+    walk_init(A, W, S, A.pre + i * uint64_t(A.d + 3));
+    uint64_t rows = S.pn;
+    while (!S.done) {
+      next_prog(A, W, S);
+      if (!S.done) rows += S.pn;
+    }
+    A.cnt[i] = rows;
+  }
 }
 
+__device__ inline void wave_sync_walk() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Pass 2: a wavefront takes 64 consecutive records, one per lane.  In
+// rounds, every lane stages up to stage_rows rows of its record in LDS (each
+// lane's rows are contiguous in the output); then the wavefront writes the
+// staged words two lanes' rows at a time, consecutive lanes on consecutive
+// words: a store instruction covers two contiguous runs instead of 64
+// scattered words.
+constexpr uint32_t kWalkLaneWords = 32;  // LDS words staged per lane per round
 __global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
-  for (uint64_t i = uint64_t(blockIdx.x) * kWalkThreads + threadIdx.x; i < A.nprefix;
-       i += uint64_t(gridDim.x) * kWalkThreads)
-    (void)walk_prefix<true>(A, i, A.off[i]);
+  __shared__ WalkLds W;
+  __shared__ uint32_t stage[kWalkThreads * kWalkLaneWords];
+  extern __shared__ uint32_t cols[];  // a[] then r[]: (d - 2) columns each
+  walk_lds_init(A, W);
+  const uint32_t levels = uint32_t(A.d > 2 ? A.d - 2 : 1);
+  const int lane = int(threadIdx.x & 63);
+  const int wave = int(threadIdx.x >> 6);
+  uint32_t* buf = stage + uint32_t(threadIdx.x) * kWalkLaneWords;
+  const uint32_t* wstage = stage + uint32_t(wave) * 64 * kWalkLaneWords;
+  const int d = A.d;
+  const uint32_t g2 = W.g[d - 2];
+  const DivMod32 dlast = W.dg[d - 1];
+  const uint64_t waves = uint64_t(gridDim.x) * (kWalkThreads / 64);
+  for (uint64_t w = uint64_t(blockIdx.x) * (kWalkThreads / 64) + uint64_t(wave);
+       w * 64 < A.nprefix; w += waves) {
+    const uint64_t i = w * 64 + uint64_t(lane);
+    const bool has = i < A.nprefix;
+    WalkState S;
+    S.a = cols + threadIdx.x;
+    S.r = cols + levels * kWalkThreads + threadIdx.x;
+    uint64_t pos = 0;
+    S.done = true;
+    S.pn = 0;
+    if (has) {
+      walk_init(A, W, S, A.pre + i * uint64_t(d + 3));
+      pos = A.off[i];
+    }
+    for (;;) {
+      // Stage up to stage_rows rows (divergent: each lane in its own walk).
+      uint32_t nb = 0;
+      while (nb < A.stage_rows) {
+        if (S.pn == 0) {
+          if (S.done) break;
+          next_prog(A, W, S);
+          continue;
+        }
+        uint32_t* row = buf + nb * uint32_t(d);
+        for (int j = 0; j < d - 2; ++j) row[j] = WA(j);
+        row[d - 2] = S.pv;
+        row[d - 1] = dlast.div(S.pR - S.pv * g2);
+        ++nb;
+        --S.pn;
+        if (S.pn) S.pv = A.desc ? S.pv - A.step : S.pv + A.step;
+      }
+      const bool more = !(S.done && S.pn == 0);
+      // Flush: two lanes' staged rows per step, lanes 0-31 on the first
+      // one's words and lanes 32-63 on the second's (at most 32 words each),
+      // so that every store instruction covers two contiguous runs.
+      const uint32_t wl = nb * uint32_t(d);
+      const uint64_t gw = pos * uint64_t(d);  // this lane's first output word
+      const uint32_t gw_lo = uint32_t(gw), gw_hi = uint32_t(gw >> 32);
+      wave_sync_walk();  // the staged rows are visible to the wavefront
+      const bool upper = lane >= 32;
+      const uint32_t t = uint32_t(lane) & 31u;
+      for (int s2 = 0; s2 < 64; s2 += 2) {
+        const uint32_t wa = __builtin_amdgcn_readlane(wl, s2);
+        const uint32_t wb = __builtin_amdgcn_readlane(wl, s2 + 1);
+        if ((wa | wb) == 0) continue;
+        const uint32_t w = upper ? wb : wa;
+        const uint32_t lo = upper ? __builtin_amdgcn_readlane(gw_lo, s2 + 1)
+                                  : __builtin_amdgcn_readlane(gw_lo, s2);
+        const uint32_t hi = upper ? __builtin_amdgcn_readlane(gw_hi, s2 + 1)
+                                  : __builtin_amdgcn_readlane(gw_hi, s2);
+        if (t < w) {
+          const uint32_t src = uint32_t(s2) + (upper ? 1u : 0u);
+          const uint32_t v = wstage[src * kWalkLaneWords + t];
+          __builtin_nontemporal_store(v, A.out + ((uint64_t(hi) << 32) | lo) + t);
+        }
+      }
+      wave_sync_walk();  // every lane has read the staged rows
+      pos += nb;
+      if (__ballot(more) == 0) break;
+    }
+  }
 }
 
 // Host side: prefix records and their estimated work.
@@ -376,13 +535,18 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
   A.h = h;
   A.step = gens[d - 1] / A.h;
   A.inv = inverse_mod((gens[d - 2] / A.h) % A.step, A.step);
+  for (int i = 0; i < d; ++i) A.dg[i] = DivMod32::make(gens[i]);
+  A.dh = DivMod32::make(A.h);
+  A.dstep = DivMod32::make(A.step);
+  A.stage_rows = std::max<uint32_t>(1, kWalkLaneWords / uint32_t(d));
   A.nprefix = np;
   A.pre = reinterpret_cast<const uint32_t*>(c.pre.p);
   A.cnt = reinterpret_cast<uint64_t*>(c.cnt.p);
   A.off = reinterpret_cast<const uint64_t*>(c.off.p);
   A.out = out;
   const uint64_t blocks = std::min<uint64_t>((np + kWalkThreads - 1) / kWalkThreads, 65535);
-  hipLaunchKernelGGL(k_walk_count, dim3(uint32_t(blocks)), dim3(kWalkThreads), 0, s, A);
+  const size_t cols_bytes = size_t(2) * std::max(d - 2, 1) * kWalkThreads * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_walk_count, dim3(uint32_t(blocks)), dim3(kWalkThreads), cols_bytes, s, A);
   ZSET_HIP(hipGetLastError());
   // off[i] = rows of prefixes before i; off[np] = |Z(n)| (cnt[np] is zero).
   ZSET_HIP(hipMemsetAsync(A.cnt + np, 0, sizeof(uint64_t), s));
@@ -396,7 +560,8 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
     return fail(ZSET_ECAPACITY, "out holds " + std::to_string(out_rows_cap) + " rows, |Z(n)| = " +
                                     std::to_string(total));
   if (total > 0) {
-    hipLaunchKernelGGL(k_walk_write, dim3(uint32_t(blocks)), dim3(kWalkThreads), 0, s, A);
+    hipLaunchKernelGGL(k_walk_write, dim3(uint32_t(blocks)), dim3(kWalkThreads), cols_bytes, s,
+                       A);
     ZSET_HIP(hipGetLastError());
     ZSET_HIP(hipStreamSynchronize(s));
   }

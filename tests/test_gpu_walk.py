@@ -40,6 +40,25 @@ def test_walk_matches_oracle_small(seed):
     assert np.array_equal(walk(n, g, 1, len(want)), want[::-1])
 
 
+@pytest.mark.parametrize("d", [2, 3, 9, 17, 32])
+def test_walk_row_widths(d):
+    """Rows of 2 to 32 words: each lane stages 16 rows (d = 2) down to one
+    (d >= 17) per round, and the wavefront's writes cross lanes' row runs."""
+    rng = np.random.default_rng(77 + d)
+    cases = 0
+    while cases < 3:
+        g = [int(x) for x in rng.integers(2, 40 if d <= 9 else 90, size=d)]
+        n = int(rng.integers(10, 400 if d <= 9 else 160))
+        c = oracle.count(n, g)
+        if c == 0 or c > 200_000:
+            continue
+        want = oracle.enumerate_rows(n, g)
+        say(f"d={d}: n={n} g={g} rows={c}")
+        assert np.array_equal(walk(n, g, 0, c), want)
+        assert np.array_equal(walk(n, g, 1, c), want[::-1])
+        cases += 1
+
+
 def test_walk_matches_count_table_path():
     g = [13, 34, 37, 54, 65, 83]
     for n in (0, 12, 13, 700, 2400):
