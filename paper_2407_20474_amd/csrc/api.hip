@@ -74,6 +74,7 @@ struct Ctx {
   // own end.
   hipStream_t plan = nullptr;
   hipEvent_t counted = nullptr, planned = nullptr;
+  int wall_khz = 0;  // the device's constant-rate clock (kernel time stamps)
 };
 
 std::map<int, Ctx*> g_ctx;
@@ -88,10 +89,10 @@ constexpr uint64_t kSharedSlicesPerWave = 8;
 
 // misc layout (uint64 words): [0] status word (int), [1] checksum, [2..] the
 // count table's row sums, |Z(n)| and row maxima (2 kMaxD + 3 words), then the
-// write pass's chunk counter.
+// write pass's chunk counter and two kernel time stamps.
 constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2,
-              kMiscPool = kMiscRowSums + 2 * kMaxD + 3;
-constexpr size_t kMiscWords = kMiscPool + 1;
+              kMiscPool = kMiscRowSums + 2 * kMaxD + 3, kMiscStamp = kMiscPool + 1;
+constexpr size_t kMiscWords = kMiscStamp + 2;
 constexpr int kDefaultClaimPct = 100;  // percent of slices claimed at run time
 constexpr size_t kPinnedWords = 128;
 
@@ -126,6 +127,10 @@ zset_status get_ctx(Ctx** out) {
       hipStreamCreateWithFlags(&c->plan, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ZSET_EDEVICE, "side stream or event creation failed");
+  }
+  if (hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    c->wall_khz = 0;
   }
   zset_status st = ensure(c->misc, kMiscWords * sizeof(uint64_t));
   if (st != ZSET_OK) return st;
@@ -684,6 +689,9 @@ namespace {
 // larger generator.  Returns false when that takes more than kHostCountSteps
 // steps.
 constexpr uint64_t kHostCountSteps = 1 << 16;
+// Memo rows the setup launch's one memo workgroup builds, at most (larger
+// memos take the element-parallel launches).
+constexpr uint64_t kSetupMemoRows = uint64_t(1) << 19;
 bool host_memo_rows(uint64_t n, const uint32_t* h, int k, uint64_t* rows) {
   if (k == 1) {
     *rows = n / h[0] + 1;
@@ -769,49 +777,90 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
   uint64_t* off = reinterpret_cast<uint64_t*>(c->off.p);
   uint32_t* nat = reinterpret_cast<uint32_t*>(c->nat.p);
 
-  // Enqueued in the order of the critical path: status words clear, count
-  // table, class ends and slice plan on the call's stream; then the memo
-  // (closed form) on the side stream, which needs only the status reset and
-  // runs beside them; then the leaf layout (after the memo) and the write
-  // pass.  The host's enqueue time would otherwise delay the count table.
-  ZSET_HIP(hipEventRecord(c->ev[0], s));
-  ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
-  ZSET_HIP(hipEventRecord(c->fork, s));
-  ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
-  ZSET_HIP(hipEventRecord(c->ev[1], s));
-  uint32_t nclass = 0;
-  ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc), &nclass,
-                             s));
-  ZSET_HIP(launch_plan_device_sized(P, s));
-  ZSET_HIP(hipEventRecord(c->ev[3], s));
-  struct SideJoin {
-    Ctx* c = nullptr;
-    ~SideJoin() {
-      if (c) (void)hipStreamSynchronize(c->side);
-    }
-  } side_join;
-  ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
-  side_join.c = c;
-  ZSET_HIP(hipEventRecord(c->memo0, c->side));
-  if (k == 2)
-    ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn, nat, off,
-                            reinterpret_cast<uint64_t*>(c->cnt2.p), c->side));
-  else
-    ZSET_HIP(launch_memo_k1(gens[L], N, Rn, nat, off, c->side));
-  ZSET_HIP(hipEventRecord(c->memo1, c->side));
-  ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
-  ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
-                                          const_cast<uint32_t*>(P.leaf), Rn, P),
-                            err, s));
-  ZSET_HIP(hipEventRecord(c->ev[4], s));
-  ZSET_HIP(launch_write(P, count_only, align16, s));
-  ZSET_HIP(hipEventRecord(c->ev[5], s));
-  // Status, checksum and |Z(n)| in one readback.
-  static_assert(kMiscErr == 0 && kMiscSum == 1 && kMiscRowSums == 2, "misc layout");
-  ZSET_HIP(hipMemcpyAsync(c->pinned, misc, (kMiscRowSums + d + 2) * sizeof(uint64_t),
-                          hipMemcpyDeviceToHost, s));
-  ZSET_HIP(hipStreamSynchronize(s));
-  side_join.c = nullptr;  // the call's stream waited for the side stream
+  const bool fused = N <= count_table_lds_max() && Rn <= kSetupMemoRows &&
+                     !std::getenv("ZSET_COUNT_PATH") && !std::getenv("ZSET_FIXED_K_SPLIT");
+  if (fused) {
+    // Three launches: setup (count table and class ends in one workgroup,
+    // the memo in another; status words cleared), slice plan and leaf layout
+    // in one grid, write pass.  Fewer launches is less host enqueue time
+    // ahead of the write pass.
+    SetupJob J;
+    std::memset(&J, 0, sizeof J);
+    J.table = T;
+    J.sums = misc + kMiscRowSums;
+    J.status = misc;
+    for (int i = 0; i < d; ++i) J.g.g[i] = gens[i];
+    J.N = uint32_t(N);
+    J.d = d;
+    J.U = U;
+    J.nclass = P.nclass;
+    J.dG = DivMod32::make(G);
+    J.endc = const_cast<uint64_t*>(P.endc);
+    J.k = k;
+    if (k == 2) J.M = make_memo2(gens[L], gens[L + 1]);
+    J.h1 = gens[L];
+    J.R = uint32_t(Rn);
+    J.nat = nat;
+    J.off = off;
+    J.stamps = misc + kMiscStamp;
+    const bool timed = stats != nullptr;  // no timing events without stats
+    if (timed) ZSET_HIP(hipEventRecord(c->ev[0], s));
+    ZSET_HIP(launch_setup_fixed(J, s));
+    if (timed) ZSET_HIP(hipEventRecord(c->ev[1], s));
+    ZSET_HIP(launch_plan_leaf(P, make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                               const_cast<uint32_t*>(P.leaf), Rn, P),
+                              s));
+    if (timed) ZSET_HIP(hipEventRecord(c->ev[4], s));
+    ZSET_HIP(launch_write(P, count_only, align16, s));
+    if (timed) ZSET_HIP(hipEventRecord(c->ev[5], s));
+    ZSET_HIP(hipMemcpyAsync(c->pinned, misc, kMiscWords * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s));
+    ZSET_HIP(hipStreamSynchronize(s));
+  } else {
+    // Enqueued in the order of the critical path: status words clear, count
+    // table, class ends and slice plan on the call's stream; then the memo
+    // (closed form) on the side stream, which needs only the status reset and
+    // runs beside them; then the leaf layout (after the memo) and the write
+    // pass.  The host's enqueue time would otherwise delay the count table.
+    ZSET_HIP(hipEventRecord(c->ev[0], s));
+    ZSET_HIP(hipMemsetAsync(misc, 0, 2 * sizeof(uint64_t), s));
+    ZSET_HIP(hipEventRecord(c->fork, s));
+    ZSET_HIP(launch_count_table(T, n, gens, d, misc + kMiscRowSums, s));
+    ZSET_HIP(hipEventRecord(c->ev[1], s));
+    uint32_t nclass = 0;
+    ZSET_HIP(launch_class_ends(T + uint64_t(U) * N, n, G, const_cast<uint64_t*>(P.endc), &nclass,
+                               s));
+    ZSET_HIP(launch_plan_device_sized(P, s));
+    ZSET_HIP(hipEventRecord(c->ev[3], s));
+    struct SideJoin {
+      Ctx* c = nullptr;
+      ~SideJoin() {
+        if (c) (void)hipStreamSynchronize(c->side);
+      }
+    } side_join;
+    ZSET_HIP(hipStreamWaitEvent(c->side, c->fork, 0));
+    side_join.c = c;
+    ZSET_HIP(hipEventRecord(c->memo0, c->side));
+    if (k == 2)
+      ZSET_HIP(launch_memo_k2(gens[L], gens[L + 1], N, Rn, nat, off,
+                              reinterpret_cast<uint64_t*>(c->cnt2.p), c->side));
+    else
+      ZSET_HIP(launch_memo_k1(gens[L], N, Rn, nat, off, c->side));
+    ZSET_HIP(hipEventRecord(c->memo1, c->side));
+    ZSET_HIP(hipStreamWaitEvent(s, c->memo1, 0));
+    ZSET_HIP(launch_memo_leaf(make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                                            const_cast<uint32_t*>(P.leaf), Rn, P),
+                              err, s));
+    ZSET_HIP(hipEventRecord(c->ev[4], s));
+    ZSET_HIP(launch_write(P, count_only, align16, s));
+    ZSET_HIP(hipEventRecord(c->ev[5], s));
+    // Status, checksum and |Z(n)| in one readback.
+    static_assert(kMiscErr == 0 && kMiscSum == 1 && kMiscRowSums == 2, "misc layout");
+    ZSET_HIP(hipMemcpyAsync(c->pinned, misc, (kMiscRowSums + d + 2) * sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, s));
+    ZSET_HIP(hipStreamSynchronize(s));
+    side_join.c = nullptr;  // the call's stream waited for the side stream
+  }
   const int code = *reinterpret_cast<int*>(c->pinned);
   const uint64_t total = c->pinned[kMiscRowSums + d + 1];
   if (code == kErrOverflow) {
@@ -831,9 +880,19 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
     // count: the status reset and the count table; plan: class ends and
     // slice plan; memo: the closed form on the side stream and the leaf
     // layout (from the plan's end).
-    stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
-    stats->plan_us = elapsed_us(c->ev[1], c->ev[3]);
-    stats->memo_us = elapsed_us(c->memo0, c->memo1) + elapsed_us(c->ev[3], c->ev[4]);
+    if (fused) {
+      // count: the setup launch (count table and class ends, the memo beside
+      // them); memo: the memo workgroup's own time (device clock); plan: the
+      // slice plan and leaf layout launch.
+      stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
+      const uint64_t t0 = c->pinned[kMiscStamp], t1 = c->pinned[kMiscStamp + 1];
+      stats->memo_us = c->wall_khz > 0 && t1 >= t0 ? double(t1 - t0) * 1000.0 / c->wall_khz : 0.0;
+      stats->plan_us = elapsed_us(c->ev[1], c->ev[4]);
+    } else {
+      stats->count_us = elapsed_us(c->ev[0], c->ev[1]);
+      stats->plan_us = elapsed_us(c->ev[1], c->ev[3]);
+      stats->memo_us = elapsed_us(c->memo0, c->memo1) + elapsed_us(c->ev[3], c->ev[4]);
+    }
     stats->write_us = elapsed_us(c->ev[4], c->ev[5]);
     stats->total_us = elapsed_us(c->ev[0], c->ev[5]);
     stats->rows = total;

@@ -319,6 +319,129 @@ __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __rest
   if (threadIdx.x == 0 && sums) sums[d + 1] = buf[N - 1];  // |Z(n)| = C[0][n] (row 0 in LDS)
 }
 
+// Inclusive prefix sums (saturating) of load(0..count-1) into out, by the
+// whole 1024-thread workgroup: rounds of 4096 entries, 4 consecutive entries
+// per thread, a DPP scan per wavefront and the wavefront totals in wtot.
+template <class Load>
+__device__ inline void block_scan_incl_u64(uint32_t count, Load load, uint64_t* __restrict__ out,
+                                           uint64_t* wtot) {
+  constexpr int kWaves = kCtThreads / kWave;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  uint64_t carry = 0;
+  for (uint32_t base = 0; base < count; base += kCtThreads * 4) {
+    const uint32_t first = base + uint32_t(tid) * 4;
+    uint64_t v[4];
+    uint64_t run = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      run = sat_add_u64(run, first + q < count ? load(first + q) : 0);
+      v[q] = run;
+    }
+    const uint64_t incl = wave_incl_scan_sat_u64(run, kWave);
+    if (lane == kWave - 1) wtot[wave] = incl;
+    lds_barrier();
+    uint64_t before = carry, tot = 0;
+    for (int w = 0; w < kWaves; ++w) {
+      if (w < wave) before = sat_add_u64(before, wtot[w]);
+      tot = sat_add_u64(tot, wtot[w]);
+    }
+    const uint64_t up = __shfl_up(incl, 1, kWave);
+    before = sat_add_u64(before, lane ? up : 0);
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q)
+      if (first + q < count) out[first + q] = sat_add_u64(before, v[q]);
+    carry = sat_add_u64(carry, tot);
+    lds_barrier();
+  }
+}
+
+// The first launch of a fixed-k call (SetupJob, zset_internal.h).  Workgroup
+// 0: status words, count table, |Z(n)|, then the class ends of the leaf
+// layout, end[r] = sum over r' <= r of C_U[pmax(r')] with pmax(r) = r +
+// floor((n - r) / G) G the largest element <= n in class r.  Workgroup 1: the
+// memo in natural order, off[p] = rows of the elements below p (p = 0..top),
+// rows in ascending order of p and, within p, the closed form's order.
+__global__ __launch_bounds__(kCtThreads) void k_setup_fixed(SetupJob J) {
+  __shared__ uint64_t buf[kCtLdsMax];
+  __shared__ uint32_t g[kMaxD];
+  __shared__ uint64_t wtot[kCtThreads / kWave];
+  const int tid = threadIdx.x;
+  if (blockIdx.x == 0) {
+    if (tid == 0) {
+      J.status[0] = 0;
+      J.status[1] = 0;
+    }
+    if (tid < kMaxD) g[tid] = J.g.g[tid];
+    __syncthreads();
+    count_table_lds(J.table, J.N, g, J.d, J.sums, J.sums + J.d + 2, buf, J.walk);
+    if (tid == 0) J.sums[J.d + 1] = buf[J.N - 1];
+    __syncthreads();  // the table's global rows are visible to the workgroup
+    const uint64_t* CU = J.table + uint64_t(J.U) * J.N;
+    const uint32_t n = J.N - 1;
+    const DivMod32 dG = J.dG;
+    block_scan_incl_u64(
+        J.nclass,
+        [&](uint32_t r) { return CU[uint64_t(r) + uint64_t(dG.div(n - r)) * dG.d]; }, J.endc,
+        wtot);
+    return;
+  }
+  if (tid == 0) J.stamps[0] = wall_clock64();
+  const uint32_t top = J.N;
+  if (J.k == 1) {
+    // Memo[p] = {(p / h)} when h divides p (the recurrence's closed solution).
+    const uint64_t h = J.h1;
+    for (uint32_t i = tid; i <= top; i += kCtThreads) {
+      J.off[i] = (uint64_t(i) + h - 1) / h;
+      if (i < J.R) J.nat[i] = i;
+    }
+  } else {
+    uint64_t carry = 0;
+    for (uint32_t base = 0; base <= top; base += kCtThreads * 4) {
+      const uint32_t first = base + uint32_t(tid) * 4;
+      uint32_t m0[4], rows[4];
+      uint64_t ex[4];
+      uint64_t run = 0;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t p = first + q;
+        rows[q] = 0;
+        m0[q] = 0;
+        if (p < top) (void)memo2_first(J.M, p, &m0[q], &rows[q]);  // element top: no rows
+        ex[q] = run;
+        run += rows[q];
+      }
+      constexpr int kWaves = kCtThreads / kWave;
+      const int lane = tid & (kWave - 1), wave = tid / kWave;
+      const uint64_t incl = wave_incl_scan_sat_u64(run, kWave);
+      if (lane == kWave - 1) wtot[wave] = incl;
+      lds_barrier();
+      uint64_t before = carry, tot = 0;
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) before += wtot[w];
+        tot += wtot[w];
+      }
+      const uint64_t up = __shfl_up(incl, 1, kWave);
+      before += lane ? up : 0;
+#pragma unroll
+      for (uint32_t q = 0; q < 4; ++q) {
+        const uint32_t p = first + q;
+        if (p > top) break;
+        const uint64_t o = before + ex[q];
+        J.off[p] = o;
+        for (uint32_t t = 0; t < rows[q] && o + t < J.R; ++t) {
+          const uint32_t m1 = m0[q] + t * J.M.h2c;
+          J.nat[(o + t) * 2] = m1;
+          J.nat[(o + t) * 2 + 1] = (p - m1 * J.M.h1) / J.M.h2;
+        }
+      }
+      carry += tot;
+      lds_barrier();
+    }
+  }
+  __syncthreads();
+  if (tid == 0) J.stamps[1] = wall_clock64();
+}
+
 // ---------------------------------------------------------------------------
 // Tables beyond LDS (n + 1 > kCtLdsMax): one launch per row, all workgroups.
 // Row j's residue classes mod g_j are independent prefix sums of row j+1, so
@@ -520,6 +643,19 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
 }
 
 uint32_t count_table_lds_max() { return kCtLdsMax; }
+
+hipError_t launch_setup_fixed(const SetupJob& J, hipStream_t s) {
+  if (J.N == 0 || J.N > kCtLdsMax || (J.k != 1 && J.k != 2) || J.d < 2 || J.U < 0 ||
+      J.U >= J.d || J.nclass == 0 || J.nclass > J.N)
+    return hipErrorInvalidValue;
+  SetupJob j = J;
+  if (j.walk == 0) {
+    const char* we = std::getenv("ZSET_COUNT_WALK");
+    j.walk = we ? uint32_t(std::atoi(we)) : kColWalk;
+  }
+  hipLaunchKernelGGL(k_setup_fixed, dim3(2), dim3(kCtThreads), 0, s, j);
+  return hipGetLastError();
+}
 
 hipError_t prepare_count_table_batch(uint32_t max_lds_n) {
   const size_t bytes = size_t(max_lds_n) * sizeof(uint64_t);

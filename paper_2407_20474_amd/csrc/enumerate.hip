@@ -158,8 +158,7 @@ __device__ inline void plan_tile_wave(const EnumParams& P, uint64_t tile, uint32
   }
 }
 
-__global__ __launch_bounds__(256) void k_plan(EnumParams P) {
-  const uint64_t tile = uint64_t(blockIdx.x) * 256 + threadIdx.x;
+__device__ inline void plan_slice(const EnumParams& P, uint64_t tile) {
   if (tile == 0) {
     if (P.pool) *P.pool = 0;  // the write pass's chunk counter
     if (P.reset_status) {     // a query of its own: status words start clear
@@ -177,6 +176,22 @@ __global__ __launch_bounds__(256) void k_plan(EnumParams P) {
   }
   if (tile >= ntiles) return;
   plan_tile(P, tile, T);
+}
+
+__global__ __launch_bounds__(256) void k_plan(EnumParams P) {
+  plan_slice(P, uint64_t(blockIdx.x) * 256 + threadIdx.x);
+}
+
+// The device-sized planner (workgroups below plan_blocks) and the memo's leaf
+// layout (the others) in one grid: both read only the count table, the class
+// ends and the natural-order memo, and neither waits for the other.
+__global__ __launch_bounds__(256) void k_plan_leaf(EnumParams P, LeafJob J,
+                                                   uint32_t plan_blocks) {
+  if (blockIdx.x < plan_blocks) {
+    plan_slice(P, uint64_t(blockIdx.x) * 256 + threadIdx.x);
+    return;
+  }
+  memo_leaf_row(J, uint64_t(blockIdx.x - plan_blocks) * 256 + threadIdx.x, P.err);
 }
 
 // Batched: global slice index -> (query, slice) by bisection of the slice
@@ -1338,6 +1353,15 @@ hipError_t launch_plan_device_sized(const EnumParams& P, hipStream_t s) {
   if (!P.total_dev || P.want_tiles == 0) return hipErrorInvalidValue;
   const uint64_t blocks = (P.want_tiles + 255) / 256;
   hipLaunchKernelGGL(k_plan, dim3(uint32_t(blocks)), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_plan_leaf(const EnumParams& P, const LeafJob& J, hipStream_t s) {
+  if (!P.total_dev || P.want_tiles == 0) return hipErrorInvalidValue;
+  const uint64_t pb = (P.want_tiles + 255) / 256;
+  const uint64_t lb = std::max<uint64_t>(1, (J.leaf_rows + 255) / 256);
+  if (pb + lb > 0x7fffffffull) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_plan_leaf, dim3(uint32_t(pb + lb)), dim3(256), 0, s, P, J, uint32_t(pb));
   return hipGetLastError();
 }
 

@@ -331,28 +331,7 @@ __global__ __launch_bounds__(256) void k_memo_k1(uint32_t h, uint32_t top, uint3
   memo_k1_item(h, top, R, uint64_t(blockIdx.x) * 256 + threadIdx.x, nat, off);
 }
 
-// k = 2: Z(p; h_1, h_2) in closed form.  With c = gcd(h_1, h_2), p has rows
-// only when c divides p; then m_1 runs over the progression
-// m_1 = m0 (mod h_2 / c), m0 = (p / c) (h_1 / c)^{-1} mod (h_2 / c), from m0
-// to (p / c) / (h_1 / c), and m_2 = (p - m_1 h_1) / h_2.  Every element is
-// independent: a counting pass, an exclusive sum (the natural offsets) and a
-// filling pass replace the recurrence's top / min(h) dependent batches with
-// the same lists in the same ascending order.
-struct Memo2 {
-  uint32_t h1, h2, c, h1c, h2c, inv;  // inv = (h1 / c)^{-1} mod (h2 / c)
-};
-
-__device__ inline bool memo2_first(const Memo2& M, uint32_t p, uint32_t* m0, uint32_t* rows) {
-  if (p % M.c != 0) return false;
-  const uint32_t q = p / M.c;
-  const uint32_t mmax = q / M.h1c;
-  const uint32_t a = uint32_t((uint64_t(q % M.h2c) * M.inv) % M.h2c);
-  if (a > mmax) return false;
-  *m0 = a;
-  *rows = (mmax - a) / M.h2c + 1;
-  return true;
-}
-
+// k = 2: Z(p; h_1, h_2) in closed form (Memo2, memo2_first: zset_internal.h).
 __global__ __launch_bounds__(256) void k_memo2_count(Memo2 M, uint32_t top,
                                                      uint64_t* __restrict__ cnt) {
   const uint64_t p = uint64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -499,36 +478,7 @@ __device__ inline void memo_leaf_element(const LeafJob& J, uint32_t p, int* __re
 // adjacent in both layouts, so neighbouring threads read and write
 // neighbouring rows, and a long list costs no more than many short ones.
 __global__ __launch_bounds__(256) void k_memo_leaf(LeafJob J, int* __restrict__ err) {
-  const uint64_t t = uint64_t(blockIdx.x) * 256 + threadIdx.x;
-  const uint64_t rows = J.off[uint64_t(J.n) + 1];
-  if (J.exact ? (t == 0 && rows != J.leaf_rows) : (t == 0 && rows > J.leaf_rows))
-    set_error(err, kErrMemoTotal);
-  if (t >= rows || t >= J.leaf_rows) return;
-  uint32_t lo = 0, hi = J.n;
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (J.off[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  const uint32_t p = lo;
-  const int k = J.k;
-  const uint32_t q = J.dG.div(p);
-  const uint32_t rho = J.dG.mod(p, q);
-  const uint64_t pos = J.endc[rho] - J.cu[p] + (t - J.off[p]);
-  if (pos >= J.leaf_rows) {
-    set_error(err, kErrMemoTotal);
-    return;
-  }
-  const uint32_t* src = J.nat + t * k;
-  if (J.pack == 0) {
-    uint32_t* dst = J.leaf + pos * (k + 1);
-    dst[0] = q;
-    for (int c = 0; c < k; ++c) dst[1 + c] = src[c];
-  } else {
-    uint64_t w = uint64_t(q) << J.fshift[0];
-    for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << J.fshift[1 + c];
-    if (J.pack == 1) J.leaf[pos] = uint32_t(w);
-    else reinterpret_cast<uint64_t*>(J.leaf)[pos] = w;
-  }
+  memo_leaf_row(J, uint64_t(blockIdx.x) * 256 + threadIdx.x, err);
 }
 
 // Batched: the workgroups of job j are [jobs[j].block0, jobs[j + 1].block0).
@@ -619,9 +569,7 @@ hipError_t launch_memo_chain_window(const uint32_t* h, int k, uint64_t top, uint
 
 uint32_t memo_k1_blocks(uint64_t top) { return uint32_t((top + 1 + 255) / 256); }
 
-hipError_t launch_memo_k2(uint32_t h1, uint32_t h2, uint64_t top, uint64_t cap, uint32_t* nat,
-                          uint64_t* off, uint64_t* cnt, hipStream_t s) {
-  if (top == 0 || top >= 0xffffffffull) return hipErrorInvalidValue;
+Memo2 make_memo2(uint32_t h1, uint32_t h2) {
   auto gcd = [](uint32_t a, uint32_t b) {
     while (b) {
       const uint32_t t = a % b;
@@ -648,6 +596,13 @@ hipError_t launch_memo_k2(uint32_t h1, uint32_t h2, uint64_t top, uint64_t cap, 
     r1 = x;
   }
   M.inv = M.h2c == 1 ? 0 : uint32_t(t0 < 0 ? t0 + M.h2c : t0);
+  return M;
+}
+
+hipError_t launch_memo_k2(uint32_t h1, uint32_t h2, uint64_t top, uint64_t cap, uint32_t* nat,
+                          uint64_t* off, uint64_t* cnt, hipStream_t s) {
+  if (top == 0 || top >= 0xffffffffull) return hipErrorInvalidValue;
+  const Memo2 M = make_memo2(h1, h2);
   const uint32_t blocks = uint32_t((top + 1 + 255) / 256);
   hipLaunchKernelGGL(k_memo2_count, dim3(blocks), dim3(256), 0, s, M, uint32_t(top), cnt);
   hipError_t e = hipGetLastError();

@@ -138,6 +138,95 @@ struct LeafJob {
                             // memo), the rows being off[n + 1]
 };
 
+// One memo row of the leaf-order layout: thread t takes natural-order row t;
+// its element p is the last one with off[p] <= t (bisection of the offsets),
+// and its place in the leaf layout is end[p mod G] - C_U[p] + (t - off[p]).
+// Rows of one element are adjacent in both layouts, so neighbouring threads
+// read and write neighbouring rows, and a long list costs no more than many
+// short ones.  Row 0 also checks the memo's row count against leaf_rows.
+__device__ inline void memo_leaf_row(const LeafJob& J, uint64_t t, int* __restrict__ err) {
+  const uint64_t rows = J.off[uint64_t(J.n) + 1];
+  if (J.exact ? (t == 0 && rows != J.leaf_rows) : (t == 0 && rows > J.leaf_rows))
+    set_error(err, kErrMemoTotal);
+  if (t >= rows || t >= J.leaf_rows) return;
+  uint32_t lo = 0, hi = J.n;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (J.off[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const uint32_t p = lo;
+  const int k = J.k;
+  const uint32_t q = J.dG.div(p);
+  const uint32_t rho = J.dG.mod(p, q);
+  const uint64_t pos = J.endc[rho] - J.cu[p] + (t - J.off[p]);
+  if (pos >= J.leaf_rows) {
+    set_error(err, kErrMemoTotal);
+    return;
+  }
+  const uint32_t* src = J.nat + t * k;
+  if (J.pack == 0) {
+    uint32_t* dst = J.leaf + pos * (k + 1);
+    dst[0] = q;
+    for (int c = 0; c < k; ++c) dst[1 + c] = src[c];
+  } else {
+    uint64_t w = uint64_t(q) << J.fshift[0];
+    for (int c = 0; c < k; ++c) w |= uint64_t(src[c]) << J.fshift[1 + c];
+    if (J.pack == 1) J.leaf[pos] = uint32_t(w);
+    else reinterpret_cast<uint64_t*>(J.leaf)[pos] = w;
+  }
+}
+
+// k = 2 memo lists Z(p; h_1, h_2) in closed form.  With c = gcd(h_1, h_2), p
+// has rows only when c divides p; then m_1 runs over the progression
+// m_1 = m0 (mod h_2 / c), m0 = (p / c) (h_1 / c)^{-1} mod (h_2 / c), from m0
+// to (p / c) / (h_1 / c), and m_2 = (p - m_1 h_1) / h_2.  Every element is
+// independent: counts per element, an exclusive sum (the natural offsets) and
+// a fill give the recurrence's lists (Lemma 2.3) in the same ascending order
+// without its top / min(h) dependent batches.
+struct Memo2 {
+  uint32_t h1, h2, c, h1c, h2c, inv;  // inv = (h1 / c)^{-1} mod (h2 / c)
+};
+Memo2 make_memo2(uint32_t h1, uint32_t h2);  // host
+
+__device__ inline bool memo2_first(const Memo2& M, uint32_t p, uint32_t* m0, uint32_t* rows) {
+  if (p % M.c != 0) return false;
+  const uint32_t q = p / M.c;
+  const uint32_t mmax = q / M.h1c;
+  const uint32_t a = uint32_t((uint64_t(q % M.h2c) * M.inv) % M.h2c);
+  if (a > mmax) return false;
+  *m0 = a;
+  *rows = (mmax - a) / M.h2c + 1;
+  return true;
+}
+
+// The first launch of a call with the memo dimension fixed at 1 or 2 and a
+// count table that fits LDS (count_table.hip): workgroup 0 clears the two
+// status words, computes the count table (row sums, |Z(n)|, row maxima into
+// sums as launch_count_table does) and then the residue-class ends of row U;
+// workgroup 1 builds the memo in natural order (off: top + 1 offsets, nat: R
+// rows; k = 1 or 2 in closed form) and stamps its start and end on the
+// device's constant-rate clock into stamps[0..1].
+struct SetupJob {
+  uint64_t* table;          // (d+1) x N
+  uint64_t* sums;           // 2d + 3 words
+  uint64_t* status;         // 2 words cleared first
+  Gens g;
+  uint32_t N;               // n + 1 (<= count_table_lds_max())
+  int d;
+  uint32_t walk;            // count-table column walk bound
+  int U;
+  uint32_t nclass;          // min(g_U, N)
+  DivMod32 dG;              // division by g_U
+  uint64_t* endc;
+  int k;                    // 1 or 2
+  Memo2 M;                  // k = 2
+  uint32_t h1;              // k = 1: the memo generator
+  uint32_t R;               // memo rows
+  uint32_t* nat;
+  uint64_t* off;
+  uint64_t* stamps;
+};
+
 struct ClassJob {
   const uint64_t* cu;       // count-table row U
   uint64_t* endc;
@@ -167,6 +256,7 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
                               uint64_t* sums, hipStream_t s);
 uint32_t count_table_lds_max();
 hipError_t prepare_count_table_batch(uint32_t max_lds_n);
+hipError_t launch_setup_fixed(const SetupJob& J, hipStream_t s);
 hipError_t launch_count_table_batch(const CountJob* jobs, uint32_t njobs, uint32_t max_lds_n,
                                     bool lds, hipStream_t s);
 
@@ -229,6 +319,9 @@ hipError_t launch_plan(const EnumParams& P, hipStream_t s);
 // The same planner sized on the device (P.total_dev, P.want_tiles): a grid for
 // want_tiles slices, of which the first ceil(|Z| / slice_rows) are planned.
 hipError_t launch_plan_device_sized(const EnumParams& P, hipStream_t s);
+// The device-sized planner and the memo's leaf layout (memo_leaf_row over
+// J.leaf_rows rows) in one grid: the planner's workgroups first.
+hipError_t launch_plan_leaf(const EnumParams& P, const LeafJob& J, hipStream_t s);
 hipError_t launch_write(const EnumParams& P, bool count_only, bool align16, hipStream_t s);
 hipError_t launch_single(uint64_t n, uint32_t g, uint32_t* out, bool count_only,
                          uint64_t* checksum, hipStream_t s);

@@ -290,11 +290,13 @@ def tuned(n: int, gens):
 def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
                  rows_per_tile: int = 0, count_only: bool = False, memo: Memo | None = None,
                  stream=None, out_rows_cap: int | None = None, claim_pct: int = -1,
-                 memo_top: int = 0) -> Result:
+                 memo_top: int = 0, stats: bool = True) -> Result:
     """Z(n; g) through zset_enumerate_ex.  `out` is an int32 CUDA tensor with at least
     |Z(n)| * d elements (allocated here when None and count_only is False).
     `claim_pct`: percent of slices claimed at run time (-1 automatic, 0 none).
-    `memo_top`: 0, or the memo covers p < memo_top only (a partial memo)."""
+    `memo_top`: 0, or the memo covers p < memo_top only (a partial memo).
+    `stats`: False passes no stats structure (the call records no timing
+    events); Result.stats is then empty."""
     import torch
     g = _gens(gens)
     d = len(g)
@@ -316,14 +318,17 @@ def enumerate_ex(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     opts.stream = _stream_handle(stream)
     opts.claim_pct = claim_pct
     opts.memo_top = memo_top
-    rows_written, csum, stats = ctypes.c_uint64(), ctypes.c_uint64(), Stats()
+    rows_written, csum = ctypes.c_uint64(), ctypes.c_uint64()
+    st = Stats() if stats else None
     _check(load().zset_enumerate_ex(n, g.ctypes.data_as(_u32p), d, ptr, cap, ctypes.byref(opts),
                                     memo.handle if memo is not None else None,
                                     ctypes.byref(rows_written), ctypes.byref(csum),
-                                    ctypes.byref(stats)), "zset_enumerate_ex")
+                                    ctypes.byref(st) if st is not None else None),
+           "zset_enumerate_ex")
     r = int(rows_written.value)
     view = out[:r] if (out is not None and out.dim() == 2) else out
-    return Result(rows=r, checksum=int(csum.value), stats=stats.as_dict(), out=view)
+    return Result(rows=r, checksum=int(csum.value), stats=st.as_dict() if st is not None else {},
+                  out=view)
 
 
 def enumerate_noalloc(n: int, gens, out=None, *, k: int = -1, order: int = 0,

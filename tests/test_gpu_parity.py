@@ -425,7 +425,9 @@ def test_fixed_k_path_matches_the_readback_path(monkeypatch):
     checksums and error statuses equal the path that reads |Z(n)| back first
     (ZSET_FIXED_K_READBACK=1), and the oracle's rows."""
     cases = [(2000, [7, 11, 13, 17]), (1000, [13, 37, 38, 40, 41, 42, 43]), (60, [1, 1, 1, 1]),
-             (3, [5, 7, 9]), (700, [10, 12, 14, 16, 19]), (0, [4, 6])]
+             (3, [5, 7, 9]), (700, [10, 12, 14, 16, 19]), (0, [4, 6]),
+             (16383, [40, 50, 61, 77]), (3000, [6, 10, 14, 21]), (50, [3, 100, 5, 7]),
+             (16384, [90, 97, 120, 131])]
     cases += list(bounded_queries(73, 6, dmax=6, gmax=30, nmax=800))
     for n, g in cases:
         want = oracle.enumerate_rows(n, g)
@@ -434,16 +436,24 @@ def test_fixed_k_path_matches_the_readback_path(monkeypatch):
                 continue
             for order in (0, 1):
                 monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
-                got, r = gpu_rows(n, g, k=k, order=order)
+                # No stats structure: the call records no timing events.
+                got, r = gpu_rows(n, g, k=k, order=order, stats=order == 1)
                 ref = want if order == 0 else np.ascontiguousarray(want[::-1])
                 assert_same(got, ref, f"fixed k={k} order={order} n={n} g={g}")
+                # The same call with the setup launches split (count table,
+                # class ends, memo, plan and leaf layout each on its own).
+                monkeypatch.setenv("ZSET_FIXED_K_SPLIT", "1")
+                got3, r3 = gpu_rows(n, g, k=k, order=order)
+                monkeypatch.delenv("ZSET_FIXED_K_SPLIT")
+                assert_same(got3, got, f"split setup k={k} order={order} n={n} g={g}")
                 monkeypatch.setenv("ZSET_FIXED_K_READBACK", "1")
                 got2, r2 = gpu_rows(n, g, k=k, order=order)
                 assert_same(got2, got, f"readback path k={k} order={order} n={n} g={g}")
-                assert r.rows == r2.rows == len(want)
+                assert r.rows == r2.rows == r3.rows == len(want)
             monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
-            c = zset.enumerate_ex(n, g, k=k, count_only=True)
-            assert c.rows == len(want) and c.checksum == oracle.checksum(want), (n, g, k)
+            for st in (True, False):
+                c = zset.enumerate_ex(n, g, k=k, count_only=True, stats=st)
+                assert c.rows == len(want) and c.checksum == oracle.checksum(want), (n, g, k)
     monkeypatch.delenv("ZSET_FIXED_K_READBACK", raising=False)
     g = [7, 11, 13, 17]
     for k in (1, 2):
