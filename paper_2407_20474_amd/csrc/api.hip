@@ -803,6 +803,7 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
     J.nat = nat;
     J.off = off;
     J.stamps = misc + kMiscStamp;
+    if (count_last_rows_enabled()) J.last = make_last_rows(gens, d);
     const bool timed = stats != nullptr;  // no timing events without stats
     if (timed) ZSET_HIP(hipEventRecord(c->ev[0], s));
     ZSET_HIP(launch_setup_fixed(J, s));

@@ -196,20 +196,49 @@ __device__ inline uint64_t wave_incl_scan_sat_u64(uint64_t v, uint32_t seg) {
 __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32_t N,
                                                 const uint32_t* gs, int d,
                                 uint64_t* __restrict__ sums, uint64_t* __restrict__ maxes,
-                                uint64_t* buf, uint32_t walk_max = kColWalk) {
+                                uint64_t* buf, uint32_t walk_max = kColWalk,
+                                const LastRows* lr = nullptr) {
   constexpr int kWaves = kCtThreads / kWave;
   __shared__ uint64_t wsum[kMaxD][kWaves];
   __shared__ uint64_t wmax[kMaxD][kWaves];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
+  const bool closed = lr && lr->on && d >= 2;
   for (uint32_t x = tid; x < N; x += kCtThreads) {
-    buf[x] = (x == 0) ? 1 : 0;
+    if (!closed) buf[x] = (x == 0) ? 1 : 0;
     T[size_t(d) * N + x] = (x == 0) ? 1 : 0;
   }
   if (tid == 0 && sums) sums[d] = 1;
   if (tid == 0 && maxes) maxes[d] = 1;
+  int jtop = d - 1;
+  if (closed) {
+    // Rows d-1 and d-2 from their closed forms (LastRows); the scans start
+    // at row d-3 from row d-2 in buf.
+    uint64_t acc = 0, mx = 0;
+    for (uint32_t x = tid; x < N; x += kCtThreads) {
+      T[size_t(d - 1) * N + x] = last_row_divides(*lr, x);
+      const uint64_t v = last_row_pair(*lr, x);
+      buf[x] = v;
+      T[size_t(d - 2) * N + x] = v;
+      acc += v;
+      mx = v > mx ? v : mx;
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) {
+      acc += __shfl_xor(acc, off, kWave);
+      const uint64_t y = __shfl_xor(mx, off, kWave);
+      mx = y > mx ? y : mx;
+    }
+    if (lane == 0) {
+      wsum[d - 2][wave] = acc;
+      wmax[d - 2][wave] = mx;
+      wsum[d - 1][wave] = wave == 0 ? uint64_t(lr->dg.div(N - 1)) + 1 : 0;
+      wmax[d - 1][wave] = wave == 0 ? 1 : 0;
+    }
+    jtop = d - 3;
+  }
   lds_barrier();
 
-  for (int j = d - 1; j >= 0; --j) {
+  for (int j = jtop; j >= 0; --j) {
     const uint32_t G = gs[j];
     if (G < N) {  // else no x - g_j >= 0: row j equals row j + 1
       const uint32_t L = (N + G - 1) / G;  // entries of the longest column
@@ -310,12 +339,12 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
 __global__ __launch_bounds__(kCtThreads) void k_count_table_lds(uint64_t* __restrict__ T,
                                                                 uint32_t N, Gens gs, int d,
                                                                 uint64_t* __restrict__ sums,
-                                                                uint32_t walk_max) {
+                                                                uint32_t walk_max, LastRows lr) {
   __shared__ uint64_t buf[kCtLdsMax];
   __shared__ uint32_t g[kMaxD];
   if (threadIdx.x < uint32_t(kMaxD)) g[threadIdx.x] = gs.g[threadIdx.x];
   __syncthreads();
-  count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf, walk_max);
+  count_table_lds(T, N, g, d, sums, sums ? sums + d + 2 : nullptr, buf, walk_max, &lr);
   if (threadIdx.x == 0 && sums) sums[d + 1] = buf[N - 1];  // |Z(n)| = C[0][n] (row 0 in LDS)
 }
 
@@ -373,7 +402,7 @@ __global__ __launch_bounds__(kCtThreads) void k_setup_fixed(SetupJob J) {
     }
     if (tid < kMaxD) g[tid] = J.g.g[tid];
     __syncthreads();
-    count_table_lds(J.table, J.N, g, J.d, J.sums, J.sums + J.d + 2, buf, J.walk);
+    count_table_lds(J.table, J.N, g, J.d, J.sums, J.sums + J.d + 2, buf, J.walk, &J.last);
     if (tid == 0) J.sums[J.d + 1] = buf[J.N - 1];
     __syncthreads();  // the table's global rows are visible to the workgroup
     const uint64_t* CU = J.table + uint64_t(J.U) * J.N;
@@ -455,10 +484,18 @@ constexpr uint32_t kShortClass = 64;
 // Row d = [x == 0]; the sums and maxima start clear (the stats launch adds
 // into them).
 __global__ __launch_bounds__(kRowThreads) void k_count_init(uint64_t* __restrict__ T, uint32_t N,
-                                                            int d, uint64_t* __restrict__ sums) {
+                                                            int d, uint64_t* __restrict__ sums,
+                                                            LastRows lr) {
   const uint64_t i = uint64_t(blockIdx.x) * kRowThreads + threadIdx.x;
   uint64_t* last = T + uint64_t(d) * N;
-  for (uint64_t x = i; x < N; x += uint64_t(gridDim.x) * kRowThreads) last[x] = (x == 0) ? 1 : 0;
+  const bool closed = lr.on && d >= 2;
+  for (uint64_t x = i; x < N; x += uint64_t(gridDim.x) * kRowThreads) {
+    last[x] = (x == 0) ? 1 : 0;
+    if (closed) {  // rows d-1 and d-2 in closed form (LastRows)
+      T[uint64_t(d - 1) * N + x] = last_row_divides(lr, uint32_t(x));
+      T[uint64_t(d - 2) * N + x] = last_row_pair(lr, uint32_t(x));
+    }
+  }
   if (sums && i < uint64_t(2 * d + 3)) sums[i] = 0;
 }
 
@@ -612,16 +649,18 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
   // ZSET_COUNT_PATH=rows takes the one-launch-per-row form at any size (tests).
   const char* path = std::getenv("ZSET_COUNT_PATH");
   const bool rows_form = path && std::strcmp(path, "rows") == 0;
+  LastRows lr{};
+  if (count_last_rows_enabled()) lr = make_last_rows(gens, d);
   if (N <= kCtLdsMax && !rows_form) {
     const char* we = std::getenv("ZSET_COUNT_WALK");
     const uint32_t walk = we ? uint32_t(std::atoi(we)) : kColWalk;
     hipLaunchKernelGGL(k_count_table_lds, dim3(1), dim3(kCtThreads), 0, s, table, N, gs, d, sums,
-                       walk);
+                       walk, lr);
   } else {
     const uint32_t ib = uint32_t(std::min<uint64_t>((uint64_t(N) + kRowThreads - 1) / kRowThreads,
                                                     4096));
-    hipLaunchKernelGGL(k_count_init, dim3(ib), dim3(kRowThreads), 0, s, table, N, d, sums);
-    for (int j = d - 1; j >= 0; --j) {
+    hipLaunchKernelGGL(k_count_init, dim3(ib), dim3(kRowThreads), 0, s, table, N, d, sums, lr);
+    for (int j = lr.on ? d - 3 : d - 1; j >= 0; --j) {
       const uint32_t G = gs.g[j];
       const uint64_t classes = std::min<uint64_t>(G, N);
       const uint64_t len = (uint64_t(N) + G - 1) / G;
@@ -643,6 +682,26 @@ hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens,
 }
 
 uint32_t count_table_lds_max() { return kCtLdsMax; }
+
+bool count_last_rows_enabled() {
+  const char* e = std::getenv("ZSET_COUNT_LAST");
+  return !(e && std::strcmp(e, "0") == 0);
+}
+
+LastRows make_last_rows(const uint32_t* gens, int d) {
+  LastRows L;
+  std::memset(&L, 0, sizeof L);
+  if (d < 2) return L;
+  const Memo2 M = make_memo2(gens[d - 2], gens[d - 1]);
+  if (M.h2c >= (1u << 16)) return L;
+  L.on = 1;
+  L.inv = M.inv;
+  L.dg = DivMod32::make(gens[d - 1]);
+  L.dc = DivMod32::make(M.c);
+  L.dh1c = DivMod32::make(M.h1c);
+  L.dh2c = DivMod32::make(M.h2c);
+  return L;
+}
 
 hipError_t launch_setup_fixed(const SetupJob& J, hipStream_t s) {
   if (J.N == 0 || J.N > kCtLdsMax || (J.k != 1 && J.k != 2) || J.d < 2 || J.U < 0 ||

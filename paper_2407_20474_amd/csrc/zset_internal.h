@@ -199,6 +199,34 @@ __device__ inline bool memo2_first(const Memo2& M, uint32_t p, uint32_t* m0, uin
   return true;
 }
 
+// The last two rows of a count table in closed form (d >= 2): C[d-1][x] =
+// [g_{d-1} divides x], and C[d-2][x] = |Z(x; g_{d-2}, g_{d-1})|, the number of
+// rows of Memo2 for (h_1, h_2) = (g_{d-2}, g_{d-1}) at p = x, with every
+// division by an invariant divisor.  `on` is 0 when the table must be scanned
+// from row d instead (d = 1, or h_2 / gcd >= 2^16, where the product below
+// could leave 32 bits).
+struct LastRows {
+  int on;
+  uint32_t inv;             // (h_1 / c)^{-1} mod (h_2 / c), c = gcd(h_1, h_2)
+  DivMod32 dg;              // g_{d-1}
+  DivMod32 dc, dh1c, dh2c;  // c, h_1 / c, h_2 / c
+};
+LastRows make_last_rows(const uint32_t* gens, int d);  // host
+
+__device__ inline uint32_t last_row_divides(const LastRows& L, uint32_t x) {
+  return x == L.dg.div(x) * L.dg.d ? 1u : 0u;
+}
+
+__device__ inline uint32_t last_row_pair(const LastRows& L, uint32_t x) {
+  const uint32_t q = L.dc.div(x);
+  if (x != q * L.dc.d) return 0;
+  const uint32_t mmax = L.dh1c.div(q);
+  const uint32_t qm = q - L.dh2c.div(q) * L.dh2c.d;
+  const uint32_t prod = qm * L.inv;  // < (h_2 / c)^2 < 2^32
+  const uint32_t a = prod - L.dh2c.div(prod) * L.dh2c.d;
+  return a > mmax ? 0u : L.dh2c.div(mmax - a) + 1u;
+}
+
 // The first launch of a call with the memo dimension fixed at 1 or 2 and a
 // count table that fits LDS (count_table.hip): workgroup 0 clears the two
 // status words, computes the count table (row sums, |Z(n)|, row maxima into
@@ -225,6 +253,7 @@ struct SetupJob {
   uint32_t* nat;
   uint64_t* off;
   uint64_t* stamps;
+  LastRows last;            // the table's rows d-1 and d-2 in closed form (when on)
 };
 
 struct ClassJob {
@@ -254,6 +283,9 @@ struct BatchLds {
 // sums[d+2+j] = max_x C[j][x] (all saturating).
 hipError_t launch_count_table(uint64_t* table, uint64_t n, const uint32_t* gens, int d,
                               uint64_t* sums, hipStream_t s);
+// ZSET_COUNT_LAST=0 scans every row from row d (tests); else rows d-1 and d-2
+// come from their closed forms when make_last_rows allows.
+bool count_last_rows_enabled();
 uint32_t count_table_lds_max();
 hipError_t prepare_count_table_batch(uint32_t max_lds_n);
 hipError_t launch_setup_fixed(const SetupJob& J, hipStream_t s);

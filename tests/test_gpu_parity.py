@@ -57,9 +57,13 @@ def assert_same(got, want, what):
 # Counting pass
 # --------------------------------------------------------------------------
 
-def test_count_table_matches_oracle():
+def test_count_table_matches_oracle(monkeypatch):
     rng = np.random.default_rng(11)
     cases = [(2000, [7, 11, 13, 17]), (10130, [13, 34, 37, 54, 65, 83]), (0, [5]),
+             # the last two rows in closed form: gcd > 1, g > n, beyond LDS, and
+             # h_2 / gcd >= 2^16 (scanned from row d instead)
+             (9000, [6, 4]), (5, [7, 9]), (100000, [11, 2, 70000]), (200000, [3, 70001]),
+             (16383, [1, 65537, 65536]),
              (3000, [1, 1, 2]), (500, [600, 7, 3]), (16383, [5, 9, 4]), (16384, [5, 9, 4]),
              (20000, [3, 5, 7]), (77847, [14, 99, 135, 161, 163]),
              # residue classes walked by one thread (<= 32 entries), one run per
@@ -79,6 +83,12 @@ def test_count_table_matches_oracle():
             assert e.value.status == zset.EOVERFLOW
         else:
             assert zset.count(n, g) == int(want[0, n])
+    # Every row scanned from row d (no closed-form rows), LDS and row forms.
+    monkeypatch.setenv("ZSET_COUNT_LAST", "0")
+    for n, g in cases[:12]:
+        say(f"count_table scanned n={n} g={g}")
+        t = zset.count_table(n, g).cpu().numpy().view(np.uint64)
+        assert np.array_equal(t, oracle.count_table(n, g)), (n, g)
 
 
 def test_count_overflow_is_reported():
