@@ -527,7 +527,11 @@ zset_status zset_server_add_set(zset_server S, const uint32_t* gens, int d, uint
       if (Rc == ~uint64_t(0) || Rc >= (uint64_t(1) << 32)) continue;
       EnumParams P;
       tmpl_for(c, P);
-      const uint64_t words = P.pack ? Rc * uint64_t(P.pack) : Rc * uint64_t(c + 1);
+      // The memo as the write pass will hold it: packed when the packed memo
+      // fits the write pass's LDS, else k + 1 plain words per row.
+      const bool packed =
+          P.pack != 0 && write_lds_bytes(P) <= lds_max;
+      const uint64_t words = packed ? Rc * uint64_t(P.pack) : Rc * uint64_t(c + 1);
       if (words * 4 <= S->memo_bytes) {
         kk = c;
         break;

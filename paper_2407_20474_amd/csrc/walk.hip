@@ -226,16 +226,20 @@ __device__ inline void wave_sync_walk() {
 // words: a store instruction covers two contiguous runs instead of 64
 // scattered words.
 constexpr uint32_t kWalkLaneWords = 32;  // LDS words staged per lane per round
+// Each lane's staging area starts kWalkLaneWords + 1 words after the previous
+// lane's: with an odd stride the lanes' stores of one staged word fall in
+// different LDS banks (a stride of 32 words puts every lane in one bank).
+constexpr uint32_t kWalkLaneStride = kWalkLaneWords + 1;
 __global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
   __shared__ WalkLds W;
-  __shared__ uint32_t stage[kWalkThreads * kWalkLaneWords];
+  __shared__ uint32_t stage[kWalkThreads * kWalkLaneStride];
   extern __shared__ uint32_t cols[];  // a[] then r[]: (d - 2) columns each
   walk_lds_init(A, W);
   const uint32_t levels = uint32_t(A.d > 2 ? A.d - 2 : 1);
   const int lane = int(threadIdx.x & 63);
   const int wave = int(threadIdx.x >> 6);
-  uint32_t* buf = stage + uint32_t(threadIdx.x) * kWalkLaneWords;
-  const uint32_t* wstage = stage + uint32_t(wave) * 64 * kWalkLaneWords;
+  uint32_t* buf = stage + uint32_t(threadIdx.x) * kWalkLaneStride;
+  const uint32_t* wstage = stage + uint32_t(wave) * 64 * kWalkLaneStride;
   const int d = A.d;
   const uint32_t g2 = W.g[d - 2];
   const DivMod32 dlast = W.dg[d - 1];
@@ -292,7 +296,7 @@ __global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
                                   : __builtin_amdgcn_readlane(gw_hi, s2);
         if (t < w) {
           const uint32_t src = uint32_t(s2) + (upper ? 1u : 0u);
-          const uint32_t v = wstage[src * kWalkLaneWords + t];
+          const uint32_t v = wstage[src * kWalkLaneStride + t];
           __builtin_nontemporal_store(v, A.out + ((uint64_t(hi) << 32) | lo) + t);
         }
       }
