@@ -47,7 +47,13 @@ namespace zset {
 namespace {
 
 constexpr int kWalkThreads = 256;
-constexpr uint64_t kWantPrefixes = 1 << 17;   // lanes the work is spread over
+// Lanes the work is spread over: one per kWorkPerRecord units of estimated
+// work (walk_estimate), between kMinPrefixes and kWantPrefixes.  Small walks
+// then take few records (the host's splitting is most of their time), large
+// ones enough wavefronts to hide the walk's dependent LDS and division chains.
+constexpr uint64_t kWantPrefixes = 1 << 18;
+constexpr uint64_t kMinPrefixes = 1 << 12;
+constexpr double kWorkPerRecord = 256.0;
 constexpr uint64_t kMaxPrefixes = 1 << 22;    // host refinement bound
 constexpr int kSplitThreads = 8;              // host threads that refine records
 
@@ -390,7 +396,7 @@ void split_below(Prefix seed, const uint32_t* g, int d, uint32_t step, double sh
 }
 
 // Prefix records in lexicographic order: from the whole range, every record
-// whose estimate exceeds twice the share of one of kWantPrefixes lanes (and
+// whose estimate exceeds twice the share of one of the lanes above (and
 // one unit) is split -- a range of a_{m+1} in two halves of about equal work,
 // a single value into the next coordinate's range -- until the list holds
 // kMaxPrefixes.  This is the static counterpart of re-splitting the heaviest
@@ -401,8 +407,10 @@ void split_below(Prefix seed, const uint32_t* g, int d, uint32_t step, double sh
 // concatenated in seed order.
 std::vector<Prefix> make_prefixes(uint64_t n, const uint32_t* g, int d, uint32_t step) {
   Prefix root = full_prefix(0, n, nullptr, g, d);
-  const double share =
-      std::max(1.0, 2.0 * walk_estimate(root, g, d, step) / double(kWantPrefixes));
+  const double work = walk_estimate(root, g, d, step);
+  const double want = std::min(double(kWantPrefixes),
+                               std::max(double(kMinPrefixes), work / kWorkPerRecord));
+  const double share = std::max(1.0, 2.0 * work / want);
   std::vector<Prefix> seeds{std::move(root)};
   while (seeds.size() < size_t(kSplitThreads)) {
     size_t heavy = 0;
