@@ -55,7 +55,7 @@ constexpr uint64_t kWantPrefixes = 1 << 18;
 constexpr uint64_t kMinPrefixes = 1 << 12;
 constexpr double kWorkPerRecord = 256.0;
 constexpr uint64_t kMaxPrefixes = 1 << 22;    // host refinement bound
-constexpr int kSplitThreads = 8;              // host threads that refine records
+constexpr int kSplitThreads = 16;             // host threads that refine records, at most
 
 struct WalkArgs {
   Gens g;
@@ -360,10 +360,14 @@ void split_record(Prefix p, const uint32_t* g, int d, std::vector<Prefix>* stack
   if (p.hi > p.lo) {
     uint64_t mid = p.lo + (p.hi - p.lo) / 2;
     if (p.m < d - 2) {
-      const double k = double(d - 2 - p.m);
+      const int k = d - 2 - p.m;
       const double y0 = double(p.x) - double(p.lo) * g[p.m];
       const double y1 = std::max(0.0, double(p.x) - double(p.hi + 1) * g[p.m]);
-      const double ym = std::pow(0.5 * (std::pow(y0, k) + std::pow(y1, k)), 1.0 / k);
+      // The cut where the volumes (powers k of the remainders) halve: y0 times
+      // the k-th root of (1 + (y1 / y0)^k) / 2.
+      double q = 1.0, rk = y0 > 0 ? y1 / y0 : 0.0;
+      for (int t = 0; t < k; ++t) q *= rk;
+      const double ym = k == 1 ? 0.5 * (y0 + y1) : y0 * std::pow(0.5 * (1.0 + q), 1.0 / k);
       const double cut = (double(p.x) - ym) / double(g[p.m]);
       if (cut >= double(p.lo) && cut < double(p.hi)) mid = uint64_t(cut);
     }
@@ -378,17 +382,33 @@ void split_record(Prefix p, const uint32_t* g, int d, std::vector<Prefix>* stack
   }
 }
 
-// The records below one seed, depth first, in order, at most `cap` of them.
+// A record as the kernels read it: d + 3 words, m, the remainder, lo, hi,
+// then a_1..a_m (zero-padded).
+void pack_record(const Prefix& p, int d, std::vector<uint32_t>* out) {
+  const size_t at = out->size();
+  out->resize(at + size_t(d + 3), 0u);
+  uint32_t* r = out->data() + at;
+  r[0] = uint32_t(p.m);
+  r[1] = uint32_t(p.x);
+  r[2] = uint32_t(p.lo);
+  r[3] = uint32_t(p.hi);
+  for (int j = 0; j < p.m; ++j) r[4 + j] = p.a[j];
+}
+
+// The records below one seed, depth first, in order, at most `cap` of them,
+// packed into `out`.
 void split_below(Prefix seed, const uint32_t* g, int d, uint32_t step, double share,
-                 uint64_t cap, std::vector<Prefix>* out) {
+                 uint64_t cap, std::vector<uint32_t>* out) {
   std::vector<Prefix> stack;
   stack.push_back(std::move(seed));
+  uint64_t count = 0;
   while (!stack.empty()) {
     Prefix p = std::move(stack.back());
     stack.pop_back();
-    if (p.m >= d - 1 || out->size() + stack.size() + 2 > cap ||
+    if (p.m >= d - 1 || count + stack.size() + 2 > cap ||
         walk_estimate(p, g, d, step) <= share) {
-      out->push_back(std::move(p));
+      pack_record(p, d, out);
+      ++count;
       continue;
     }
     split_record(std::move(p), g, d, &stack);
@@ -402,17 +422,21 @@ void split_below(Prefix seed, const uint32_t* g, int d, uint32_t step, double sh
 // kMaxPrefixes.  This is the static counterpart of re-splitting the heaviest
 // remaining lexicographic range.  Depth first with an explicit stack, so the
 // records come out in order in one pass per seed.
-// The first splits, heaviest record first, make up to kSplitThreads seeds in
-// order; each is refined below by its own host thread and the lists are
-// concatenated in seed order.
-std::vector<Prefix> make_prefixes(uint64_t n, const uint32_t* g, int d, uint32_t step) {
+// The first splits, heaviest record first, make up to kSplitThreads seeds (no
+// more than the host's hardware threads) in
+// order; each is refined below by its own host thread into its own list of
+// packed records (the lists, in seed order, are the records in order).
+std::vector<std::vector<uint32_t>> make_prefixes(uint64_t n, const uint32_t* g, int d,
+                                                 uint32_t step) {
   Prefix root = full_prefix(0, n, nullptr, g, d);
   const double work = walk_estimate(root, g, d, step);
   const double want = std::min(double(kWantPrefixes),
                                std::max(double(kMinPrefixes), work / kWorkPerRecord));
   const double share = std::max(1.0, 2.0 * work / want);
   std::vector<Prefix> seeds{std::move(root)};
-  while (seeds.size() < size_t(kSplitThreads)) {
+  const unsigned hw = std::thread::hardware_concurrency();
+  const size_t nseeds = size_t(std::max(1, std::min(kSplitThreads, hw ? int(hw) : 1)));
+  while (seeds.size() < nseeds) {
     size_t heavy = 0;
     double most = -1;
     for (size_t i = 0; i < seeds.size(); ++i) {
@@ -429,19 +453,13 @@ std::vector<Prefix> make_prefixes(uint64_t n, const uint32_t* g, int d, uint32_t
     seeds.erase(seeds.begin() + long(heavy));
     seeds.insert(seeds.begin() + long(heavy), parts.begin(), parts.end());
   }
-  std::vector<std::vector<Prefix>> lists(seeds.size());
+  std::vector<std::vector<uint32_t>> lists(seeds.size());
   const uint64_t cap = kMaxPrefixes / seeds.size();
   std::vector<std::thread> pool;
   for (size_t i = 0; i < seeds.size(); ++i)
     pool.emplace_back(split_below, seeds[i], g, d, step, share, cap, &lists[i]);
   for (auto& t : pool) t.join();
-  std::vector<Prefix> out;
-  size_t total = 0;
-  for (const auto& l : lists) total += l.size();
-  out.reserve(total);
-  for (auto& l : lists) out.insert(out.end(), std::make_move_iterator(l.begin()),
-                                   std::make_move_iterator(l.end()));
-  return out;
+  return lists;
 }
 
 uint32_t gcd32(uint32_t a, uint32_t b) {
@@ -474,6 +492,8 @@ uint32_t inverse_mod(uint32_t x, uint32_t m) {
 struct WalkCtx {
   DevBuf pre, cnt, off;
   uint64_t* pinned = nullptr;
+  uint32_t* hpre = nullptr;  // pinned host staging of the records, hpre_words long
+  size_t hpre_words = 0;
 };
 WalkCtx g_walk[64];
 
@@ -519,25 +539,41 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
   }
 
   const uint32_t h = gcd32(gens[d - 2], gens[d - 1]);
-  std::vector<Prefix> list = make_prefixes(n, gens, d, gens[d - 1] / h);
-  if (order == 1) std::reverse(list.begin(), list.end());  // descending: reverse order
+  const std::vector<std::vector<uint32_t>> lists = make_prefixes(n, gens, d, gens[d - 1] / h);
   const uint64_t W = uint64_t(d + 3);
-  const uint64_t np = list.size();
-  std::vector<uint32_t> pre(np * W, 0);
-  for (uint64_t i = 0; i < np; ++i) {
-    const Prefix& p = list[i];
-    uint32_t* r = &pre[i * W];
-    r[0] = uint32_t(p.m);
-    r[1] = uint32_t(p.x);
-    r[2] = uint32_t(p.lo);
-    r[3] = uint32_t(p.hi);
-    for (int j = 0; j < p.m; ++j) r[4 + j] = p.a[j];
+  size_t words = 0;
+  for (const auto& l : lists) words += l.size();
+  const uint64_t np = words / W;
+  // The records in pinned host memory (grown on demand, kept for later
+  // calls), in order, or in reverse order for the descending walk.
+  if (words > c.hpre_words) {
+    if (c.hpre) (void)hipHostFree(c.hpre);
+    c.hpre = nullptr;
+    c.hpre_words = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&c.hpre), words * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      c.hpre = nullptr;
+      return fail(ZSET_ENOMEM, "pinned staging of the walk's records");
+    }
+    c.hpre_words = words;
   }
-  if ((st = ensure(c.pre, pre.size() * sizeof(uint32_t))) != ZSET_OK) return st;
+  if (order == 0) {
+    size_t at = 0;
+    for (const auto& l : lists) {
+      std::memcpy(c.hpre + at, l.data(), l.size() * sizeof(uint32_t));
+      at += l.size();
+    }
+  } else {  // descending: the records in reverse order
+    size_t at = 0;
+    for (auto l = lists.rbegin(); l != lists.rend(); ++l)
+      for (size_t r = l->size(); r >= W; r -= W, at += W)
+        std::memcpy(c.hpre + at, l->data() + (r - W), W * sizeof(uint32_t));
+  }
+  if ((st = ensure(c.pre, words * sizeof(uint32_t))) != ZSET_OK) return st;
   if ((st = ensure(c.cnt, (np + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
   if ((st = ensure(c.off, (np + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
-  ZSET_HIP(hipMemcpyAsync(c.pre.p, pre.data(), pre.size() * sizeof(uint32_t),
-                          hipMemcpyHostToDevice, s));
+  ZSET_HIP(hipMemcpyAsync(c.pre.p, c.hpre, words * sizeof(uint32_t), hipMemcpyHostToDevice, s));
 
   WalkArgs A;
   std::memset(&A, 0, sizeof A);
