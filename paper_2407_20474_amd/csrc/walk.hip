@@ -236,6 +236,9 @@ constexpr uint32_t kWalkLaneWords = 32;  // LDS words staged per lane per round
 // lane's: with an odd stride the lanes' stores of one staged word fall in
 // different LDS banks (a stride of 32 words puts every lane in one bank).
 constexpr uint32_t kWalkLaneStride = kWalkLaneWords + 1;
+// The flush covers a lane's staged words with 32 lanes, and a row of up to
+// kMaxD words must fit.
+static_assert(kWalkLaneWords <= 32 && kWalkLaneWords >= uint32_t(kMaxD), "walk staging size");
 __global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
   __shared__ WalkLds W;
   __shared__ uint32_t stage[kWalkThreads * kWalkLaneStride];
