@@ -12,15 +12,17 @@
 //           replaced by its children (the prefixes one coordinate longer), in
 //           order, until the work is spread over enough prefixes (the static
 //           counterpart of re-splitting the heaviest remaining range);
-//   pass 1: one thread per prefix walks the rest and counts the rows (a
-//           progression of the last two coordinates at a time);
+//   pass 1: one wavefront per prefix walks the rest and counts the rows: an
+//           odometer over the coordinates above the last three, 64 values
+//           of coordinate d-3 at a time across the lanes, each with the
+//           progression of the last two coordinates below it (closed form);
 //   scan:   exclusive sum of the counts = each prefix's first output row;
-//   pass 2: the same walk again, 64 consecutive prefixes per wavefront (their
-//           rows are one contiguous range): each lane stages a few rows of its
-//           own in LDS, and the wavefront writes the staged words with
-//           consecutive lanes on consecutive words of the output.
+//   pass 2: the same walk again, the rows placed by a wave prefix sum of the
+//           progressions' lengths, staged in LDS and written 64 rows at a time
+//           with consecutive lanes on consecutive words of the output.
 //
-// The walk below a prefix takes coordinates m..d-3 one value at a time.  For
+// The walk below a prefix takes the coordinates above the last three as an
+// odometer and coordinate d-3 in 64-value steps.  For
 // the last free coordinate a_{d-1} only values that leave a remainder divisible
 // by g_d can complete a row: with h = gcd(g_{d-1}, g_d) they are the
 // progression a = a0 (mod g_d / h), a0 = (R / h) (g_{d-1} / h)^{-1} mod (g_d / h),
@@ -51,9 +53,9 @@ constexpr int kWalkThreads = 256;
 // work (walk_estimate), between kMinPrefixes and kWantPrefixes.  Small walks
 // then take few records (the host's splitting is most of their time), large
 // ones enough wavefronts to hide the walk's dependent LDS and division chains.
-constexpr uint64_t kWantPrefixes = 1 << 18;
-constexpr uint64_t kMinPrefixes = 1 << 12;
-constexpr double kWorkPerRecord = 256.0;
+constexpr uint64_t kWantPrefixes = 1 << 16;
+constexpr uint64_t kMinPrefixes = 1 << 10;
+constexpr double kWorkPerRecord = 1024.0;
 constexpr uint64_t kMaxPrefixes = 1 << 22;    // host refinement bound
 constexpr int kSplitThreads = 16;             // host threads that refine records, at most
 
@@ -69,46 +71,68 @@ struct WalkArgs {
   uint32_t* out;             // rows, d uint32 each
   DivMod32 dg[kMaxD];        // division by g_j
   DivMod32 dh, dstep;        // division by h and by step
-  uint32_t stage_rows;       // pass 2: rows each lane stages in LDS per round
+  DivMod32 dd;               // division by d (descending flush)
 };
 
-// The walk below one prefix record (a_1..a_m fixed, a_{m+1} in [lo, hi],
-// later coordinates free) as a resumable generator: a[0..m) the record's
-// coordinates, a[m..d-3] and r[m..d-3] the current node's coordinates and
-// remainders, and the progression of the last two coordinates below it (pn
-// rows left, pv the next value of a_{d-1}, pR the remainder the two share).
-// next_prog moves to the next node in the walk's order; rows are taken from
-// the progression one at a time.  a[] and r[] live in LDS, one column per
-// thread (entry j at j * kWalkThreads), as do the generators and their
-// divisions: indexed per lane, registers would spill to scratch and kernel
-// arguments would be read from memory, and either load would wait for the
-// wavefront's earlier stores.
-struct WalkState {
-  int m, j;
-  bool done;
-  uint32_t lo, hi;
-  uint32_t* a;  // this thread's columns
-  uint32_t* r;
-  uint32_t pR, pv, pn;
-};
-#define WA(j) S.a[(j) * kWalkThreads]
-#define WR(j) S.r[(j) * kWalkThreads]
+// The walk below one record, by one wavefront.  A record fixes coordinates
+// 0..m-1 (0-based), lets coordinate m run over [lo, hi] with remainder x
+// before it, and leaves the later ones free.  With l = d - 3, the last
+// coordinate above the progression of coordinates d-2 and d-1:
+//   - coordinates m..l-1 ("outer") step as an odometer, lane j holding a_j and
+//     the remainder after it (lanes below m hold the record's coordinates);
+//   - the 64 lanes take 64 consecutive values v of coordinate l at a time;
+//     lane v's remainder R = y - v g_l (y: the remainder before l) completes
+//     pn(R) rows, the progression of coordinate d-2 below R (closed form);
+//   - a wave prefix sum of the pn places the rows.  They are produced 64 at a
+//     time, each lane finding the lane whose first row is the last one at or
+//     before its own (LDS marks and a wave prefix max), staged in the
+//     wavefront's LDS ring and written out 64 rows at a time, consecutive
+//     lanes on consecutive words.
+// m = d-2 is one progression (coordinate d-2 in [lo, hi]); m = d-1 at most one
+// row.  Rows come out in ascending order within the record; in descending
+// output, the record's row of ascending rank t goes to its last place - t.
+constexpr int kWalkWaves = kWalkThreads / 64;  // wavefronts per workgroup
+constexpr uint32_t kWalkRing = 128;            // rows in a wavefront's LDS ring
+constexpr uint32_t kWalkFlush = 64;            // rows per flush
 
-struct WalkLds {
-  uint32_t g[kMaxD];
-  DivMod32 dg[kMaxD];
-};
+__device__ inline void wave_sync_walk() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-// Rows of the last two coordinates for remainder R with a_{d-1} in
-// [vlo, vhi]: a_{d-1} runs over the progression a0 (mod step), a0 =
-// (R / h) (g_{d-1} / h)^{-1} mod step, when h divides R, up to R / g_{d-1}.
-__device__ inline void prog_setup(const WalkArgs& A, const WalkLds& W, WalkState& S, uint32_t R,
-                                  uint32_t vlo, uint32_t vhi) {
-  const int d = A.d;
-  S.pn = 0;
-  S.pR = R;
+__device__ inline uint64_t readlane_u64(uint64_t v, int l) {
+  return (uint64_t(__builtin_amdgcn_readlane(uint32_t(v >> 32), l)) << 32) |
+         __builtin_amdgcn_readlane(uint32_t(v), l);
+}
+
+__device__ inline uint64_t wave_incl_sum_u64(uint64_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint64_t y = __shfl_up(v, off, 64);
+    if (lane >= off) v += y;
+  }
+  return v;
+}
+
+__device__ inline uint32_t wave_incl_max_u32(uint32_t v, int lane) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(v, off, 64);
+    if (lane >= off && y > v) v = y;
+  }
+  return v;
+}
+
+// Rows of the last two coordinates for remainder R with coordinate d-2 in
+// [vlo, vhi]: its values run over the progression a0 (mod step), a0 =
+// (R / h) (g_{d-2} / h)^{-1} mod step, when h divides R, up to R / g_{d-2}.
+// Returns their number; *v0 = the first.
+__device__ inline uint32_t prog_count(const WalkArgs& A, const DivMod32& dg2, uint32_t R,
+                                      uint32_t vlo, uint32_t vhi, uint32_t* v0) {
+  *v0 = 0;
   const uint32_t qh = A.dh.div(R);
-  if (A.dh.mod(R, qh) != 0) return;
+  if (A.dh.mod(R, qh) != 0) return 0;
   const uint32_t rh = A.dstep.mod(qh, A.dstep.div(qh));
   uint32_t a0;
   if (A.step <= 65536u) {
@@ -117,201 +141,203 @@ __device__ inline void prog_setup(const WalkArgs& A, const WalkLds& W, WalkState
   } else {
     a0 = uint32_t((uint64_t(rh) * A.inv) % A.step);
   }
-  const uint32_t qmax = W.dg[d - 2].div(R);  // (an explicit compare: min() of two uint32_t
-  const uint32_t amax = qmax < vhi ? qmax : vhi;  // can resolve to the int overload)
-  uint64_t v0 = a0;
-  if (vlo > a0) v0 = a0 + (uint64_t(vlo) - a0 + A.step - 1) / A.step * A.step;
-  if (v0 > amax) return;
-  S.pn = A.dstep.div(amax - uint32_t(v0)) + 1;
-  S.pv = A.desc ? uint32_t(v0) + (S.pn - 1) * A.step : uint32_t(v0);
+  const uint32_t qmax = dg2.div(R);
+  const uint32_t amax = qmax < vhi ? qmax : vhi;
+  uint64_t first = a0;
+  if (vlo > a0) first = a0 + (uint64_t(vlo) - a0 + A.step - 1) / A.step * A.step;
+  if (first > amax) return 0;
+  *v0 = uint32_t(first);
+  return A.dstep.div(amax - uint32_t(first)) + 1;
 }
 
-// Descend from level j to level d - 3, each coordinate at its first value
-// (the last, in descending order), and set up that node's progression.
-__device__ inline void descend(const WalkArgs& A, const WalkLds& W, WalkState& S) {
-  const int d = A.d;
-  int j = S.j;
-  while (j < d - 3) {
-    WR(j + 1) = WR(j) - WA(j) * W.g[j];
-    ++j;
-    WA(j) = A.desc ? W.dg[j].div(WR(j)) : 0;
-  }
-  S.j = j;
-  prog_setup(A, W, S, WR(j) - WA(j) * W.g[j], 0, 0xffffffffu);
-}
-
-__device__ inline void walk_init(const WalkArgs& A, const WalkLds& W, WalkState& S,
-                                 const uint32_t* p) {
-  const int d = A.d;
-  S.m = int(p[0]);
-  S.lo = p[2];
-  S.hi = p[3];
-  S.done = false;
-  S.pn = 0;
-  for (int j = 0; j < S.m && j < d - 2; ++j) WA(j) = p[4 + j];
-  if (S.m == d - 1) {  // a_1..a_{d-1} fixed: the last coordinate is forced
-    S.done = true;     // a progression of one row (a_{d-1} = p[4 + d - 2]) or none
-    const uint32_t x = p[1];
-    const uint32_t q = W.dg[d - 1].div(x);
-    if (W.dg[d - 1].mod(x, q) == 0) {
-      S.pn = 1;
-      S.pv = p[4 + d - 2];
-      S.pR = x + S.pv * W.g[d - 2];  // so that (pR - pv g_{d-1}) / g_d = x / g_d
+// Rows [first, first + nrows) of a record from the ring (first a multiple of
+// kWalkFlush, so the rows are contiguous there) to the output: in place, or
+// reversed for descending order (the record's rows are base .. base + cnt - 1).
+__device__ inline void walk_flush(const WalkArgs& A, const uint32_t* ring, uint64_t base,
+                                  uint64_t cnt, uint64_t first, uint32_t nrows, int lane) {
+  if (first + nrows > cnt) return;  // never: the count pass walked the same rows
+  const uint32_t d = uint32_t(A.d);
+  const uint32_t nw = nrows * d;
+  const uint32_t* src = ring + (uint32_t(first) & (kWalkRing - 1)) * d;
+  if (!A.desc) {
+    uint32_t* dst = A.out + (base + first) * d;
+    for (uint32_t w = uint32_t(lane); w < nw; w += 64) __builtin_nontemporal_store(src[w], dst + w);
+  } else {
+    uint32_t* dst = A.out + (base + cnt - first - nrows) * d;
+    for (uint32_t w = uint32_t(lane); w < nw; w += 64) {
+      const uint32_t r = A.dd.div(w), c = w - r * d;
+      __builtin_nontemporal_store(src[(nrows - 1 - r) * d + c], dst + w);
     }
-    return;
   }
-  if (S.m == d - 2) {  // one progression over a_{d-1} in [lo, hi]
-    S.done = true;
-    prog_setup(A, W, S, p[1], S.lo, S.hi);
-    return;
-  }
-  S.j = S.m;
-  WR(S.m) = p[1];
-  WA(S.m) = A.desc ? S.hi : S.lo;
-  descend(A, W, S);
 }
 
-// The next node at level d - 3 in the walk's order (its progression set
-// up), or done: the deepest level below m whose coordinate can still move,
-// else level m within [lo, hi].
-__device__ inline void next_prog(const WalkArgs& A, const WalkLds& W, WalkState& S) {
-  int j = S.j;
-  while (j > S.m) {
-    const uint32_t last = A.desc ? 0u : W.dg[j].div(WR(j));
-    if (WA(j) != last) break;
-    --j;
-  }
-  if (j == S.m && WA(j) == (A.desc ? S.lo : S.hi)) {
-    S.done = true;
-    return;
-  }
-  WA(j) = A.desc ? WA(j) - 1 : WA(j) + 1;
-  S.j = j;
-  descend(A, W, S);
-}
+// The rows of one record (kind 0: values of coordinate l per lane; 1: one
+// progression; 2: a single row), counted, or staged and written (WRITE).
+struct RecordOut {
+  uint32_t* ring;
+  uint32_t* marks;
+  uint64_t base, cnt, produced, flushed;
+};
 
-__device__ inline void walk_lds_init(const WalkArgs& A, WalkLds& W) {
-  if (threadIdx.x < uint32_t(kMaxD)) {
-    W.g[threadIdx.x] = A.g.g[threadIdx.x];
-    W.dg[threadIdx.x] = A.dg[threadIdx.x];
-  }
-  __syncthreads();
-}
-
-// Pass 1: one thread per record counts its rows (a progression at a time).
-__global__ __launch_bounds__(kWalkThreads) void k_walk_count(WalkArgs A) {
-  __shared__ WalkLds W;
-  extern __shared__ uint32_t cols[];  // a[] then r[]: (d - 2) columns each
-  walk_lds_init(A, W);
-  const uint32_t levels = uint32_t(A.d > 2 ? A.d - 2 : 1);
-  for (uint64_t i = uint64_t(blockIdx.x) * kWalkThreads + threadIdx.x; i < A.nprefix;
-       i += uint64_t(gridDim.x) * kWalkThreads) {
-    WalkState S;
-    S.a = cols + threadIdx.x;
-    S.r = cols + levels * kWalkThreads + threadIdx.x;
-    walk_init(A, W, S, A.pre + i * uint64_t(A.d + 3));
-    uint64_t rows = S.pn;
-    while (!S.done) {
-      next_prog(A, W, S);
-      if (!S.done) rows += S.pn;
+// One chunk: lane i has pn rows (0 if idle); they follow in lane order.
+// Counting, it returns pn (the record sums its lanes once at its end).
+// Writing, every row is staged (its words from the owning lane's v, v0 and
+// R, and the prefix in lanes 0..npre-1 of aj) and full blocks are written out.
+template <bool WRITE>
+__device__ inline uint64_t walk_chunk(const WalkArgs& A, RecordOut& O, int lane, uint32_t pn,
+                                      uint32_t aj, int npre, int kind, uint32_t v, uint32_t v0,
+                                      uint32_t R, const DivMod32& dg2, const DivMod32& dlast) {
+  if (!WRITE) return pn;
+  if (__ballot(pn != 0) == 0) return 0;
+  const uint64_t incl = wave_incl_sum_u64(pn, lane);
+  const uint64_t tot = readlane_u64(incl, 63);
+  const int d = A.d;
+  const uint64_t excl = incl - pn;
+  uint32_t carry = 0;
+  for (uint64_t beta = 0; beta < tot; beta += 64) {
+    const uint64_t rho = beta + uint64_t(lane);
+    O.marks[lane] = 0;
+    wave_sync_walk();
+    if (pn != 0 && excl >= beta && excl - beta < 64) O.marks[excl - beta] = uint32_t(lane) + 1;
+    wave_sync_walk();
+    uint32_t mk = wave_incl_max_u32(O.marks[lane], lane);
+    mk = mk > carry ? mk : carry;
+    carry = __builtin_amdgcn_readlane(mk, 63);
+    const int owner = int(mk) - 1;  // row beta's owner: a first row at or before it
+    // Every lane reads the owner's values (a cross-lane read runs in all lanes).
+    const uint32_t o_lo = __shfl(uint32_t(excl), owner, 64);
+    const uint32_t o_hi = __shfl(uint32_t(excl >> 32), owner, 64);
+    const uint32_t o_v = __shfl(v, owner, 64);
+    const uint32_t o_v0 = __shfl(v0, owner, 64);
+    const uint32_t o_R = __shfl(R, owner, 64);
+    if (rho < tot) {
+      const uint64_t t = rho - ((uint64_t(o_hi) << 32) | o_lo);
+      uint32_t* row = O.ring + (uint32_t(O.produced + rho) & (kWalkRing - 1)) * uint32_t(d);
+      for (int j = 0; j < npre; ++j) row[j] = __builtin_amdgcn_readlane(aj, j);
+      if (kind == 2) {
+        row[d - 1] = o_v;  // the forced last coordinate
+      } else {
+        if (kind == 0) row[d - 3] = o_v;
+        const uint32_t pv = o_v0 + uint32_t(t) * A.step;
+        row[d - 2] = pv;
+        row[d - 1] = dlast.div(o_R - pv * dg2.d);
+      }
     }
-    A.cnt[i] = rows;
+    wave_sync_walk();
+    const uint64_t left = tot - beta;
+    const uint64_t written = O.produced + beta + (left < 64 ? left : 64);
+    while (written - O.flushed >= kWalkFlush) {
+      walk_flush(A, O.ring, O.base, O.cnt, O.flushed, kWalkFlush, lane);
+      O.flushed += kWalkFlush;
+    }
+    wave_sync_walk();
   }
+  O.produced += tot;
+  return tot;
 }
 
-__device__ inline void wave_sync_walk() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// The record's rows: counted (returned, in every lane), or written to their
+// place (WRITE; the return value is then unused).
+template <bool WRITE>
+__device__ uint64_t walk_record(const WalkArgs& A, uint64_t rec, RecordOut& O, int lane,
+                                uint32_t gj) {
+  const int d = A.d;
+  const uint32_t* p = A.pre + rec * uint64_t(d + 3);
+  const int m = int(p[0]);
+  const uint32_t x = p[1], lo = p[2], hi = p[3];
+  uint32_t aj = lane < m && lane < d - 1 ? p[4 + lane] : 0;
+  const DivMod32 dg2 = A.dg[d - 2 >= 0 ? d - 2 : 0];
+  const DivMod32 dlast = A.dg[d - 1];
+  if (m >= d - 1) {  // coordinates 0..d-2 fixed: the last is forced, or no row
+    const uint32_t q = dlast.div(x);
+    const uint32_t pn = dlast.mod(x, q) == 0 ? 1u : 0u;
+    walk_chunk<WRITE>(A, O, lane, lane == 0 ? pn : 0u, aj, d - 1, 2, q, 0, 0, dg2, dlast);
+    return pn;
+  }
+  if (m == d - 2) {  // one progression of coordinate d-2 over [lo, hi]
+    uint32_t v0 = 0;
+    const uint32_t c = prog_count(A, dg2, x, lo, hi, &v0);
+    walk_chunk<WRITE>(A, O, lane, lane == 0 ? c : 0u, aj, d - 2, 1, 0, v0, x, dg2, dlast);
+    return c;
+  }
+  const int l = d - 3;
+  const DivMod32 dgl = A.dg[l];
+  uint32_t rj = 0;  // lanes m..l-1: the remainder after coordinate j
+  uint32_t y = x;   // the remainder before coordinate l
+  if (m < l) {
+    const uint32_t rm = x - lo * gj;  // lane m's value of gj is g_m
+    const uint32_t r0 = __builtin_amdgcn_readlane(rm, m);
+    if (lane == m) aj = lo;
+    if (lane >= m && lane < l) rj = r0;
+    y = r0;
+  }
+  uint64_t rows = 0;
+  for (;;) {
+    const uint32_t vlo = m == l ? lo : 0u;
+    uint32_t vhi = dgl.div(y);
+    if (m == l && hi < vhi) vhi = hi;
+    for (uint64_t vb = vlo; vb <= vhi; vb += 64) {
+      const uint64_t v64 = vb + uint64_t(lane);
+      const bool act = v64 <= vhi;
+      const uint32_t v = uint32_t(v64);
+      const uint32_t R = act ? y - v * dgl.d : 0u;
+      uint32_t v0 = 0;
+      const uint32_t c = act ? prog_count(A, dg2, R, 0, 0xffffffffu, &v0) : 0u;
+      rows += walk_chunk<WRITE>(A, O, lane, c, aj, l, 0, v, v0, R, dg2, dlast);
+    }
+    if (m >= l) break;
+    // Odometer over coordinates m..l-1: the deepest one that can still grow.
+    const bool can = lane >= m && lane < l && rj >= gj && (lane != m || aj < hi);
+    const uint64_t mask = __ballot(can);
+    if (mask == 0) break;
+    const int js = 63 - __clzll((unsigned long long)mask);
+    if (lane == js) {
+      aj += 1;
+      rj -= gj;
+    }
+    const uint32_t nrem = __builtin_amdgcn_readlane(rj, js);
+    if (lane > js && lane < l) {
+      aj = 0;
+      rj = nrem;
+    }
+    y = __builtin_amdgcn_readlane(rj, l - 1);
+  }
+  if (!WRITE) {  // this lane's rows summed over the wavefront
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) rows += __shfl_xor(rows, off, 64);
+  }
+  return rows;
 }
 
-// Pass 2: a wavefront takes 64 consecutive records, one per lane.  In
-// rounds, every lane stages up to stage_rows rows of its record in LDS (each
-// lane's rows are contiguous in the output); then the wavefront writes the
-// staged words two lanes' rows at a time, consecutive lanes on consecutive
-// words: a store instruction covers two contiguous runs instead of 64
-// scattered words.
-constexpr uint32_t kWalkLaneWords = 32;  // LDS words staged per lane per round
-// Each lane's staging area starts kWalkLaneWords + 1 words after the previous
-// lane's: with an odd stride the lanes' stores of one staged word fall in
-// different LDS banks (a stride of 32 words puts every lane in one bank).
-constexpr uint32_t kWalkLaneStride = kWalkLaneWords + 1;
-// The flush covers a lane's staged words with 32 lanes, and a row of up to
-// kMaxD words must fit.
-static_assert(kWalkLaneWords <= 32 && kWalkLaneWords >= uint32_t(kMaxD), "walk staging size");
-__global__ __launch_bounds__(kWalkThreads) void k_walk_write(WalkArgs A) {
-  __shared__ WalkLds W;
-  __shared__ uint32_t stage[kWalkThreads * kWalkLaneStride];
-  extern __shared__ uint32_t cols[];  // a[] then r[]: (d - 2) columns each
-  walk_lds_init(A, W);
-  const uint32_t levels = uint32_t(A.d > 2 ? A.d - 2 : 1);
+// Pass 1 (WRITE = false): each wavefront counts records w, w + W, ... into
+// cnt.  Pass 2 (WRITE = true): the same walks write each record's rows at
+// off[record].
+template <bool WRITE>
+__global__ __launch_bounds__(kWalkThreads) void k_walk(WalkArgs A) {
+  extern __shared__ uint32_t lds[];  // per wavefront: ring (kWalkRing x d words), 64 marks
   const int lane = int(threadIdx.x & 63);
   const int wave = int(threadIdx.x >> 6);
-  uint32_t* buf = stage + uint32_t(threadIdx.x) * kWalkLaneStride;
-  const uint32_t* wstage = stage + uint32_t(wave) * 64 * kWalkLaneStride;
-  const int d = A.d;
-  const uint32_t g2 = W.g[d - 2];
-  const DivMod32 dlast = W.dg[d - 1];
-  const uint64_t waves = uint64_t(gridDim.x) * (kWalkThreads / 64);
-  for (uint64_t w = uint64_t(blockIdx.x) * (kWalkThreads / 64) + uint64_t(wave);
-       w * 64 < A.nprefix; w += waves) {
-    const uint64_t i = w * 64 + uint64_t(lane);
-    const bool has = i < A.nprefix;
-    WalkState S;
-    S.a = cols + threadIdx.x;
-    S.r = cols + levels * kWalkThreads + threadIdx.x;
-    uint64_t pos = 0;
-    S.done = true;
-    S.pn = 0;
-    if (has) {
-      walk_init(A, W, S, A.pre + i * uint64_t(d + 3));
-      pos = A.off[i];
+  const uint32_t wave_words = kWalkRing * uint32_t(A.d) + 64;
+  RecordOut O;
+  O.ring = lds + uint32_t(wave) * wave_words;
+  O.marks = O.ring + kWalkRing * uint32_t(A.d);
+  const uint32_t gj = lane < A.d ? A.g.g[lane] : 0u;
+  const uint64_t waves = uint64_t(gridDim.x) * kWalkWaves;
+  for (uint64_t rec = uint64_t(blockIdx.x) * kWalkWaves + uint64_t(wave); rec < A.nprefix;
+       rec += waves) {
+    O.produced = 0;
+    O.flushed = 0;
+    if (WRITE) {
+      O.base = A.off[rec];
+      O.cnt = A.off[rec + 1] - O.base;
+      if (O.cnt == 0) continue;
     }
-    for (;;) {
-      // Stage up to stage_rows rows (divergent: each lane in its own walk).
-      uint32_t nb = 0;
-      while (nb < A.stage_rows) {
-        if (S.pn == 0) {
-          if (S.done) break;
-          next_prog(A, W, S);
-          continue;
-        }
-        uint32_t* row = buf + nb * uint32_t(d);
-        for (int j = 0; j < d - 2; ++j) row[j] = WA(j);
-        row[d - 2] = S.pv;
-        row[d - 1] = dlast.div(S.pR - S.pv * g2);
-        ++nb;
-        --S.pn;
-        if (S.pn) S.pv = A.desc ? S.pv - A.step : S.pv + A.step;
-      }
-      const bool more = !(S.done && S.pn == 0);
-      // Flush: two lanes' staged rows per step, lanes 0-31 on the first
-      // one's words and lanes 32-63 on the second's (at most 32 words each),
-      // so that every store instruction covers two contiguous runs.
-      const uint32_t wl = nb * uint32_t(d);
-      const uint64_t gw = pos * uint64_t(d);  // this lane's first output word
-      const uint32_t gw_lo = uint32_t(gw), gw_hi = uint32_t(gw >> 32);
-      wave_sync_walk();  // the staged rows are visible to the wavefront
-      const bool upper = lane >= 32;
-      const uint32_t t = uint32_t(lane) & 31u;
-      for (int s2 = 0; s2 < 64; s2 += 2) {
-        const uint32_t wa = __builtin_amdgcn_readlane(wl, s2);
-        const uint32_t wb = __builtin_amdgcn_readlane(wl, s2 + 1);
-        if ((wa | wb) == 0) continue;
-        const uint32_t w = upper ? wb : wa;
-        const uint32_t lo = upper ? __builtin_amdgcn_readlane(gw_lo, s2 + 1)
-                                  : __builtin_amdgcn_readlane(gw_lo, s2);
-        const uint32_t hi = upper ? __builtin_amdgcn_readlane(gw_hi, s2 + 1)
-                                  : __builtin_amdgcn_readlane(gw_hi, s2);
-        if (t < w) {
-          const uint32_t src = uint32_t(s2) + (upper ? 1u : 0u);
-          const uint32_t v = wstage[src * kWalkLaneStride + t];
-          __builtin_nontemporal_store(v, A.out + ((uint64_t(hi) << 32) | lo) + t);
-        }
-      }
-      wave_sync_walk();  // every lane has read the staged rows
-      pos += nb;
-      if (__ballot(more) == 0) break;
+    const uint64_t rows = walk_record<WRITE>(A, rec, O, lane, gj);
+    if (!WRITE) {
+      if (lane == 0) A.cnt[rec] = rows;
+    } else if (O.produced > O.flushed) {
+      walk_flush(A, O.ring, O.base, O.cnt, O.flushed, uint32_t(O.produced - O.flushed), lane);
+      wave_sync_walk();
     }
   }
 }
@@ -589,15 +615,16 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
   for (int i = 0; i < d; ++i) A.dg[i] = DivMod32::make(gens[i]);
   A.dh = DivMod32::make(A.h);
   A.dstep = DivMod32::make(A.step);
-  A.stage_rows = std::max<uint32_t>(1, kWalkLaneWords / uint32_t(d));
+  A.dd = DivMod32::make(uint32_t(d));
   A.nprefix = np;
   A.pre = reinterpret_cast<const uint32_t*>(c.pre.p);
   A.cnt = reinterpret_cast<uint64_t*>(c.cnt.p);
   A.off = reinterpret_cast<const uint64_t*>(c.off.p);
   A.out = out;
-  const uint64_t blocks = std::min<uint64_t>((np + kWalkThreads - 1) / kWalkThreads, 65535);
-  const size_t cols_bytes = size_t(2) * std::max(d - 2, 1) * kWalkThreads * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_walk_count, dim3(uint32_t(blocks)), dim3(kWalkThreads), cols_bytes, s, A);
+  // One wavefront per record (records w, w + W, ... beyond the grid).
+  const uint64_t blocks = std::min<uint64_t>((np + kWalkWaves - 1) / kWalkWaves, 65535);
+  const size_t ring_bytes = size_t(kWalkWaves) * (kWalkRing * uint32_t(d) + 64) * sizeof(uint32_t);
+  hipLaunchKernelGGL(k_walk<false>, dim3(uint32_t(blocks)), dim3(kWalkThreads), 0, s, A);
   ZSET_HIP(hipGetLastError());
   // off[i] = rows of prefixes before i; off[np] = |Z(n)| (cnt[np] is zero).
   ZSET_HIP(hipMemsetAsync(A.cnt + np, 0, sizeof(uint64_t), s));
@@ -611,7 +638,7 @@ extern "C" zset_status zset_enumerate_walk(uint64_t n, const uint32_t* gens, int
     return fail(ZSET_ECAPACITY, "out holds " + std::to_string(out_rows_cap) + " rows, |Z(n)| = " +
                                     std::to_string(total));
   if (total > 0) {
-    hipLaunchKernelGGL(k_walk_write, dim3(uint32_t(blocks)), dim3(kWalkThreads), cols_bytes, s,
+    hipLaunchKernelGGL(k_walk<true>, dim3(uint32_t(blocks)), dim3(kWalkThreads), ring_bytes, s,
                        A);
     ZSET_HIP(hipGetLastError());
     ZSET_HIP(hipStreamSynchronize(s));
