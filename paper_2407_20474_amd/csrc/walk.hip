@@ -188,10 +188,38 @@ __device__ inline uint64_t walk_chunk(const WalkArgs& A, RecordOut& O, int lane,
                                       uint32_t aj, int npre, int kind, uint32_t v, uint32_t v0,
                                       uint32_t R, const DivMod32& dg2, const DivMod32& dlast) {
   if (!WRITE) return pn;
-  if (__ballot(pn != 0) == 0) return 0;
+  const uint64_t some = __ballot(pn != 0);
+  if (some == 0) return 0;
+  const int d = A.d;
+  if (__ballot(pn > 1) == 0) {
+    // At most one row per lane (the usual case for large generators): the
+    // rows' places come from a ballot, and each lane stages its own row.
+    const uint32_t pos = __builtin_amdgcn_mbcnt_hi(
+        uint32_t(some >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(some), 0u));
+    const uint32_t nrows = uint32_t(__popcll((unsigned long long)some));
+    if (pn != 0) {
+      uint32_t* row = O.ring + (uint32_t(O.produced + pos) & (kWalkRing - 1)) * uint32_t(d);
+      for (int j = 0; j < npre; ++j) row[j] = __builtin_amdgcn_readlane(aj, j);
+      if (kind == 2) {
+        row[d - 1] = v;
+      } else {
+        if (kind == 0) row[d - 3] = v;
+        row[d - 2] = v0;
+        row[d - 1] = dlast.div(R - v0 * dg2.d);
+      }
+    }
+    wave_sync_walk();
+    const uint64_t written = O.produced + nrows;
+    while (written - O.flushed >= kWalkFlush) {
+      walk_flush(A, O.ring, O.base, O.cnt, O.flushed, kWalkFlush, lane);
+      O.flushed += kWalkFlush;
+    }
+    wave_sync_walk();
+    O.produced = written;
+    return nrows;
+  }
   const uint64_t incl = wave_incl_sum_u64(pn, lane);
   const uint64_t tot = readlane_u64(incl, 63);
-  const int d = A.d;
   const uint64_t excl = incl - pn;
   uint32_t carry = 0;
   for (uint64_t beta = 0; beta < tot; beta += 64) {
