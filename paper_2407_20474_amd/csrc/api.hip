@@ -1420,6 +1420,28 @@ zset_status zset_selftest_host(void) {
       }
     }
   }
+  // The count table's closed-form last rows against direct counts:
+  // [h_2 divides x] and |Z(x; h_1, h_2)| = #{m_1 : m_1 h_1 <= x, h_2 divides x - m_1 h_1}.
+  const uint32_t pairs[][2] = {{1, 1},   {1, 3},    {3, 1},      {6, 4},     {4, 6},
+                               {7, 7},   {13, 83},  {65, 83},    {10, 15},   {12, 18},
+                               {2, 70000}, {600, 7}, {65535, 2}, {1, 65535}, {30, 65536}};
+  for (const auto& hp : pairs) {
+    const uint32_t g2[2] = {hp[0], hp[1]};
+    const LastRows L = make_last_rows(g2, 2);
+    if (!L.on) return fail(ZSET_EDEVICE, "closed-form rows refused a pair below the bound");
+    for (uint32_t x = 0; x < 3000; x += (x < 600 ? 1 : 7)) {
+      uint32_t want = 0;
+      for (uint64_t m1 = 0; m1 * hp[0] <= x; ++m1) want += ((x - m1 * hp[0]) % hp[1] == 0);
+      if (last_row_pair(L, x) != want || last_row_divides(L, x) != (x % hp[1] == 0 ? 1u : 0u)) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "closed-form count rows wrong for x = %u, g = (%u, %u)", x,
+                      hp[0], hp[1]);
+        return fail(ZSET_EDEVICE, buf);
+      }
+    }
+  }
+  const uint32_t big[2] = {3, 70001};  // h_2 / gcd >= 2^16: scanned instead
+  if (make_last_rows(big, 2).on) return fail(ZSET_EDEVICE, "closed-form rows beyond their bound");
   return ZSET_OK;
 }
 

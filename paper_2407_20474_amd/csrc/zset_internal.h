@@ -213,11 +213,11 @@ struct LastRows {
 };
 LastRows make_last_rows(const uint32_t* gens, int d);  // host
 
-__device__ inline uint32_t last_row_divides(const LastRows& L, uint32_t x) {
+__host__ __device__ inline uint32_t last_row_divides(const LastRows& L, uint32_t x) {
   return x == L.dg.div(x) * L.dg.d ? 1u : 0u;
 }
 
-__device__ inline uint32_t last_row_pair(const LastRows& L, uint32_t x) {
+__host__ __device__ inline uint32_t last_row_pair(const LastRows& L, uint32_t x) {
   const uint32_t q = L.dc.div(x);
   if (x != q * L.dc.d) return 0;
   const uint32_t mmax = L.dh1c.div(q);
