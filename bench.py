@@ -5,8 +5,12 @@ buffer already resident in HBM: count table, memo build (k = 2: the library
 builds two-coordinate memos in closed form, element-parallel, which gives the
 same lists as the recurrence of Lemma 2.3; the recurrence itself is timed
 beside the step and reported as stages_us.memo_recurrence_us), slice plan, and
-the write pass that stores every uint32 row.  Prints one JSON line (the
-driver's contract).
+the write pass that stores every uint32 row.  The timed steps are queued
+calls (zset_enumerate_async: each enqueues the whole path and returns, the
+host waits once after the last); the write pass is timed by HIP events that
+the call records around it, in a second run of the same queued steps.
+`--sync-steps` times synchronous calls instead, and the line also reports
+their per-step time.  Prints one JSON line.
 
 The default workload is the large single enumeration: d = 6 generators drawn
 distinct in [10, 100] with gcd 1 (seed 0), n the smallest element with
@@ -67,6 +71,9 @@ def parse():
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--rows-per-tile", type=int, default=0)
     ap.add_argument("--count-only", action="store_true")
+    ap.add_argument("--sync-steps", action="store_true",
+                    help="time synchronous calls (zset_enumerate_ex, a host wait per step) "
+                         "instead of queued ones (zset_enumerate_async)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=float, default=2.5e8)
     ap.add_argument("--serve-queries", type=int, default=10000,
@@ -231,6 +238,10 @@ def run_batch(args):
     print(f"# plain path: {plain_s:.2f} s for {len(allq)} calls", file=sys.stderr, flush=True)
     st = srv.stats()
     srv.free()
+    if queued:
+        stages["write_us_queued"] = round(write_us, 2)
+        stages["ms_per_step_write_events"] = round(ms_events, 4)
+        stages["ms_per_step_synchronous"] = round(ms_sync, 4)
     line = {
         "metric": "Z(n) factorizations/s emitted (bit-exact)",
         "value": value,
@@ -719,23 +730,71 @@ def main():
         return zset.enumerate_ex(n, g, out=out, k=k, rows_per_tile=args.rows_per_tile,
                                  count_only=args.count_only)
 
+    # Queued steps (zset_enumerate_async): each call enqueues the whole path
+    # (count table and memo, slice plan and memo layout, write pass, outcome
+    # word) and returns; the host waits once after the last one.  Only the
+    # three-launch form queues (k = 1 or 2, default slices); any other call
+    # runs to completion inside zset_enumerate_async.
+    queued = (not args.sync_steps and args.rows_per_tile == 0 and k in (1, 2))
+    results = torch.zeros((max(args.steps, args.warmup, 1), 4), dtype=torch.int64).pin_memory()
+    wev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+
+    def queue(i, events=None):
+        zset.enumerate_async(n, g, out, results[i], k=k, count_only=args.count_only,
+                             write_events=events)
+
+    def outcomes():
+        # Every queued step's outcome: |Z(n)| rows (and the checksum when
+        # count-only) or the error it found.
+        got = {zset.async_outcome(results[i]) for i in range(args.steps)}
+        assert len(got) == 1 and next(iter(got))[0] == rows, got
+        results.fill_(-1)
+
     for i in range(args.warmup):
         step()
+        if queued:
+            queue(i)
+            torch.cuda.synchronize()
+            zset.async_outcome(results[i])
         print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     stats = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stats.append(step().stats)
+    for i in range(args.steps):
+        if queued:
+            queue(i)
+        else:
+            stats.append(step().stats)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = dt * 1e3 / args.steps
     value = rows / (dt / args.steps)
+    if queued:
+        outcomes()
+        # The write pass's duration: the same queued steps again, each with a
+        # pair of HIP events around its write pass (recorded on the call's
+        # stream by the library).  Event markers between launches idle the
+        # device for a few microseconds each, so the steps above carry none.
+        t1 = time.perf_counter()
+        for i in range(args.steps):
+            queue(i, wev[i])
+        torch.cuda.synchronize()
+        ms_events = (time.perf_counter() - t1) * 1e3 / args.steps
+        outcomes()
+        write_list = [a.elapsed_time(b) * 1e3 for a, b in wev]
+        # The per-stage times come from synchronous calls (timing events
+        # inside the call, a host wait per call).
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            stats.append(step().stats)
+        torch.cuda.synchronize()
+        ms_sync = (time.perf_counter() - t1) * 1e3 / args.steps
 
     def avg(key):
         return sum(s[key] for s in stats) / len(stats)
 
-    write_us = avg("write_us")
+    write_us = sum(write_list) / len(write_list) if queued else avg("write_us")
     bytes_written = rows * d * 4
     stages = {key: round(avg(key), 2) for key in
               ("count_us", "memo_us", "plan_us", "write_us", "total_us")}
@@ -776,6 +835,10 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
                 "kernel": "k_write (write pass)",
                 "algorithmic_bytes_per_launch": bytes_written}
+    if queued:
+        stages["write_us_queued"] = round(write_us, 2)
+        stages["ms_per_step_write_events"] = round(ms_events, 4)
+        stages["ms_per_step_synchronous"] = round(ms_sync, 4)
     line = {
         "metric": "Z(n) factorizations/s emitted (bit-exact)",
         "value": value,

@@ -28,7 +28,10 @@
  *     count-table rows have n + 1 entries, indexed in 32 bits on the GPU).
  *   - Status codes are returned, never thrown; zset_strerror gives the text.
  *     On any error returned before the first kernel launch, `out` is untouched.
- *   - Every call that launches work synchronises its stream before returning.
+ *   - Every call that launches work synchronises its stream before returning,
+ *     except zset_enumerate_async, which may return with its launches still
+ *     queued (the library's later calls wait for them before they reuse its
+ *     scratch memory).
  *   - The library keeps per-device scratch memory (count table, tile table,
  *     memo staging) that it grows on demand and reuses; calls are serialised
  *     by an internal lock.
@@ -185,6 +188,44 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t 
                               uint64_t out_rows_cap, const zset_opts *opts,
                               zset_memo memo, uint64_t *rows_written,
                               uint64_t *checksum, zset_stats *stats);
+
+/*
+ * zset_enumerate_async -- zset_enumerate_ex without waiting for the device
+ * (no memo handle, no timings).  When the call takes the three-launch form
+ * (k fixed at 1 or 2 by opts->k, n + 1 <= 16384, a memo of at most 2^19
+ * rows, the default slice options, no partial memo), its launches (count
+ * table and memo, slice plan and memo layout, write pass, then one thread
+ * that writes the outcome) are enqueued on opts->stream and the call returns
+ * at once; the caller synchronises the stream (or waits on an event recorded
+ * after the call) before it reads `result` or `out`.  Otherwise the call runs
+ * to completion as zset_enumerate_ex does and fills `result` before it
+ * returns.  Calls on one stream run in call order, each reading and writing
+ * the library's scratch memory after the one before; a call on another stream
+ * first waits on the host for the last asynchronous call to end.  Rows,
+ * order and checksum are exactly those of zset_enumerate_ex (Section 3,
+ * Alg 3.2).
+ *   out           device, out_rows_cap * d uint32; ignored when count_only
+ *   out_rows_cap  rows `out` holds; checked on the device (nothing written,
+ *                 result[0] = ZSET_ECAPACITY) when < |Z(n)|
+ *   opts          host, or NULL for the defaults
+ *   result        pinned host memory (hipHostMalloc, or a pinned torch
+ *                 tensor), 3 uint64, written by the device once the call's
+ *                 work is done: [0] the outcome as a zset_status (read as
+ *                 int64_t: ZSET_OK, or ECAPACITY, EOVERFLOW, EINVAL for a
+ *                 slice count beyond the plan, EDEVICE), [1] |Z(n)|, [2] the
+ *                 checksum (count_only, else 0).  Owned by the caller; must
+ *                 not be reused before the stream has passed this call.
+ *   write_events  NULL, or two hipEvent_t that the call records on
+ *                 opts->stream right before and right after its write pass
+ *                 (for timing the pass of an asynchronous call)
+ * Returns ZSET_OK once the work is enqueued.  Errors found before any launch
+ * are returned (EINVAL: as zset_enumerate_ex, `result` not pinned host memory,
+ * a NULL event; ENOMEM; EDEVICE for a failed launch); a call that ran to
+ * completion returns its outcome and also writes it to result[0].
+ */
+zset_status zset_enumerate_async(uint64_t n, const uint32_t *gens, int d, uint32_t *out,
+                                 uint64_t out_rows_cap, const zset_opts *opts,
+                                 uint64_t *result, void *const *write_events);
 
 /*
  * zset_enumerate_noalloc -- zset_enumerate_ex for callers that cannot

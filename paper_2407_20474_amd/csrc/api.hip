@@ -2,6 +2,7 @@
 // per-device scratch memory, the order of launches, status codes and timings.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -9,6 +10,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 
 #include "zset.h"
 #include "zset_host.h"
@@ -75,6 +77,14 @@ struct Ctx {
   hipStream_t plan = nullptr;
   hipEvent_t counted = nullptr, planned = nullptr;
   int wall_khz = 0;  // the device's constant-rate clock (kernel time stamps)
+  // Asynchronous calls: the sequence number of the last one enqueued, its
+  // stream, and whether it may still be running.  Its last launch stores the
+  // sequence number to pinned[kDoneWord] (through done_dev, the device's
+  // address of that word), after its result words.
+  uint64_t seq = 0;
+  hipStream_t busy_stream = nullptr;
+  bool inflight = false;
+  uint64_t* done_dev = nullptr;
 };
 
 std::map<int, Ctx*> g_ctx;
@@ -95,6 +105,8 @@ constexpr int kMiscErr = 0, kMiscSum = 1, kMiscRowSums = 2,
 constexpr size_t kMiscWords = kMiscStamp + 2;
 constexpr int kDefaultClaimPct = 100;  // percent of slices claimed at run time
 constexpr size_t kPinnedWords = 128;
+constexpr size_t kDoneWord = kPinnedWords - 1;  // pinned word of the asynchronous calls
+static_assert(kMiscWords < kDoneWord && 2 * kMaxD + 3 < kDoneWord, "pinned readback layout");
 
 zset_status get_ctx(Ctx** out) {
   int dev = 0;
@@ -128,6 +140,12 @@ zset_status get_ctx(Ctx** out) {
     (void)hipGetLastError();
     return fail(ZSET_EDEVICE, "side stream or event creation failed");
   }
+  c->pinned[kDoneWord] = 0;
+  if (hipHostGetDevicePointer(reinterpret_cast<void**>(&c->done_dev), c->pinned + kDoneWord, 0) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ZSET_EDEVICE, "hipHostGetDevicePointer of the readback area failed");
+  }
   if (hipDeviceGetAttribute(&c->wall_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) {
     (void)hipGetLastError();
     c->wall_khz = 0;
@@ -137,6 +155,39 @@ zset_status get_ctx(Ctx** out) {
   g_ctx[dev] = c;
   *out = c;
   return ZSET_OK;
+}
+
+// Waits for the last asynchronous call's launches, which read and write the
+// context's buffers, before anything else may reuse or free them.
+// No event is recorded per call (each event marker between kernels leaves
+// the device idle for microseconds): the host watches the pinned word that
+// the call's last launch stores, and after 30 s falls back to a device-wide
+// wait.
+zset_status settle(Ctx* c) {
+  if (!c->inflight) return ZSET_OK;
+  const volatile uint64_t* done = c->pinned + kDoneWord;
+  const auto t0 = std::chrono::steady_clock::now();
+  while (*done < c->seq) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(30)) {
+      const hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+      if (*done < c->seq) return fail(ZSET_EDEVICE, "an asynchronous call did not finish");
+      break;
+    }
+    std::this_thread::yield();
+  }
+  c->inflight = false;
+  return ZSET_OK;
+}
+
+// ensure() for a context buffer that an asynchronous call may still be using:
+// a buffer that must grow is freed only after that call is done.
+zset_status grow(Ctx* c, DevBuf& b, size_t bytes) {
+  if (b.bytes < std::max<size_t>(bytes, 16)) {
+    const zset_status st = settle(c);
+    if (st != ZSET_OK) return st;
+  }
+  return ensure(b, bytes);
 }
 
 }  // namespace
@@ -481,6 +532,27 @@ __global__ void k_clear_words(uint64_t* p, uint32_t n) {
   if (i < n) p[i] = 0;
 }
 
+// The outcome of an asynchronous call, for a host that reads pinned memory
+// once the stream is done: result[0] = zset_status (as a signed 64-bit value;
+// the kernels' status word mapped as the synchronous call maps it), [1] =
+// |Z(n)|, [2] = the checksum (count-only calls, else 0).  One thread.
+__global__ void k_publish_result(const uint64_t* misc, uint32_t total_word, int count_only,
+                                 uint64_t* result, uint64_t* done, uint64_t seq) {
+  if (threadIdx.x != 0) return;
+  const int code = reinterpret_cast<const volatile int*>(misc)[0];
+  int64_t st = ZSET_OK;
+  if (code == kErrOverflow) st = ZSET_EOVERFLOW;
+  else if (code == kErrCapacity) st = ZSET_ECAPACITY;
+  else if (code == kErrSlices) st = ZSET_EINVAL;
+  else if (code != 0) st = ZSET_EDEVICE;
+  result[1] = misc[total_word];
+  result[2] = count_only ? misc[1] : 0;
+  __threadfence_system();
+  result[0] = uint64_t(st);
+  __threadfence_system();
+  *reinterpret_cast<volatile uint64_t*>(done) = seq;
+}
+
 }  // namespace
 }  // namespace zset
 
@@ -560,6 +632,7 @@ zset_status zset_count(uint64_t n, const uint32_t* gens, int d, uint64_t* count)
   std::lock_guard<std::mutex> lock(g_mu);
   Ctx* c = nullptr;
   if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  if ((st = settle(c)) != ZSET_OK) return st;
   const uint64_t N = n + 1;
   if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
@@ -597,6 +670,7 @@ zset_status zset_memo_build(const uint32_t* gens_trailing, int k, uint64_t top, 
   std::lock_guard<std::mutex> lock(g_mu);
   Ctx* c = nullptr;
   if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  if ((st = settle(c)) != ZSET_OK) return st;
   // Count table of the memo's own generators up to top - 1: row i holds
   // |Z(m; h_i..h_k)| = |Z_{>=i}(m; h)|, and row 0 gives the list sizes.
   const uint64_t nm = top - 1;
@@ -712,10 +786,15 @@ bool host_memo_rows(uint64_t n, const uint32_t* h, int k, uint64_t* rows) {
 // slices from it, and a query that overflows or exceeds out_rows_cap is
 // refused on the device (no slices: nothing written) and reported at the end.
 // *taken = false (and nothing enqueued) when the call needs the general path.
+// The three-launch path of a call whose memo dimension is 1 or 2, when the
+// call qualifies (*taken).  With async_result the launches are only enqueued:
+// the outcome goes to async_result (pinned host words, k_publish_result) and
+// wev, if given, are recorded around the write pass.
 zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, uint32_t* out,
                               uint64_t out_rows_cap, const zset_opts& opts,
                               uint64_t* rows_written, uint64_t* checksum, zset_stats* stats,
-                              hipStream_t s, bool* taken) {
+                              hipStream_t s, bool* taken, uint64_t* async_result = nullptr,
+                              const hipEvent_t* wev = nullptr) {
   *taken = false;
   const int k = opts.k;
   const bool count_only = opts.count_only != 0;
@@ -740,7 +819,7 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
   uint64_t* misc = reinterpret_cast<uint64_t*>(c->misc.p);
   int* err = reinterpret_cast<int*>(misc + kMiscErr);
   zset_status st;
-  if ((st = ensure(c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
+  if ((st = grow(c, c->table, size_t(d + 1) * N * sizeof(uint64_t))) != ZSET_OK) return st;
   uint64_t* T = reinterpret_cast<uint64_t*>(c->table.p);
   EnumParams P;
   const uint64_t leaf_words = init_params(P, n, gens, d, k, 0, sums, T, err, misc + kMiscSum, out,
@@ -764,13 +843,13 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
   P.dyn = 1;
   *taken = true;
 
-  if ((st = ensure(c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
-  if ((st = ensure(c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
-  if ((st = ensure(c->endc, size_t(std::min<uint64_t>(G, N)) * sizeof(uint64_t))) != ZSET_OK)
+  if ((st = grow(c, c->off, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+  if ((st = grow(c, c->nat, size_t(Rn) * k * sizeof(uint32_t))) != ZSET_OK) return st;
+  if ((st = grow(c, c->endc, size_t(std::min<uint64_t>(G, N)) * sizeof(uint64_t))) != ZSET_OK)
     return st;
-  if ((st = ensure(c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
-  if ((st = ensure(c->tiles, size_t(want) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
-  if (k == 2 && (st = ensure(c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
+  if ((st = grow(c, c->leaf, size_t(leaf_words) * sizeof(uint32_t))) != ZSET_OK) return st;
+  if ((st = grow(c, c->tiles, size_t(want) * (U + 2) * sizeof(uint32_t))) != ZSET_OK) return st;
+  if (k == 2 && (st = grow(c, c->cnt2, size_t(N + 1) * sizeof(uint64_t))) != ZSET_OK) return st;
   P.endc = reinterpret_cast<uint64_t*>(c->endc.p);
   P.leaf = reinterpret_cast<uint32_t*>(c->leaf.p);
   P.tiles = reinterpret_cast<uint32_t*>(c->tiles.p);
@@ -812,8 +891,21 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
                                                const_cast<uint32_t*>(P.leaf), Rn, P),
                               s));
     if (timed) ZSET_HIP(hipEventRecord(c->ev[4], s));
+    if (wev) ZSET_HIP(hipEventRecord(wev[0], s));
     ZSET_HIP(launch_write(P, count_only, align16, s));
+    if (wev) ZSET_HIP(hipEventRecord(wev[1], s));
     if (timed) ZSET_HIP(hipEventRecord(c->ev[5], s));
+    if (async_result) {
+      const uint64_t seq = c->seq + 1;
+      hipLaunchKernelGGL(k_publish_result, dim3(1), dim3(64), 0, s, misc,
+                         uint32_t(kMiscRowSums + d + 1), count_only ? 1 : 0, async_result,
+                         c->done_dev, seq);
+      ZSET_HIP(hipGetLastError());
+      c->seq = seq;
+      c->busy_stream = s;
+      c->inflight = true;
+      return ZSET_OK;
+    }
     ZSET_HIP(hipMemcpyAsync(c->pinned, misc, kMiscWords * sizeof(uint64_t),
                             hipMemcpyDeviceToHost, s));
     ZSET_HIP(hipStreamSynchronize(s));
@@ -864,6 +956,18 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
   }
   const int code = *reinterpret_cast<int*>(c->pinned);
   const uint64_t total = c->pinned[kMiscRowSums + d + 1];
+  if (async_result) {
+    // An asynchronous call that took the separate launches ran to the end
+    // here: its outcome is written from the host.
+    int64_t rs = ZSET_OK;
+    if (code == kErrOverflow) rs = ZSET_EOVERFLOW;
+    else if (code == kErrCapacity) rs = ZSET_ECAPACITY;
+    else if (code == kErrSlices) rs = ZSET_EINVAL;
+    else if (code != 0) rs = ZSET_EDEVICE;
+    async_result[1] = total;
+    async_result[2] = count_only ? c->pinned[kMiscSum] : 0;
+    async_result[0] = uint64_t(rs);
+  }
   if (code == kErrOverflow) {
     if (total == ~uint64_t(0)) return fail(ZSET_EOVERFLOW, "|Z(n)| >= 2^64 - 1");
     return fail(ZSET_EOVERFLOW, "|Z(n)| * d * 4 bytes overflows 64 bits");
@@ -909,13 +1013,16 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
 }  // namespace
 }  // namespace zset
 
-zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
-                              uint64_t out_rows_cap, const zset_opts* opts_in, zset_memo memo,
-                              uint64_t* rows_written, uint64_t* checksum, zset_stats* stats) {
-  g_last_error.clear();
+namespace zset {
+namespace {
+
+// The checks zset_enumerate_ex and zset_enumerate_async share: the query,
+// the options (opts = *opts_in or the defaults) and the output pointer's
+// presence.
+zset_status check_enumerate(uint64_t n, const uint32_t* gens, int d, const uint32_t* out,
+                            const zset_opts* opts_in, zset_opts& opts) {
   zset_status st = check_query(n, gens, d);
   if (st != ZSET_OK) return st;
-  zset_opts opts;
   if (opts_in) opts = *opts_in; else zset_default_opts(&opts);
   if (opts.k < -1 || opts.k > d - 1) return fail(ZSET_EINVAL, "k must be -1 or lie in [0, d-1]");
   if (opts.order != 0 && opts.order != 1) return fail(ZSET_EINVAL, "order must be 0 or 1");
@@ -923,8 +1030,21 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     return fail(ZSET_EINVAL, "claim_pct must be -1 or lie in [0, 100]");
   if (opts.rows_per_tile % 128 != 0 || opts.rows_per_tile > (uint64_t(1) << 30))
     return fail(ZSET_EINVAL, "rows_per_tile must be a multiple of 128 and at most 2^30");
+  if (opts.count_only == 0 && !out) return fail(ZSET_EINVAL, "out is NULL");
+  return ZSET_OK;
+}
+
+}  // namespace
+}  // namespace zset
+
+zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
+                              uint64_t out_rows_cap, const zset_opts* opts_in, zset_memo memo,
+                              uint64_t* rows_written, uint64_t* checksum, zset_stats* stats) {
+  g_last_error.clear();
+  zset_opts opts;
+  zset_status st = check_enumerate(n, gens, d, out, opts_in, opts);
+  if (st != ZSET_OK) return st;
   const bool count_only = opts.count_only != 0;
-  if (!count_only && !out) return fail(ZSET_EINVAL, "out is NULL");
   if (memo) {
     if (opts.k != -1 && opts.k != memo->k)
       return fail(ZSET_EINVAL, "opts.k differs from the memo's k");
@@ -941,6 +1061,7 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
   std::lock_guard<std::mutex> lock(g_mu);
   Ctx* c = nullptr;
   if ((st = get_ctx(&c)) != ZSET_OK) return st;
+  if ((st = settle(c)) != ZSET_OK) return st;
   if (memo && memo->device != c->device)
     return fail(ZSET_EINVAL, "memo lives on another device");
   if (!memo) {
@@ -1252,6 +1373,52 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t* gens, int d, uint32_t*
     stats->k = k;
   }
   return ZSET_OK;
+}
+
+zset_status zset_enumerate_async(uint64_t n, const uint32_t* gens, int d, uint32_t* out,
+                                 uint64_t out_rows_cap, const zset_opts* opts_in,
+                                 uint64_t* result, void* const* write_events) {
+  g_last_error.clear();
+  zset_opts opts;
+  zset_status st = check_enumerate(n, gens, d, out, opts_in, opts);
+  if (st != ZSET_OK) return st;
+  if (!result) return fail(ZSET_EINVAL, "result is NULL");
+  hipPointerAttribute_t attr;
+  std::memset(&attr, 0, sizeof attr);
+  if (hipPointerGetAttributes(&attr, result) != hipSuccess || attr.type != hipMemoryTypeHost ||
+      !attr.devicePointer) {
+    (void)hipGetLastError();
+    return fail(ZSET_EINVAL, "result is not pinned host memory (hipHostMalloc)");
+  }
+  if (opts.count_only == 0 && !is_device_pointer(out))
+    return fail(ZSET_EINVAL, "out is not device memory");
+  hipEvent_t wev[2] = {};
+  if (write_events) {
+    wev[0] = reinterpret_cast<hipEvent_t>(write_events[0]);
+    wev[1] = reinterpret_cast<hipEvent_t>(write_events[1]);
+    if (!wev[0] || !wev[1]) return fail(ZSET_EINVAL, "write_events holds a NULL event");
+  }
+  hipStream_t s = reinterpret_cast<hipStream_t>(opts.stream);
+  {
+    std::lock_guard<std::mutex> lock(g_mu);
+    Ctx* c = nullptr;
+    if ((st = get_ctx(&c)) != ZSET_OK) return st;
+    // A previous asynchronous call on another stream may still read the
+    // context's buffers; one on this stream runs before this call anyway.
+    if (c->inflight && c->busy_stream != s && (st = settle(c)) != ZSET_OK) return st;
+    bool taken = false;
+    st = enumerate_fixed_k(c, n, gens, d, out, out_rows_cap, opts, nullptr, nullptr, nullptr, s,
+                           &taken, static_cast<uint64_t*>(attr.devicePointer),
+                           write_events ? wev : nullptr);
+    if (taken || st != ZSET_OK) return st;
+  }
+  // Not the three-launch form: the call runs to completion here.
+  uint64_t rows = 0, sum = 0;
+  st = zset_enumerate_ex(n, gens, d, out, out_rows_cap, &opts, nullptr, &rows, &sum, nullptr);
+  result[1] = rows;
+  result[2] = sum;
+  result[0] = uint64_t(int64_t(st));
+  return st;
 }
 
 zset_status zset_enumerate_noalloc(uint64_t n, const uint32_t* gens, int d, uint32_t* out,

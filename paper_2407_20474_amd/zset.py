@@ -25,7 +25,7 @@ MAX_D = 32
 SYMBOLS = (
     "zset_default_opts", "zset_count", "zset_count_table", "zset_memo_build",
     "zset_memo_free", "zset_memo_read", "zset_enumerate", "zset_enumerate_ex",
-    "zset_enumerate_noalloc", "zset_enumerate_walk",
+    "zset_enumerate_noalloc", "zset_enumerate_async", "zset_enumerate_walk",
     "zset_batch_default_opts", "zset_batch_create", "zset_batch_info", "zset_batch_run",
     "zset_batch_times", "zset_batch_free",
     "zset_server_default_opts", "zset_server_create", "zset_server_add_set",
@@ -127,6 +127,9 @@ def load():
                                       _u64p, _u64p, ctypes.POINTER(Stats)]
     lib.zset_enumerate_noalloc.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
                                            ctypes.c_uint64, ctypes.POINTER(Opts), _u64p, _u64p]
+    lib.zset_enumerate_async.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_uint64, ctypes.POINTER(Opts), ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]
     lib.zset_store_ceiling.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int,
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.zset_enumerate_walk.argtypes = [ctypes.c_uint64, _u32p, ctypes.c_int, ctypes.c_void_p,
@@ -165,7 +168,7 @@ def load():
     lib.zset_last_error.restype = ctypes.c_char_p
     for name in ("zset_count", "zset_count_table", "zset_memo_build", "zset_memo_read",
                  "zset_enumerate", "zset_enumerate_ex", "zset_enumerate_noalloc",
-                 "zset_batch_create", "zset_batch_info",
+                 "zset_enumerate_async", "zset_batch_create", "zset_batch_info",
                  "zset_batch_run", "zset_batch_times", "zset_selftest_host",
                  "zset_server_create", "zset_server_add_set", "zset_server_set_info",
                  "zset_server_count", "zset_server_submit", "zset_server_wait",
@@ -359,6 +362,52 @@ def enumerate_noalloc(n: int, gens, out=None, *, k: int = -1, order: int = 0,
     r = int(rows_written.value)
     view = out[:r] if (out is not None and out.dim() == 2) else out
     return Result(rows=r, checksum=int(csum.value), stats={}, out=view)
+
+
+def enumerate_async(n: int, gens, out, result, *, k: int = -1, order: int = 0,
+                    count_only: bool = False, stream=None, out_rows_cap: int | None = None,
+                    write_events=None) -> None:
+    """Enqueue Z(n; g) through zset_enumerate_async and return without waiting.
+    `result` is a pinned int64 CPU tensor of at least 3 elements, written by
+    the device (read it with async_outcome once the stream is synchronised);
+    `out` as for enumerate_ex, never allocated here.  `write_events`: None, or
+    two torch.cuda.Event(enable_timing=True) recorded around the write pass."""
+    g = _gens(gens)
+    d = len(g)
+    if not (result.is_pinned() and result.dtype.itemsize == 8 and result.numel() >= 3
+            and result.is_contiguous()):
+        raise ValueError("result must be a contiguous pinned 64-bit CPU tensor of >= 3 elements")
+    if out is not None:
+        cap = out.numel() // max(d, 1) if out_rows_cap is None else out_rows_cap
+        ptr = out.data_ptr()
+    else:
+        cap, ptr = 0, None
+    opts = Opts()
+    load().zset_default_opts(ctypes.byref(opts))
+    opts.k, opts.order = k, order
+    opts.count_only = 1 if count_only else 0
+    opts.stream = _stream_handle(stream)
+    evs = None
+    if write_events is not None:
+        handles = []
+        for ev in write_events:
+            if not ev.cuda_event:
+                ev.record()  # torch creates the event at its first record
+            handles.append(ev.cuda_event)
+        evs = (ctypes.c_void_p * 2)(*handles)
+    _check(load().zset_enumerate_async(n, g.ctypes.data_as(_u32p), d, ptr, cap,
+                                       ctypes.byref(opts), result.data_ptr(), evs),
+           "zset_enumerate_async")
+
+
+def async_outcome(result) -> tuple[int, int]:
+    """(|Z(n)|, checksum) from the result words of a finished asynchronous
+    call; raises ZsetError when the call's outcome was an error."""
+    import torch
+    st, rows, csum = (int(x) for x in result[:3].view(torch.int64).tolist())
+    if st != OK:
+        raise ZsetError(st, "zset_enumerate_async", f"outcome {strerror(st)}, |Z(n)| = {rows}")
+    return rows & ((1 << 64) - 1), csum & ((1 << 64) - 1)
 
 
 def store_ceiling(buf, reps: int = 5, stream=None) -> float:

@@ -89,6 +89,27 @@ def test_enumerate_ex_option_checks():
     assert run() == zset.EINVAL              # out is NULL and rows are wanted
 
 
+def test_enumerate_async_checks_before_the_device():
+    lib = zset.load()
+    g = np.array([3, 5, 7], dtype=np.uint32)
+    gp = g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+    def run(result=None, **kw):
+        o = zset.Opts()
+        lib.zset_default_opts(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return lib.zset_enumerate_async(20, gp, 3, None, 0, ctypes.byref(o), result, None)
+
+    assert run(k=3) == zset.EINVAL
+    assert run(order=2) == zset.EINVAL
+    assert run(rows_per_tile=100) == zset.EINVAL
+    assert run() == zset.EINVAL                      # out is NULL and rows are wanted
+    assert run(count_only=1) == zset.EINVAL          # result is NULL
+    assert "result" in zset.last_error()
+    assert lib.zset_enumerate_async(20, None, 3, None, 0, None, None, None) == zset.EINVAL
+
+
 def test_memo_build_argument_checks():
     lib = zset.load()
     h = np.array([4, 9], dtype=np.uint32)
