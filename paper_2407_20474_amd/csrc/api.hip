@@ -64,7 +64,7 @@ namespace {
 // Per-device scratch, reused across calls.
 struct Ctx {
   int device = -1;
-  DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount, cnt2;
+  DevBuf table, off, nat, srcw, endc, leaf, tiles, misc, hcount, cnt2, rowp;
   uint64_t* pinned = nullptr;  // host readback area
   hipEvent_t ev[7] = {};
   // Side stream for a memo recurrence that runs beside the count table, with
@@ -883,13 +883,16 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
     J.off = off;
     J.stamps = misc + kMiscStamp;
     if (count_last_rows_enabled()) J.last = make_last_rows(gens, d);
+    if ((st = grow(c, c->rowp, size_t(Rn) * sizeof(uint32_t))) != ZSET_OK) return st;
+    J.rowp = reinterpret_cast<uint32_t*>(c->rowp.p);
+    LeafJob LJ = make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
+                               const_cast<uint32_t*>(P.leaf), Rn, P);
+    LJ.rowp = J.rowp;
     const bool timed = stats != nullptr;  // no timing events without stats
     if (timed) ZSET_HIP(hipEventRecord(c->ev[0], s));
     ZSET_HIP(launch_setup_fixed(J, s));
     if (timed) ZSET_HIP(hipEventRecord(c->ev[1], s));
-    ZSET_HIP(launch_plan_leaf(P, make_leaf_job(k, n, G, off, nat, T + uint64_t(U) * N, P.endc,
-                                               const_cast<uint32_t*>(P.leaf), Rn, P),
-                              s));
+    ZSET_HIP(launch_plan_leaf(P, LJ, s));
     if (timed) ZSET_HIP(hipEventRecord(c->ev[4], s));
     if (wev) ZSET_HIP(hipEventRecord(wev[0], s));
     ZSET_HIP(launch_write(P, count_only, align16, s));

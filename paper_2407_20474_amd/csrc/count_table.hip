@@ -158,7 +158,10 @@ __device__ void count_table_global(uint64_t* __restrict__ T, uint32_t N, const u
 // segment's reach takes several passes with a running carry.  Between rows the workgroup
 // synchronises on LDS only: the row's global copy-out need not complete before
 // the next row starts.  Row sums and maxima are reduced per wavefront as the
-// row is copied and combined once at the end.
+// row is copied and combined once at the end (skipped when neither is asked
+// for).  A caller that reads only rows 0..top_row, and row 0 only at its
+// entries x = n mod g_0 (mod g_0), passes top_row and row0_class: rows above
+// top_row stay in LDS, and row 0 is scanned and stored on that one class.
 constexpr uint32_t kCtLdsMax = 16384;
 constexpr uint32_t kColWalk = 64;
 constexpr uint32_t kColRun = 15;  // longest run per lane (odd)
@@ -197,15 +200,17 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
                                                 const uint32_t* gs, int d,
                                 uint64_t* __restrict__ sums, uint64_t* __restrict__ maxes,
                                 uint64_t* buf, uint32_t walk_max = kColWalk,
-                                const LastRows* lr = nullptr) {
+                                const LastRows* lr = nullptr, int top_row = kMaxD,
+                                bool row0_class = false) {
   constexpr int kWaves = kCtThreads / kWave;
   __shared__ uint64_t wsum[kMaxD][kWaves];
   __shared__ uint64_t wmax[kMaxD][kWaves];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wave = tid / kWave;
   const bool closed = lr && lr->on && d >= 2;
+  const bool stats = sums || maxes;
   for (uint32_t x = tid; x < N; x += kCtThreads) {
     if (!closed) buf[x] = (x == 0) ? 1 : 0;
-    T[size_t(d) * N + x] = (x == 0) ? 1 : 0;
+    if (d <= top_row) T[size_t(d) * N + x] = (x == 0) ? 1 : 0;
   }
   if (tid == 0 && sums) sums[d] = 1;
   if (tid == 0 && maxes) maxes[d] = 1;
@@ -215,10 +220,10 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
     // at row d-3 from row d-2 in buf.
     uint64_t acc = 0, mx = 0;
     for (uint32_t x = tid; x < N; x += kCtThreads) {
-      T[size_t(d - 1) * N + x] = last_row_divides(*lr, x);
+      if (d - 1 <= top_row) T[size_t(d - 1) * N + x] = last_row_divides(*lr, x);
       const uint64_t v = last_row_pair(*lr, x);
       buf[x] = v;
-      T[size_t(d - 2) * N + x] = v;
+      if (d - 2 <= top_row) T[size_t(d - 2) * N + x] = v;
       acc += v;
       mx = v > mx ? v : mx;
     }
@@ -240,10 +245,15 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
 
   for (int j = jtop; j >= 0; --j) {
     const uint32_t G = gs[j];
+    // Row 0 on one class only: the class of n, scanned as the single column
+    // of a one-column view (columns r0 + c, c < ncol).
+    const bool one = row0_class && j == 0 && G < N;
+    const uint32_t r0 = one ? (N - 1) % G : 0u, ncol = one ? 1u : G;
     if (G < N) {  // else no x - g_j >= 0: row j equals row j + 1
       const uint32_t L = (N + G - 1) / G;  // entries of the longest column
       if (L <= walk_max) {
-        for (uint32_t r = tid; r < G; r += kCtThreads) {
+        for (uint32_t rc = tid; rc < ncol; rc += kCtThreads) {
+          const uint32_t r = r0 + rc;
           uint64_t run = 0;
           for (uint32_t t0 = 0; t0 < L; t0 += 8) {
             uint64_t v[8];
@@ -274,9 +284,10 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
         const uint32_t passes = (L + span - 1) / span;
         const uint32_t per_wave = uint32_t(kWave) / seg;  // columns per wavefront pass
         const uint32_t sl = uint32_t(lane) % seg, sb = uint32_t(lane) - sl;
-        for (uint32_t r0 = uint32_t(wave) * per_wave; r0 < G; r0 += kWaves * per_wave) {
-          const uint32_t r = r0 + uint32_t(lane) / seg;
-          const bool col = r < G;
+        for (uint32_t c0 = uint32_t(wave) * per_wave; c0 < ncol; c0 += kWaves * per_wave) {
+          const uint32_t rc = c0 + uint32_t(lane) / seg;
+          const uint32_t r = r0 + rc;
+          const bool col = rc < ncol;
           uint64_t carry = 0;
           for (uint32_t ps = 0; ps < passes; ++ps) {
             const uint32_t t0 = ps * span + sl * E;
@@ -306,26 +317,32 @@ __device__ __forceinline__ void count_table_lds(uint64_t* __restrict__ T, uint32
       }
     }
     lds_barrier();
+    if (one) {  // row 0 on the class of n only (no statistics); the last row
+      for (uint32_t x = r0 + tid * G; x < N; x += kCtThreads * G) T[x] = buf[x];
+      continue;
+    }
     uint64_t acc = 0, mx = 0;
     for (uint32_t x = tid; x < N; x += kCtThreads) {
       const uint64_t v = buf[x];
-      T[size_t(j) * N + x] = v;
+      if (j <= top_row) T[size_t(j) * N + x] = v;
       acc = sat_add_u64(acc, v);
       mx = v > mx ? v : mx;
     }
+    if (stats) {
 #pragma unroll
-    for (int off = kWave / 2; off >= 1; off >>= 1) {
-      acc = sat_add_u64(acc, __shfl_xor(acc, off, kWave));
-      const uint64_t y = __shfl_xor(mx, off, kWave);
-      mx = y > mx ? y : mx;
-    }
-    if (lane == 0) {
-      wsum[j][wave] = acc;
-      wmax[j][wave] = mx;
+      for (int off = kWave / 2; off >= 1; off >>= 1) {
+        acc = sat_add_u64(acc, __shfl_xor(acc, off, kWave));
+        const uint64_t y = __shfl_xor(mx, off, kWave);
+        mx = y > mx ? y : mx;
+      }
+      if (lane == 0) {
+        wsum[j][wave] = acc;
+        wmax[j][wave] = mx;
+      }
     }
     lds_barrier();
   }
-  if (tid < d) {
+  if (stats && tid < d) {
     uint64_t s = 0, m = 0;
     for (int w = 0; w < kWaves; ++w) {
       s = sat_add_u64(s, wsum[tid][w]);
@@ -402,7 +419,11 @@ __global__ __launch_bounds__(kCtThreads) void k_setup_fixed(SetupJob J) {
     }
     if (tid < kMaxD) g[tid] = J.g.g[tid];
     __syncthreads();
-    count_table_lds(J.table, J.N, g, J.d, J.sums, J.sums + J.d + 2, buf, J.walk, &J.last);
+    // The rest of the call reads rows 1..U of the table, and row 0 only on
+    // the class of n (the slice plan's first coordinate): rows above U stay
+    // in LDS, row 0 is scanned on that class, and no row statistics are kept.
+    count_table_lds(J.table, J.N, g, J.d, nullptr, nullptr, buf, J.walk, &J.last, J.U,
+                    J.U >= 1);
     if (tid == 0) J.sums[J.d + 1] = buf[J.N - 1];
     __syncthreads();  // the table's global rows are visible to the workgroup
     const uint64_t* CU = J.table + uint64_t(J.U) * J.N;
@@ -421,7 +442,10 @@ __global__ __launch_bounds__(kCtThreads) void k_setup_fixed(SetupJob J) {
     const uint64_t h = J.h1;
     for (uint32_t i = tid; i <= top; i += kCtThreads) {
       J.off[i] = (uint64_t(i) + h - 1) / h;
-      if (i < J.R) J.nat[i] = i;
+      if (i < J.R) {
+        J.nat[i] = i;
+        J.rowp[i] = uint32_t(i * h);  // row i lists p = i h (i h < top)
+      }
     }
   } else {
     uint64_t carry = 0;
@@ -461,6 +485,7 @@ __global__ __launch_bounds__(kCtThreads) void k_setup_fixed(SetupJob J) {
           const uint32_t m1 = m0[q] + t * J.M.h2c;
           J.nat[(o + t) * 2] = m1;
           J.nat[(o + t) * 2 + 1] = (p - m1 * J.M.h1) / J.M.h2;
+          J.rowp[o + t] = p;
         }
       }
       carry += tot;
@@ -705,7 +730,7 @@ LastRows make_last_rows(const uint32_t* gens, int d) {
 
 hipError_t launch_setup_fixed(const SetupJob& J, hipStream_t s) {
   if (J.N == 0 || J.N > kCtLdsMax || (J.k != 1 && J.k != 2) || J.d < 2 || J.U < 0 ||
-      J.U >= J.d || J.nclass == 0 || J.nclass > J.N)
+      J.U >= J.d || J.nclass == 0 || J.nclass > J.N || !J.rowp || !J.nat || !J.off)
     return hipErrorInvalidValue;
   SetupJob j = J;
   if (j.walk == 0) {

@@ -136,6 +136,8 @@ struct LeafJob {
   uint32_t fshift[kMaxD + 1];
   int exact;                // 1: leaf_rows is the memo's row count; 0: a bound (partial
                             // memo), the rows being off[n + 1]
+  const uint32_t* rowp;     // non-NULL: rowp[t] = the element p of natural-order row t
+                            // (written with the memo), else found by bisection of off
 };
 
 // One memo row of the leaf-order layout: thread t takes natural-order row t;
@@ -149,12 +151,17 @@ __device__ inline void memo_leaf_row(const LeafJob& J, uint64_t t, int* __restri
   if (J.exact ? (t == 0 && rows != J.leaf_rows) : (t == 0 && rows > J.leaf_rows))
     set_error(err, kErrMemoTotal);
   if (t >= rows || t >= J.leaf_rows) return;
-  uint32_t lo = 0, hi = J.n;
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (J.off[mid] <= t) lo = mid; else hi = mid - 1;
+  uint32_t p;
+  if (J.rowp) {
+    p = J.rowp[t];
+  } else {
+    uint32_t lo = 0, hi = J.n;
+    while (lo < hi) {
+      const uint32_t mid = lo + (hi - lo + 1) / 2;
+      if (J.off[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    p = lo;
   }
-  const uint32_t p = lo;
   const int k = J.k;
   const uint32_t q = J.dG.div(p);
   const uint32_t rho = J.dG.mod(p, q);
@@ -229,14 +236,16 @@ __host__ __device__ inline uint32_t last_row_pair(const LastRows& L, uint32_t x)
 
 // The first launch of a call with the memo dimension fixed at 1 or 2 and a
 // count table that fits LDS (count_table.hip): workgroup 0 clears the two
-// status words, computes the count table (row sums, |Z(n)|, row maxima into
-// sums as launch_count_table does) and then the residue-class ends of row U;
+// status words, computes the rows of the count table that the slice plan, the
+// leaf layout and the write pass read (rows 1..U; row 0 only on the residue
+// class of n mod g_0 when U >= 1) and |Z(n)| into sums[d + 1], and then the
+// residue-class ends of row U;
 // workgroup 1 builds the memo in natural order (off: top + 1 offsets, nat: R
 // rows; k = 1 or 2 in closed form) and stamps its start and end on the
 // device's constant-rate clock into stamps[0..1].
 struct SetupJob {
   uint64_t* table;          // (d+1) x N
-  uint64_t* sums;           // 2d + 3 words
+  uint64_t* sums;           // 2d + 3 words; [d + 1] receives |Z(n)|
   uint64_t* status;         // 2 words cleared first
   Gens g;
   uint32_t N;               // n + 1 (<= count_table_lds_max())
@@ -254,6 +263,7 @@ struct SetupJob {
   uint64_t* off;
   uint64_t* stamps;
   LastRows last;            // the table's rows d-1 and d-2 in closed form (when on)
+  uint32_t* rowp;           // R words: the element p of each natural-order memo row
 };
 
 struct ClassJob {
