@@ -733,9 +733,10 @@ def main():
     # Queued steps (zset_enumerate_async): each call enqueues the whole path
     # (count table and memo, slice plan and memo layout, write pass, outcome
     # word) and returns; the host waits once after the last one.  Only the
-    # three-launch form queues (k = 1 or 2, default slices); any other call
-    # runs to completion inside zset_enumerate_async.
-    queued = (not args.sync_steps and args.rows_per_tile == 0 and k in (1, 2))
+    # three-launch form queues (k = 1 or 2, default slices, n + 1 <= 16384);
+    # other workloads time synchronous calls.
+    queued = (not args.sync_steps and args.rows_per_tile == 0 and k in (1, 2)
+              and n + 1 <= 16384)
     results = torch.zeros((max(args.steps, args.warmup, 1), 4), dtype=torch.int64).pin_memory()
     wev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]

@@ -217,7 +217,9 @@ zset_status zset_enumerate_ex(uint64_t n, const uint32_t *gens, int d, uint32_t 
  *                 not be reused before the stream has passed this call.
  *   write_events  NULL, or two hipEvent_t that the call records on
  *                 opts->stream right before and right after its write pass
- *                 (for timing the pass of an asynchronous call)
+ *                 (for timing the pass of an asynchronous call) when k is
+ *                 fixed at 1 or 2 with the default slice options; other
+ *                 calls leave them unrecorded
  * Returns ZSET_OK once the work is enqueued.  Errors found before any launch
  * are returned (EINVAL: as zset_enumerate_ex, `result` not pinned host memory,
  * a NULL event; ENOMEM; EDEVICE for a failed launch); a call that ran to

@@ -948,7 +948,9 @@ zset_status enumerate_fixed_k(Ctx* c, uint64_t n, const uint32_t* gens, int d, u
                                             const_cast<uint32_t*>(P.leaf), Rn, P),
                               err, s));
     ZSET_HIP(hipEventRecord(c->ev[4], s));
+    if (wev) ZSET_HIP(hipEventRecord(wev[0], s));
     ZSET_HIP(launch_write(P, count_only, align16, s));
+    if (wev) ZSET_HIP(hipEventRecord(wev[1], s));
     ZSET_HIP(hipEventRecord(c->ev[5], s));
     // Status, checksum and |Z(n)| in one readback.
     static_assert(kMiscErr == 0 && kMiscSum == 1 && kMiscRowSums == 2, "misc layout");
